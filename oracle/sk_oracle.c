@@ -1,0 +1,310 @@
+/*
+ * CPU ORACLE for the multi-receiver spectral-kurtosis estimator.
+ *
+ * TEST INFRASTRUCTURE ONLY. The test suite, the smoke check and the bench's
+ * CPU-baseline leg are the only callers. The GPU library never calls, links
+ * or includes this file, and this file includes nothing of the GPU library.
+ *
+ * Plain loops, int64 for integer sums, FP64 for everything that is not an
+ * integer, summation in input order i = 0..N-1. No blocking, no fusion.
+ *
+ * Paper: Taylor et al., "Spectral Kurtosis Based RFI Mitigation for CHIME"
+ * (arXiv:1808.10365).
+ *   Sec. 2.1, Eq. (1)-(2)        single-receiver S1, S2 and SK
+ *   Sec. 2.2.1 Eq. singlesums    per-receiver (S1)_i, (S2)_i over n samples
+ *   Sec. 2.2.1 Eq. originalSK    per-receiver SK_i
+ *   Sec. 2.2.1 Eq. discreteMean  mean power mu_i = (S1)_i / n
+ *   Sec. 2.2.1 Eq. normedSum1/2  normalised array cumulants
+ *   Sec. 2.2.1 Eq. avgSK         multi-receiver estimator, effective count nN
+ *   Sec. 2.2.1 Eq. final         rescaled estimator = Avg(SK_i)
+ *   Sec. 3.2                     detection significance, symmetric a-sigma cut
+ *   App. B                       4+4-bit data bounded to [-7, 7]
+ *
+ * Names: N inputs (receivers), F channels, T samples per channel, M samples
+ * per input per estimate (the paper's n), B = T / M blocks, K = N_eff * M the
+ * effective sample count (the paper's nN), L the normaliser window in blocks.
+ *
+ * Readings where the paper is silent (each is listed with its reason in the
+ * design notes):
+ *   - Byte encoding: high nibble = Re + 8, low nibble = Im + 8. Code 0 decodes
+ *     literally to -8, so one sample's power is at most 128.
+ *   - Normaliser: mu_i is proportional to P_i[b], the sum of S1_i over the L
+ *     blocks ending at and including b (blocks before the stream's start are
+ *     absent, so a warm-up window holds fewer blocks). L = 1 is exactly
+ *     Eq. discreteMean; L = 0 means no normalisation (unit weights). The
+ *     factor count*M that turns P_i into a mean is the same for every input of
+ *     a (channel, block) and cancels in the estimator, so weights are 1/P_i.
+ *   - Inputs with P_i = 0, or masked out, are dropped and not counted in N_eff.
+ *   - V is invalid (NaN, flag bit 2) when N_eff * M < 2 or A = 0.
+ *   - Expectation: E = E0 + delta, where E0 = 1, except the unrescaled
+ *     estimator with L = 1, whose mean is (K+1)(M-1) / ((K-1)(M+1)) by
+ *     Eq. avgSK (last line) with mean(SK_i) = 1. delta is the caller's
+ *     digitisation offset (App. B adds it to the threshold).
+ *   - sigma = sqrt(4 / K) (Eq. final variance) unless the caller overrides it.
+ *   - Flags: bit 0 when V < E - k sigma, bit 1 when V > E + k sigma (strict).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+enum { ORC_EST_HAT = 0, ORC_EST_TILDE = 1 };
+enum { ORC_FLAG_LOW = 1, ORC_FLAG_HIGH = 2, ORC_FLAG_INVALID = 4 };
+
+/* Power of one offset-encoded complex sample: re(x)^2 + im(x)^2
+ * (Sec. 2.2.3, "Calculating Power"). */
+int orc_power(uint8_t byte) {
+  int re = (int)(byte >> 4) - 8;
+  int im = (int)(byte & 15) - 8;
+  return re * re + im * im;
+}
+
+/* Eq. singlesums: (S1)_i = sum_j |x_j|^2, (S2)_i = sum_j |x_j|^4 over the M
+ * samples of block b, for every (channel f, block b, input i).
+ * x is [T][F][N]; S1, S2 are [F][B][N]. */
+void orc_block_sums(const uint8_t* x, int64_t N, int64_t F, int64_t T, int64_t M,
+                    int64_t* S1, int64_t* S2) {
+  int64_t B = T / M;
+  memset(S1, 0, sizeof(int64_t) * (size_t)(F * B * N));
+  memset(S2, 0, sizeof(int64_t) * (size_t)(F * B * N));
+  for (int64_t f = 0; f < F; ++f)
+    for (int64_t b = 0; b < B; ++b)
+      for (int64_t j = 0; j < M; ++j) {
+        int64_t t = b * M + j;
+        for (int64_t i = 0; i < N; ++i) {
+          int64_t p = orc_power(x[(t * F + f) * N + i]);
+          S1[(f * B + b) * N + i] += p;
+          S2[(f * B + b) * N + i] += p * p;
+        }
+      }
+}
+
+/* Same sums for real-valued power p[T][F][N] (FP64), for statistics tests on
+ * continuous chi-squared power. */
+void orc_block_sums_f64(const double* p, int64_t N, int64_t F, int64_t T, int64_t M,
+                        double* S1, double* S2) {
+  int64_t B = T / M;
+  for (int64_t q = 0; q < F * B * N; ++q) S1[q] = S2[q] = 0.0;
+  for (int64_t f = 0; f < F; ++f)
+    for (int64_t b = 0; b < B; ++b)
+      for (int64_t j = 0; j < M; ++j)
+        for (int64_t i = 0; i < N; ++i) {
+          double v = p[((b * M + j) * F + f) * N + i];
+          S1[(f * B + b) * N + i] += v;
+          S2[(f * B + b) * N + i] += v * v;
+        }
+}
+
+/* Normaliser window: P[f][b][i] = sum of S1_i over blocks b-L+1 .. b.
+ * Blocks before this call come from hist[f][H + b'][i] for -H <= b' < 0
+ * (oldest first); blocks before that do not exist. L = 0 gives P = S1. */
+void orc_window(const int64_t* S1, const int64_t* hist, int64_t H, int64_t N, int64_t F,
+                int64_t B, int64_t L, int64_t* P) {
+  for (int64_t f = 0; f < F; ++f)
+    for (int64_t b = 0; b < B; ++b)
+      for (int64_t i = 0; i < N; ++i) {
+        if (L == 0) {
+          P[(f * B + b) * N + i] = S1[(f * B + b) * N + i];
+          continue;
+        }
+        int64_t s = 0;
+        for (int64_t bb = b - L + 1; bb <= b; ++bb) {
+          if (bb >= 0)
+            s += S1[(f * B + bb) * N + i];
+          else if (bb >= -H)
+            s += hist[(f * H + (H + bb)) * N + i];
+        }
+        P[(f * B + b) * N + i] = s;
+      }
+}
+
+void orc_window_f64(const double* S1, int64_t N, int64_t F, int64_t B, int64_t L, double* P) {
+  for (int64_t f = 0; f < F; ++f)
+    for (int64_t b = 0; b < B; ++b)
+      for (int64_t i = 0; i < N; ++i) {
+        if (L == 0) {
+          P[(f * B + b) * N + i] = S1[(f * B + b) * N + i];
+          continue;
+        }
+        double s = 0;
+        for (int64_t bb = b - L + 1; bb <= b; ++bb)
+          if (bb >= 0) s += S1[(f * B + bb) * N + i];
+        P[(f * B + b) * N + i] = s;
+      }
+}
+
+/* Expectation and spread used by the symmetric cut (Sec. 3.2). */
+static void orc_expectation(int64_t K, int64_t M, int64_t L, int est, double delta,
+                            double sigma_override, double* E, double* sigma) {
+  double Kd = (double)K, Md = (double)M;
+  double e0 = 1.0;
+  if (est == ORC_EST_HAT && L == 1) e0 = ((Kd + 1.0) * (Md - 1.0)) / ((Kd - 1.0) * (Md + 1.0));
+  *E = e0 + delta;
+  *sigma = sigma_override > 0.0 ? sigma_override : sqrt(4.0 / Kd);
+}
+
+/* Symmetric a-sigma cut on one value (Sec. 3.2). */
+uint8_t orc_flag_one(double V, int64_t n_eff, int64_t M, int64_t L, int est, double k,
+                     double delta, double sigma_override) {
+  int64_t K = n_eff * M;
+  if (K < 2 || isnan(V)) return ORC_FLAG_INVALID;
+  double E, s;
+  orc_expectation(K, M, L, est, delta, sigma_override, &E, &s);
+  double lo = E - k * s, hi = E + k * s;
+  uint8_t fl = 0;
+  if (V < lo) fl |= ORC_FLAG_LOW;
+  if (V > hi) fl |= ORC_FLAG_HIGH;
+  return fl;
+}
+
+void orc_flags(const double* V, const int32_t* n_eff, int64_t n, int64_t M, int64_t L, int est,
+               double k, double delta, double sigma_override, uint8_t* flags) {
+  for (int64_t j = 0; j < n; ++j)
+    flags[j] = orc_flag_one(V[j], n_eff[j], M, L, est, k, delta, sigma_override);
+}
+
+/* Array combine, estimator and flags for every (f, b).
+ * Eq. normedSum1: A = sum_i S1_i / P_i;  Eq. normedSum2: Bq = sum_i S2_i / P_i^2
+ * (both up to the common factors M*count and (M*count)^2, which cancel).
+ * Eq. avgSK line 1: V = (K+1)/(K-1) * (K * Bq / A^2 - 1), K = N_eff * M.
+ * Eq. final line 2 (L = 1 only): V = (M+1)/(M-1) * (M * Bq / N_eff - 1).
+ * L = 0: Eq. (2) over all K samples: V = (K+1)/(K-1) * (K R2 - R1^2) / R1^2,
+ * with the numerator formed exactly in 128-bit integers.
+ * R1, R2 are the raw integer sums over the included inputs. */
+void orc_combine(const int64_t* S1, const int64_t* S2, const int64_t* P, const uint8_t* mask,
+                 int64_t N, int64_t F, int64_t B, int64_t M, int64_t L, int est, double k,
+                 double delta, double sigma_override, double* A_out, double* Bq_out,
+                 int64_t* R1_out, int64_t* R2_out, int32_t* n_eff_out, double* V_out,
+                 uint8_t* flags_out) {
+  for (int64_t f = 0; f < F; ++f)
+    for (int64_t b = 0; b < B; ++b) {
+      double A = 0.0, Bq = 0.0;
+      int64_t R1 = 0, R2 = 0, n = 0;
+      for (int64_t i = 0; i < N; ++i) {
+        if (mask && mask[f * N + i] == 0) continue;
+        int64_t idx = (f * B + b) * N + i;
+        int64_t p = P[idx];
+        if (p <= 0) continue;
+        n += 1;
+        R1 += S1[idx];
+        R2 += S2[idx];
+        if (L >= 1) {
+          double pd = (double)p;
+          A += (double)S1[idx] / pd;
+          Bq += (double)S2[idx] / (pd * pd);
+        }
+      }
+      int64_t K = n * M;
+      double Kd = (double)K, Md = (double)M;
+      double V;
+      int invalid = (K < 2);
+      if (L == 0) {
+        A = (double)R1;
+        Bq = (double)R2;
+        invalid = invalid || (R1 == 0);
+        if (!invalid) {
+          __int128 num = (__int128)K * (__int128)R2 - (__int128)R1 * (__int128)R1;
+          __int128 den = (__int128)R1 * (__int128)R1;
+          V = (Kd + 1.0) / (Kd - 1.0) * ((double)num / (double)den);
+        }
+      } else {
+        invalid = invalid || (A == 0.0);
+        if (!invalid) {
+          if (est == ORC_EST_TILDE)
+            V = (Md + 1.0) / (Md - 1.0) * (Md * Bq / (double)n - 1.0);
+          else
+            V = (Kd + 1.0) / (Kd - 1.0) * (Kd * Bq / (A * A) - 1.0);
+        }
+      }
+      if (invalid) V = NAN;
+      int64_t o = f * B + b;
+      if (A_out) A_out[o] = A;
+      if (Bq_out) Bq_out[o] = Bq;
+      if (R1_out) R1_out[o] = R1;
+      if (R2_out) R2_out[o] = R2;
+      if (n_eff_out) n_eff_out[o] = (int32_t)n;
+      if (V_out) V_out[o] = V;
+      if (flags_out) flags_out[o] = orc_flag_one(V, n, M, L, est, k, delta, sigma_override);
+    }
+}
+
+/* The same combine on real-valued sums (continuous chi-squared power). */
+void orc_combine_f64(const double* S1, const double* S2, const double* P, int64_t N, int64_t F,
+                     int64_t B, int64_t M, int64_t L, int est, double* V_out) {
+  for (int64_t f = 0; f < F; ++f)
+    for (int64_t b = 0; b < B; ++b) {
+      double A = 0.0, Bq = 0.0, R1 = 0.0, R2 = 0.0;
+      int64_t n = 0;
+      for (int64_t i = 0; i < N; ++i) {
+        int64_t idx = (f * B + b) * N + i;
+        double p = P[idx];
+        if (!(p > 0.0)) continue;
+        n += 1;
+        R1 += S1[idx];
+        R2 += S2[idx];
+        A += S1[idx] / p;
+        Bq += S2[idx] / (p * p);
+      }
+      double Kd = (double)(n * M), Md = (double)M, V;
+      if (n * M < 2) V = NAN;
+      else if (L == 0) V = (Kd + 1.0) / (Kd - 1.0) * (Kd * R2 / (R1 * R1) - 1.0);
+      else if (est == ORC_EST_TILDE) V = (Md + 1.0) / (Md - 1.0) * (Md * Bq / (double)n - 1.0);
+      else V = (Kd + 1.0) / (Kd - 1.0) * (Kd * Bq / (A * A) - 1.0);
+      V_out[f * B + b] = V;
+    }
+}
+
+/* Eq. originalSK: per-receiver estimate SK_i = (M+1)/(M-1) (M S2_i / S1_i^2 - 1).
+ * NaN where S1_i = 0. */
+void orc_sk_per_input(const int64_t* S1, const int64_t* S2, int64_t count, int64_t M, double* out) {
+  double Md = (double)M;
+  for (int64_t j = 0; j < count; ++j) {
+    if (S1[j] == 0) { out[j] = NAN; continue; }
+    double s1 = (double)S1[j];
+    out[j] = (Md + 1.0) / (Md - 1.0) * (Md * (double)S2[j] / (s1 * s1) - 1.0);
+  }
+}
+
+/* Whole path on one call: decode, sums, window, combine, flags.
+ * hist (may be NULL when H = 0) is [F][H][N] S1 of the blocks just before
+ * this call, oldest first. Outputs are [F][B][N] (S1, S2, P) and [F][B]. */
+int orc_sk(const uint8_t* x, const uint8_t* mask, int64_t N, int64_t F, int64_t T, int64_t M,
+           int64_t L, int est, double k, double delta, double sigma_override,
+           const int64_t* hist, int64_t H, int64_t* S1, int64_t* S2, int64_t* P,
+           int64_t* R1, int64_t* R2, int32_t* n_eff, double* V, uint8_t* flags) {
+  if (M < 2 || T % M != 0 || N < 1 || F < 1 || L < 0) return -1;
+  if (est == ORC_EST_TILDE && L != 1) return -1;
+  int64_t B = T / M;
+  orc_block_sums(x, N, F, T, M, S1, S2);
+  orc_window(S1, hist, H, N, F, B, L, P);
+  orc_combine(S1, S2, P, mask, N, F, B, M, L, est, k, delta, sigma_override, NULL, NULL, R1, R2,
+              n_eff, V, flags);
+  return 0;
+}
+
+/* ------------------------------------------------------------------ App. B
+ * Digitised Gaussian model. A component is round(sigma z) clipped to
+ * [-clip, clip]: Pr(v) = Phi((v+1/2)/sigma) - Phi((v-1/2)/sigma) for |v| <
+ * clip, with both tails lumped into +-clip. The complex sample has
+ * independent components, so p = re^2 + im^2 has the 2-D lattice PMF.
+ * Output: m[0] = E[p], m[1] = E[p^2], m[2] = E[p^3], m[3] = E[p^4]. */
+static double orc_phi(double x) { return 0.5 * erfc(-x / sqrt(2.0)); }
+
+void orc_quantised_power_moments(double sigma, int clip, double* m) {
+  double pr[64];
+  for (int v = -clip; v <= clip; ++v) {
+    double lo = (v == -clip) ? 0.0 : orc_phi(((double)v - 0.5) / sigma);
+    double hi = (v == clip) ? 1.0 : orc_phi(((double)v + 0.5) / sigma);
+    pr[v + clip] = hi - lo;
+  }
+  m[0] = m[1] = m[2] = m[3] = 0.0;
+  for (int a = -clip; a <= clip; ++a)
+    for (int c = -clip; c <= clip; ++c) {
+      double w = pr[a + clip] * pr[c + clip];
+      double p = (double)(a * a + c * c);
+      m[0] += w * p;
+      m[1] += w * p * p;
+      m[2] += w * p * p * p;
+      m[3] += w * p * p * p * p;
+    }
+}
