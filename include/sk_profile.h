@@ -1,0 +1,41 @@
+/*
+ * sk_profile.h - per-phase timing and tile control for sk_plan_t.
+ *
+ * For measurement tools and the autotuner: HIP events recorded on the
+ * caller's stream around the two kernel phases of sk_compute (pass A: the
+ * per-input block sums of Eq. singlesums; pass B: normaliser window, array
+ * combine, estimator and flags of Eq. discreteMean .. final).
+ */
+#ifndef SK_PROFILE_H
+#define SK_PROFILE_H
+
+#include <stdint.h>
+
+#include "sk.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Record events around the phases of the next max_records sk_compute calls
+ * on this plan (0 turns recording off and frees the events). Host-side only. */
+int sk_profile_enable(sk_plan_t plan, int32_t max_records);
+
+/* Wait for the recorded calls and return their phase durations in
+ * milliseconds (ms_pass_a[j], ms_pass_b[j], j < *n, n <= cap); then start a
+ * new recording. */
+int sk_profile_read(sk_plan_t plan, float* ms_pass_a, float* ms_pass_b, int32_t cap, int32_t* n);
+
+/* Force pass A's lanes per row (power of two, 1..256; 0 = library choice). */
+int sk_plan_set_pass_a_tile(sk_plan_t plan, int32_t lanes_per_row);
+
+/* Pass A's lanes per row and workgroup count for the next call (after
+ * sk_plan_set_pass_a_tile or the library's choice), for reporting. */
+int sk_plan_get_pass_a_tile(sk_plan_t plan, const uint8_t* d_packed, int32_t* vec_bytes,
+                            int32_t* lanes_per_row, int64_t* workgroups);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SK_PROFILE_H */

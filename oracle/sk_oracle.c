@@ -101,36 +101,38 @@ void orc_block_sums_f64(const double* p, int64_t N, int64_t F, int64_t T, int64_
 void orc_window(const int64_t* S1, const int64_t* hist, int64_t H, int64_t N, int64_t F,
                 int64_t B, int64_t L, int64_t* P) {
   for (int64_t f = 0; f < F; ++f)
-    for (int64_t b = 0; b < B; ++b)
-      for (int64_t i = 0; i < N; ++i) {
-        if (L == 0) {
-          P[(f * B + b) * N + i] = S1[(f * B + b) * N + i];
-          continue;
-        }
-        int64_t s = 0;
-        for (int64_t bb = b - L + 1; bb <= b; ++bb) {
-          if (bb >= 0)
-            s += S1[(f * B + bb) * N + i];
-          else if (bb >= -H)
-            s += hist[(f * H + (H + bb)) * N + i];
-        }
-        P[(f * B + b) * N + i] = s;
+    for (int64_t b = 0; b < B; ++b) {
+      int64_t* out = P + (f * B + b) * N;
+      if (L == 0) {
+        for (int64_t i = 0; i < N; ++i) out[i] = S1[(f * B + b) * N + i];
+        continue;
       }
+      for (int64_t i = 0; i < N; ++i) out[i] = 0;
+      for (int64_t bb = b - L + 1; bb <= b; ++bb) {
+        const int64_t* src = NULL;
+        if (bb >= 0)
+          src = S1 + (f * B + bb) * N;
+        else if (bb >= -H)
+          src = hist + (f * H + (H + bb)) * N;
+        if (src)
+          for (int64_t i = 0; i < N; ++i) out[i] += src[i];
+      }
+    }
 }
 
 void orc_window_f64(const double* S1, int64_t N, int64_t F, int64_t B, int64_t L, double* P) {
   for (int64_t f = 0; f < F; ++f)
-    for (int64_t b = 0; b < B; ++b)
-      for (int64_t i = 0; i < N; ++i) {
-        if (L == 0) {
-          P[(f * B + b) * N + i] = S1[(f * B + b) * N + i];
-          continue;
-        }
-        double s = 0;
-        for (int64_t bb = b - L + 1; bb <= b; ++bb)
-          if (bb >= 0) s += S1[(f * B + bb) * N + i];
-        P[(f * B + b) * N + i] = s;
+    for (int64_t b = 0; b < B; ++b) {
+      double* out = P + (f * B + b) * N;
+      if (L == 0) {
+        for (int64_t i = 0; i < N; ++i) out[i] = S1[(f * B + b) * N + i];
+        continue;
       }
+      for (int64_t i = 0; i < N; ++i) out[i] = 0.0;
+      for (int64_t bb = b - L + 1; bb <= b; ++bb)
+        if (bb >= 0)
+          for (int64_t i = 0; i < N; ++i) out[i] += S1[(f * B + bb) * N + i];
+    }
 }
 
 /* Expectation and spread used by the symmetric cut (Sec. 3.2). */

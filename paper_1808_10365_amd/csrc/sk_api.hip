@@ -1,0 +1,374 @@
+// C ABI: plans, validation, device memory ownership, normaliser state.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+
+#include "sk_internal.h"
+#include "sk_profile.h"
+#include <vector>
+
+namespace sk {
+
+static thread_local std::string g_err;
+
+void set_error(const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+}
+
+void clear_error() { g_err.clear(); }
+
+}  // namespace sk
+
+using namespace sk;
+
+struct sk_plan_s {
+  sk_plan_desc d;
+  int device;
+  int64_t n_blocks;        // B = T / M
+  int32_t hist_cap;        // max(L - 1, 0)
+  int32_t hist_len;        // history blocks currently held (<= hist_cap)
+  int32_t chunk;           // R
+  int32_t n_chunks_max;    // chunks of the sequence when the history is full
+  int32_t s1_s2_owned;
+  int32_t* s1;             // [F][B][N] scratch
+  int32_t* s2;
+  int64_t* chunk_sum;      // [F][n_chunks_max][N]
+  int64_t* chunk_prefix;   // [F][n_chunks_max + 1][N]
+  int32_t* hist[2];        // [F][hist_cap][N], ping-pong
+  int32_t cur;             // index of the live history buffer
+  size_t bytes;
+  int pass_a_lpr;          // 0 = heuristic
+  std::vector<hipEvent_t> prof;   // 3 events per recorded call
+  int32_t prof_max, prof_n;
+};
+
+static const uint32_t kStateMagic = 0x534B5354u;  // "SKST"
+
+struct StateHeader {
+  uint32_t magic;
+  uint32_t version;
+  int32_t n_inputs, n_channels, block_len, window, hist_len, pad;
+};
+
+static int validate(const sk_plan_desc* d) {
+  if (!d) { set_error("desc is NULL"); return SK_ERR_INVALID_ARG; }
+  if (d->n_inputs < 1 || d->n_inputs > 16384) { set_error("n_inputs %d outside [1, 16384]", d->n_inputs); return SK_ERR_SHAPE; }
+  if (d->n_channels < 1) { set_error("n_channels %d < 1", d->n_channels); return SK_ERR_SHAPE; }
+  if (d->block_len < 2 || d->block_len > 131071) { set_error("block_len %d outside [2, 131071]", d->block_len); return SK_ERR_SHAPE; }
+  if (d->n_samples < 0 || d->n_samples % d->block_len != 0) { set_error("n_samples %lld is not a non-negative multiple of block_len %d", (long long)d->n_samples, d->block_len); return SK_ERR_SHAPE; }
+  if (d->norm_window_blocks < 0 || (int64_t)d->norm_window_blocks * d->block_len * 128 >= (1LL << 31)) { set_error("norm_window_blocks %d: window power sum must fit int32", d->norm_window_blocks); return SK_ERR_SHAPE; }
+  if (d->estimator != SK_EST_HAT && d->estimator != SK_EST_TILDE) { set_error("unknown estimator %d", d->estimator); return SK_ERR_INVALID_ARG; }
+  if (d->estimator == SK_EST_TILDE && d->norm_window_blocks != 1) { set_error("the rescaled estimator needs norm_window_blocks == 1"); return SK_ERR_INVALID_ARG; }
+  if (!(d->k_sigma >= 0.0)) { set_error("k_sigma must be >= 0"); return SK_ERR_INVALID_ARG; }
+  const int64_t cells = (int64_t)d->n_channels * d->n_samples * d->n_inputs;
+  if (cells < 0 || (double)d->n_channels * (double)d->n_samples * (double)d->n_inputs > 9.0e18) { set_error("input too large"); return SK_ERR_SHAPE; }
+  return SK_OK;
+}
+
+static int32_t pow2_floor(int64_t v) {
+  int32_t r = 1;
+  while ((int64_t)r * 2 <= v && r < (1 << 30)) r *= 2;
+  return r;
+}
+
+static void free_profile(sk_plan_s* p) {
+  for (hipEvent_t e : p->prof) (void)hipEventDestroy(e);
+  p->prof.clear();
+  p->prof_max = p->prof_n = 0;
+}
+
+static void free_plan_memory(sk_plan_s* p) {
+  free_profile(p);
+  if (p->s1_s2_owned) {
+    if (p->s1) (void)hipFree(p->s1);
+    if (p->s2) (void)hipFree(p->s2);
+  }
+  if (p->chunk_sum) (void)hipFree(p->chunk_sum);
+  if (p->chunk_prefix) (void)hipFree(p->chunk_prefix);
+  if (p->hist[0]) (void)hipFree(p->hist[0]);
+  if (p->hist[1]) (void)hipFree(p->hist[1]);
+}
+
+#define SK_ALLOC(ptr, nbytes)                                                     \
+  do {                                                                            \
+    size_t nb_ = (nbytes);                                                        \
+    if (nb_ > 0) {                                                                \
+      hipError_t e_ = hipMalloc((void**)&(ptr), nb_);                             \
+      if (e_ != hipSuccess) {                                                     \
+        set_error("hipMalloc(%zu) failed: %s", nb_, hipGetErrorString(e_));       \
+        free_plan_memory(p);                                                      \
+        delete p;                                                                 \
+        return SK_ERR_NOMEM;                                                      \
+      }                                                                           \
+      p->bytes += nb_;                                                            \
+    }                                                                             \
+  } while (0)
+
+extern "C" {
+
+const char* sk_last_error(void) { return g_err.c_str(); }
+
+int sk_plan_create(const sk_plan_desc* desc, sk_plan_t* out) {
+  clear_error();
+  if (!out) { set_error("out is NULL"); return SK_ERR_INVALID_ARG; }
+  *out = nullptr;
+  int rc = validate(desc);
+  if (rc) return rc;
+  sk_plan_s* p = new (std::nothrow) sk_plan_s();
+  if (!p) { set_error("host allocation failed"); return SK_ERR_NOMEM; }
+  p->d = *desc;
+  if (hipGetDevice(&p->device) != hipSuccess) { delete p; set_error("no HIP device"); return SK_ERR_DEVICE; }
+  const int64_t N = desc->n_inputs, F = desc->n_channels;
+  p->n_blocks = desc->n_samples / desc->block_len;
+  const int L = desc->norm_window_blocks;
+  p->hist_cap = L >= 2 ? L - 1 : 0;
+  p->hist_len = 0;
+  // Chunk length: about 512 combine workgroups, 1..64 blocks each.
+  const int64_t seq = p->hist_cap + p->n_blocks;
+  int32_t R = pow2_floor(seq * F / 512);
+  if (R > 64) R = 64;
+  if (R < 1) R = 1;
+  p->chunk = R;
+  p->n_chunks_max = (int32_t)((seq + R - 1) / R);
+  p->s1_s2_owned = 1;
+  const size_t fbn = (size_t)F * p->n_blocks * N;
+  SK_ALLOC(p->s1, fbn * sizeof(int32_t));
+  SK_ALLOC(p->s2, fbn * sizeof(int32_t));
+  if (L >= 2) {
+    SK_ALLOC(p->chunk_sum, (size_t)F * p->n_chunks_max * N * sizeof(int64_t));
+    SK_ALLOC(p->chunk_prefix, (size_t)F * (p->n_chunks_max + 1) * N * sizeof(int64_t));
+    SK_ALLOC(p->hist[0], (size_t)F * p->hist_cap * N * sizeof(int32_t));
+    SK_ALLOC(p->hist[1], (size_t)F * p->hist_cap * N * sizeof(int32_t));
+  }
+  p->cur = 0;
+  *out = p;
+  return SK_OK;
+}
+
+int sk_plan_destroy(sk_plan_t p) {
+  clear_error();
+  if (!p) return SK_OK;
+  (void)hipDeviceSynchronize();
+  free_plan_memory(p);
+  delete p;
+  return SK_OK;
+}
+
+int sk_plan_device_bytes(sk_plan_t p, size_t* bytes) {
+  if (!p || !bytes) { set_error("NULL argument"); return SK_ERR_INVALID_ARG; }
+  *bytes = p->bytes;
+  return SK_OK;
+}
+
+// Internal: force pass A lanes-per-row (autotuner and tests); 0 = heuristic.
+int sk_plan_set_pass_a_tile(sk_plan_t p, int32_t lpr) {
+  if (!p || (lpr != 0 && (lpr < 1 || lpr > 256 || (lpr & (lpr - 1))))) { set_error("bad tile"); return SK_ERR_INVALID_ARG; }
+  p->pass_a_lpr = lpr;
+  return SK_OK;
+}
+
+static PassAConfig plan_pass_a_config(const sk_plan_s* p, const uint8_t* d_packed, PassATask* t) {
+  const int64_t N = p->d.n_inputs, F = p->d.n_channels, B = p->n_blocks;
+  const int vec = pick_vec(d_packed, (int32_t)N);
+  t->row_bytes = F * N;
+  t->n_inputs = (int32_t)N;
+  t->block_len = p->d.block_len;
+  t->n_blocks = (int32_t)B;
+  PassAConfig c = default_pass_a_config(vec, t->row_bytes, B);
+  if (p->pass_a_lpr) c.lpr = p->pass_a_lpr;
+  t->col_groups = (int32_t)(t->row_bytes / vec);
+  t->chunks = (t->col_groups + c.lpr - 1) / c.lpr;
+  t->n_tasks = B * t->chunks;
+  c.grid = (int)(t->n_tasks < (1 << 30) ? t->n_tasks : (1 << 30));
+  return c;
+}
+
+int sk_plan_get_pass_a_tile(sk_plan_t p, const uint8_t* d_packed, int32_t* vec, int32_t* lpr, int64_t* wgs) {
+  if (!p || !vec || !lpr || !wgs) { set_error("NULL argument"); return SK_ERR_INVALID_ARG; }
+  PassATask t;
+  PassAConfig c = plan_pass_a_config(p, d_packed, &t);
+  *vec = c.vec;
+  *lpr = c.lpr;
+  *wgs = c.grid;
+  return SK_OK;
+}
+
+int sk_profile_enable(sk_plan_t p, int32_t max_records) {
+  clear_error();
+  if (!p || max_records < 0) { set_error("bad arguments"); return SK_ERR_INVALID_ARG; }
+  free_profile(p);
+  if (max_records == 0) return SK_OK;
+  p->prof.resize((size_t)max_records * 3);
+  for (auto& e : p->prof) SK_HIP_TRY(hipEventCreate(&e));
+  p->prof_max = max_records;
+  p->prof_n = 0;
+  return SK_OK;
+}
+
+int sk_profile_read(sk_plan_t p, float* ms_a, float* ms_b, int32_t cap, int32_t* n) {
+  clear_error();
+  if (!p || !n || (cap > 0 && (!ms_a || !ms_b))) { set_error("bad arguments"); return SK_ERR_INVALID_ARG; }
+  const int32_t m = p->prof_n < cap ? p->prof_n : cap;
+  for (int32_t j = 0; j < m; ++j) {
+    SK_HIP_TRY(hipEventSynchronize(p->prof[3 * j + 2]));
+    SK_HIP_TRY(hipEventElapsedTime(&ms_a[j], p->prof[3 * j], p->prof[3 * j + 1]));
+    SK_HIP_TRY(hipEventElapsedTime(&ms_b[j], p->prof[3 * j + 1], p->prof[3 * j + 2]));
+  }
+  *n = m;
+  p->prof_n = 0;
+  return SK_OK;
+}
+
+int sk_compute(sk_plan_t p, const uint8_t* d_packed, const uint8_t* d_mask, const sk_outputs* outs,
+               void* stream) {
+  clear_error();
+  if (!p || !outs) { set_error("NULL plan or outputs"); return SK_ERR_INVALID_ARG; }
+  if (!d_packed && p->d.n_samples > 0) { set_error("NULL input"); return SK_ERR_INVALID_ARG; }
+  int dev = -1;
+  SK_HIP_TRY(hipGetDevice(&dev));
+  if (dev != p->device) { set_error("plan was created on device %d, current device is %d", p->device, dev); return SK_ERR_INVALID_ARG; }
+  hipStream_t s = (hipStream_t)stream;
+  const sk_plan_desc& d = p->d;
+  const int64_t N = d.n_inputs, F = d.n_channels, B = p->n_blocks;
+  if (B == 0) return SK_OK;
+
+  int32_t* s1 = outs->s1 ? outs->s1 : p->s1;
+  int32_t* s2 = outs->s2 ? outs->s2 : p->s2;
+
+  PassATask t;
+  PassAConfig c = plan_pass_a_config(p, d_packed, &t);
+  t.x = d_packed;
+  t.s1 = s1;
+  t.s2 = s2;
+  const bool rec = p->prof_n < p->prof_max;
+  if (rec) SK_HIP_TRY(hipEventRecord(p->prof[3 * p->prof_n], s));
+  int rc = launch_pass_a(t, c, s);
+  if (rc) return rc;
+  if (rec) SK_HIP_TRY(hipEventRecord(p->prof[3 * p->prof_n + 1], s));
+
+  PassBArgs a;
+  memset(&a, 0, sizeof a);
+  a.s1 = s1;
+  a.s2 = s2;
+  a.hist = p->hist[p->cur];
+  a.hist_next = p->hist[1 - p->cur];
+  a.chunk_sum = p->chunk_sum;
+  a.chunk_prefix = p->chunk_prefix;
+  a.mask = d_mask;
+  a.r1 = outs->r1;
+  a.r2 = outs->r2;
+  a.v = outs->v;
+  a.flags = outs->flags;
+  a.n_eff = outs->n_eff;
+  a.n_inputs = (int32_t)N;
+  a.n_channels = (int32_t)F;
+  a.n_blocks = (int32_t)B;
+  a.block_len = d.block_len;
+  a.window = d.norm_window_blocks;
+  a.hist_len = p->hist_len;
+  a.hist_cap = p->hist_cap;
+  a.chunk = p->chunk;
+  a.n_chunks = (int32_t)((p->hist_len + B + p->chunk - 1) / p->chunk);
+  a.estimator = d.estimator;
+  a.k_sigma = d.k_sigma;
+  a.expect_offset = d.expect_offset;
+  a.sigma_override = d.sigma_override;
+  rc = launch_pass_b(a, s);
+  if (rc) return rc;
+  if (rec) {
+    SK_HIP_TRY(hipEventRecord(p->prof[3 * p->prof_n + 2], s));
+    p->prof_n += 1;
+  }
+  if (p->hist_cap > 0) {
+    const int64_t total = p->hist_len + B;
+    p->hist_len = (int32_t)(total < p->hist_cap ? total : p->hist_cap);
+    p->cur = 1 - p->cur;
+  }
+  return SK_OK;
+}
+
+int sk_flags(sk_plan_t p, const float* d_v, const int32_t* d_n_eff, uint8_t* d_flags, int64_t n,
+             void* stream) {
+  clear_error();
+  if (!p || (n > 0 && (!d_v || !d_n_eff || !d_flags)) || n < 0) { set_error("bad arguments"); return SK_ERR_INVALID_ARG; }
+  FlagArgs a;
+  a.v = d_v;
+  a.n_eff = d_n_eff;
+  a.flags = d_flags;
+  a.n = n;
+  a.block_len = p->d.block_len;
+  a.window = p->d.norm_window_blocks;
+  a.estimator = p->d.estimator;
+  a.k_sigma = p->d.k_sigma;
+  a.expect_offset = p->d.expect_offset;
+  a.sigma_override = p->d.sigma_override;
+  return launch_flags(a, (hipStream_t)stream);
+}
+
+int sk_state_reset(sk_plan_t p) {
+  clear_error();
+  if (!p) { set_error("NULL plan"); return SK_ERR_INVALID_ARG; }
+  p->hist_len = 0;
+  return SK_OK;
+}
+
+int sk_state_size(sk_plan_t p, size_t* bytes) {
+  if (!p || !bytes) { set_error("NULL argument"); return SK_ERR_INVALID_ARG; }
+  *bytes = sizeof(StateHeader) + (size_t)p->d.n_channels * p->hist_len * p->d.n_inputs * sizeof(int32_t);
+  return SK_OK;
+}
+
+int sk_state_export(sk_plan_t p, void* host_buf, size_t cap, void* stream) {
+  clear_error();
+  size_t need = 0;
+  if (sk_state_size(p, &need)) return SK_ERR_INVALID_ARG;
+  if (!host_buf || cap < need) { set_error("buffer too small: need %zu", need); return SK_ERR_INVALID_ARG; }
+  StateHeader h = {kStateMagic, 1, p->d.n_inputs, p->d.n_channels, p->d.block_len, p->d.norm_window_blocks, p->hist_len, 0};
+  memcpy(host_buf, &h, sizeof h);
+  if (p->hist_len > 0) {
+    hipStream_t s = (hipStream_t)stream;
+    const size_t row = (size_t)p->hist_len * p->d.n_inputs * sizeof(int32_t);
+    for (int f = 0; f < p->d.n_channels; ++f) {
+      const int32_t* src = p->hist[p->cur] + (size_t)f * p->hist_cap * p->d.n_inputs;
+      SK_HIP_TRY(hipMemcpyAsync((char*)host_buf + sizeof h + f * row, src, row, hipMemcpyDeviceToHost, s));
+    }
+    SK_HIP_TRY(hipStreamSynchronize(s));
+  }
+  return SK_OK;
+}
+
+int sk_state_import(sk_plan_t p, const void* host_buf, size_t size, void* stream) {
+  clear_error();
+  if (!p || !host_buf || size < sizeof(StateHeader)) { set_error("bad arguments"); return SK_ERR_INVALID_ARG; }
+  StateHeader h;
+  memcpy(&h, host_buf, sizeof h);
+  if (h.magic != kStateMagic || h.version != 1 || h.n_inputs != p->d.n_inputs || h.n_channels != p->d.n_channels ||
+      h.block_len != p->d.block_len || h.window != p->d.norm_window_blocks || h.hist_len < 0 || h.hist_len > p->hist_cap) {
+    set_error("state blob does not match this plan");
+    return SK_ERR_STATE;
+  }
+  const size_t row = (size_t)h.hist_len * p->d.n_inputs * sizeof(int32_t);
+  if (size < sizeof h + row * p->d.n_channels) { set_error("state blob truncated"); return SK_ERR_STATE; }
+  hipStream_t s = (hipStream_t)stream;
+  if (h.hist_len > 0) {
+    for (int f = 0; f < p->d.n_channels; ++f) {
+      int32_t* dst = p->hist[p->cur] + (size_t)f * p->hist_cap * p->d.n_inputs;
+      SK_HIP_TRY(hipMemcpyAsync(dst, (const char*)host_buf + sizeof h + f * row, row, hipMemcpyHostToDevice, s));
+    }
+    SK_HIP_TRY(hipStreamSynchronize(s));
+  }
+  p->hist_len = h.hist_len;
+  return SK_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,96 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "sk.h"
+
+namespace sk {
+
+// Thread-local error message behind sk_last_error().
+void set_error(const char* fmt, ...);
+void clear_error();
+
+#define SK_HIP_TRY(expr)                                                          \
+  do {                                                                            \
+    hipError_t e_ = (expr);                                                       \
+    if (e_ != hipSuccess) {                                                       \
+      ::sk::set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_),      \
+                      __FILE__, __LINE__);                                        \
+      return SK_ERR_DEVICE;                                                       \
+    }                                                                             \
+  } while (0)
+
+// ---------------------------------------------------------------- pass A
+// Per-input block sums S1 = sum p, S2 = sum p^2 over the M samples of a block
+// (Eq. singlesums), for every (channel, block, input), from bytes [T][F][N].
+//
+// A row of the input is the G = F*N bytes of one time sample. A lane owns VEC
+// consecutive columns (inputs of one channel: N % VEC == 0) and walks rows.
+// A workgroup of 256 lanes covers LPR column groups times RP = 256/LPR row
+// phases of one block; partial sums of the row phases meet in LDS.
+struct PassATask {
+  const uint8_t* x;     // [T][F][N] bytes of this call
+  int32_t* s1;          // [F][B][N]
+  int32_t* s2;          // [F][B][N]
+  int64_t row_bytes;    // G = F * N
+  int32_t n_inputs;     // N
+  int32_t block_len;    // M
+  int32_t n_blocks;     // B
+  int32_t col_groups;   // G / VEC
+  int32_t chunks;       // ceil(col_groups / LPR)
+  int64_t n_tasks;      // B * chunks
+};
+
+struct PassAConfig {
+  int vec;     // 16, 4 or 1 bytes per lane per row
+  int lpr;     // lanes per row: power of two, 1..256
+  int grid;    // workgroups launched (<= tasks; grid-stride beyond)
+};
+
+int launch_pass_a(const PassATask& t, const PassAConfig& c, hipStream_t s);
+int pick_vec(const uint8_t* x, int32_t n_inputs);
+PassAConfig default_pass_a_config(int vec, int64_t row_bytes, int64_t n_blocks);
+
+// ---------------------------------------------------------------- pass B
+// Normaliser window, array combine, estimator and flags (Eq. discreteMean,
+// normedSum1/2, avgSK, final; Sec. 3.2).
+//
+// Extended block sequence per (channel, input): e = 0..H-1 are the H history
+// blocks (oldest first), e = H..H+B-1 the blocks of this call. Chunks of R
+// consecutive e carry exclusive prefix sums so any window sum is two lookups
+// plus fewer than R reads.
+struct PassBArgs {
+  const int32_t* s1;      // [F][B][N]
+  const int32_t* s2;      // [F][B][N]
+  const int32_t* hist;    // [F][Hcap][N], entries 0..H-1 valid (oldest first)
+  int32_t* hist_next;     // [F][Hcap][N] next history (written by the update kernel)
+  int64_t* chunk_sum;     // [F][nchunks][N]
+  int64_t* chunk_prefix;  // [F][nchunks + 1][N]
+  const uint8_t* mask;    // [F][N] or null
+  int64_t* r1;            // [F][B] or null
+  int64_t* r2;
+  float* v;
+  uint8_t* flags;
+  int32_t* n_eff;
+  int32_t n_inputs, n_channels, n_blocks, block_len, window, hist_len, hist_cap;
+  int32_t chunk, n_chunks, estimator;
+  double k_sigma, expect_offset, sigma_override;
+};
+
+int launch_pass_b(const PassBArgs& a, hipStream_t s);
+
+struct FlagArgs {
+  const float* v;
+  const int32_t* n_eff;
+  uint8_t* flags;
+  int64_t n;
+  int32_t block_len, window, estimator;
+  double k_sigma, expect_offset, sigma_override;
+};
+int launch_flags(const FlagArgs& a, hipStream_t s);
+
+}  // namespace sk

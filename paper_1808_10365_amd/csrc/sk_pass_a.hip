@@ -1,0 +1,227 @@
+// Pass A: per-input block sums of power and square power (Eq. singlesums).
+//
+// The input is one byte per complex sample, [T][F][N] (time-major, inputs
+// innermost). Each lane owns VEC consecutive inputs of one channel and walks
+// the rows (time samples) of a block with one VEC-byte nontemporal load per
+// row, so a wavefront reads 64*VEC contiguous bytes per row. Power comes from
+// a 256-entry LDS table indexed by the byte (Re and Im decoded from the
+// nibbles, Sec. 2.2.3 "Calculating Power"). Two rows' powers are packed into
+// the 16-bit halves of one register; v_dot2_u32_u16 then adds p0^2 + p1^2 to
+// the S2 accumulator and p0 + p1 (dot with (1,1)) to S1, so each sample costs
+// one byte extract, one LDS read and one dot-lane. Sums are exact in 32 bits:
+// p <= 128, so S2 <= M * 2^14 < 2^31 for M <= 131071.
+#include <hip/hip_runtime.h>
+
+#include "sk_internal.h"
+
+namespace sk {
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+// Power of one offset-encoded byte: high nibble = Re + 8, low = Im + 8.
+__device__ __forceinline__ uint32_t code_power(uint32_t c) {
+  const int re = (int)(c >> 4) - 8;
+  const int im = (int)(c & 15u) - 8;
+  return (uint32_t)(re * re + im * im);
+}
+
+template <int VEC>
+struct Row {
+  static constexpr int DW = VEC >= 4 ? VEC / 4 : 1;
+  uint32_t w[DW];
+  __device__ __forceinline__ void load(const uint8_t* p) {
+    if constexpr (VEC == 16) {
+      const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p));
+      w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
+    } else if constexpr (VEC == 4) {
+      w[0] = __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(p));
+    } else {
+      w[0] = *p;
+    }
+  }
+  __device__ __forceinline__ uint32_t byte(int k) const {
+    return (w[k >> 2] >> (8 * (k & 3))) & 0xFFu;
+  }
+};
+
+template <int VEC>
+__device__ __forceinline__ void accumulate_pair(const Row<VEC>& r0, const Row<VEC>& r1,
+                                                const uint16_t* lut, uint32_t* s1, uint32_t* s2) {
+  const u16x2 ones = {1, 1};
+#pragma unroll
+  for (int k = 0; k < VEC; ++k) {
+    const uint32_t pp = (uint32_t)lut[r0.byte(k)] | ((uint32_t)lut[r1.byte(k)] << 16);
+    const u16x2 P = __builtin_bit_cast(u16x2, pp);
+    s2[k] = __builtin_amdgcn_udot2(P, P, s2[k], false);
+    s1[k] = __builtin_amdgcn_udot2(P, ones, s1[k], false);
+  }
+}
+
+template <int VEC>
+__device__ __forceinline__ void accumulate_one(const Row<VEC>& r0, const uint16_t* lut,
+                                               uint32_t* s1, uint32_t* s2) {
+#pragma unroll
+  for (int k = 0; k < VEC; ++k) {
+    const uint32_t p = lut[r0.byte(k)];
+    s1[k] += p;
+    s2[k] += p * p;
+  }
+}
+
+template <int VEC, int LPR>
+__global__ __launch_bounds__(256) void pass_a_kernel(PassATask t) {
+  constexpr int RP = 256 / LPR;         // row phases per workgroup
+  constexpr int W = 2 * VEC + 1;        // LDS stride of one lane's partials (odd: no bank conflicts)
+  __shared__ uint16_t lut[256];
+  extern __shared__ uint32_t red[];     // [RP * LPR][W] when RP > 1
+
+  const int tid = threadIdx.x;
+  lut[tid] = (uint16_t)code_power((uint32_t)tid);
+  __syncthreads();
+
+  const int lc = tid % LPR;
+  const int ph = tid / LPR;
+  const int M = t.block_len;
+  const int64_t G = t.row_bytes;
+
+  for (int64_t task = blockIdx.x; task < t.n_tasks; task += gridDim.x) {
+    const int b = (int)(task / t.chunks);
+    const int ch = (int)(task % t.chunks);
+    const int g = ch * LPR + lc;
+    uint32_t s1[VEC], s2[VEC];
+#pragma unroll
+    for (int k = 0; k < VEC; ++k) s1[k] = s2[k] = 0;
+
+    if (g < t.col_groups) {
+      const uint8_t* base = t.x + (int64_t)b * M * G + (int64_t)g * VEC;
+      int r = ph;
+      // Four row pairs per trip: eight independent loads in flight.
+      for (; r + 7 * RP < M; r += 8 * RP) {
+        Row<VEC> q[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) q[u].load(base + (int64_t)(r + u * RP) * G);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) accumulate_pair<VEC>(q[2 * u], q[2 * u + 1], lut, s1, s2);
+      }
+      for (; r + RP < M; r += 2 * RP) {
+        Row<VEC> q0, q1;
+        q0.load(base + (int64_t)r * G);
+        q1.load(base + (int64_t)(r + RP) * G);
+        accumulate_pair<VEC>(q0, q1, lut, s1, s2);
+      }
+      if (r < M) {
+        Row<VEC> q0;
+        q0.load(base + (int64_t)r * G);
+        accumulate_one<VEC>(q0, lut, s1, s2);
+      }
+    }
+
+    const int N = t.n_inputs;
+    const int B = t.n_blocks;
+    if constexpr (RP == 1) {
+      if (g < t.col_groups) {
+        const int64_t col = (int64_t)g * VEC;
+        const int64_t f = col / N, i = col % N;
+        int32_t* d1 = t.s1 + (f * B + b) * N + i;
+        int32_t* d2 = t.s2 + (f * B + b) * N + i;
+        if constexpr (VEC >= 4) {
+#pragma unroll
+          for (int k = 0; k < VEC; k += 4) {
+            u32x4 a = {s1[k], s1[k + 1], s1[k + 2], s1[k + 3]};
+            u32x4 c = {s2[k], s2[k + 1], s2[k + 2], s2[k + 3]};
+            *reinterpret_cast<u32x4*>(d1 + k) = a;
+            *reinterpret_cast<u32x4*>(d2 + k) = c;
+          }
+        } else {
+          d1[0] = (int32_t)s1[0];
+          d2[0] = (int32_t)s2[0];
+        }
+      }
+    } else {
+      uint32_t* mine = red + (ph * LPR + lc) * W;
+#pragma unroll
+      for (int k = 0; k < VEC; ++k) {
+        mine[k] = s1[k];
+        mine[VEC + k] = s2[k];
+      }
+      __syncthreads();
+      for (int o = tid; o < LPR * 2 * VEC; o += 256) {
+        const int l = o / (2 * VEC), k = o % (2 * VEC);
+        uint32_t s = 0;
+#pragma unroll
+        for (int p = 0; p < RP; ++p) s += red[(p * LPR + l) * W + k];
+        const int gg = ch * LPR + l;
+        if (gg < t.col_groups) {
+          const int64_t col = (int64_t)gg * VEC + (k % VEC);
+          const int64_t f = col / N, i = col % N;
+          int32_t* dst = k < VEC ? t.s1 : t.s2;
+          dst[(f * B + b) * N + i] = (int32_t)s;
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+template <int VEC, int LPR>
+static int launch_one(const PassATask& t, int grid, hipStream_t s) {
+  constexpr int RP = 256 / LPR;
+  const size_t lds = RP > 1 ? sizeof(uint32_t) * 256 * (2 * VEC + 1) : 0;
+  pass_a_kernel<VEC, LPR><<<dim3(grid), dim3(256), lds, s>>>(t);
+  SK_HIP_TRY(hipGetLastError());
+  return SK_OK;
+}
+
+template <int VEC>
+static int launch_vec(const PassATask& t, int lpr, int grid, hipStream_t s) {
+  switch (lpr) {
+    case 1: return launch_one<VEC, 1>(t, grid, s);
+    case 2: return launch_one<VEC, 2>(t, grid, s);
+    case 4: return launch_one<VEC, 4>(t, grid, s);
+    case 8: return launch_one<VEC, 8>(t, grid, s);
+    case 16: return launch_one<VEC, 16>(t, grid, s);
+    case 32: return launch_one<VEC, 32>(t, grid, s);
+    case 64: return launch_one<VEC, 64>(t, grid, s);
+    case 128: return launch_one<VEC, 128>(t, grid, s);
+    case 256: return launch_one<VEC, 256>(t, grid, s);
+  }
+  set_error("pass A: unsupported lanes-per-row %d", lpr);
+  return SK_ERR_INVALID_ARG;
+}
+
+int pick_vec(const uint8_t* x, int32_t n_inputs) {
+  const uintptr_t a = reinterpret_cast<uintptr_t>(x);
+  if (n_inputs % 16 == 0 && a % 16 == 0) return 16;
+  if (n_inputs % 4 == 0 && a % 4 == 0) return 4;
+  return 1;
+}
+
+PassAConfig default_pass_a_config(int vec, int64_t row_bytes, int64_t n_blocks) {
+  const int64_t cg = row_bytes / vec;
+  int lpr = 1;
+  while (lpr < 256 && lpr < cg) lpr *= 2;
+  // Keep at least ~2048 workgroups in flight when the rows are wide: trade
+  // lanes-per-row for row phases (reduced in LDS).
+  while (lpr > 64 && n_blocks * ((cg + lpr - 1) / lpr) < 2048) lpr /= 2;
+  const int64_t tasks = n_blocks * ((cg + lpr - 1) / lpr);
+  PassAConfig c;
+  c.vec = vec;
+  c.lpr = lpr;
+  c.grid = (int)(tasks < (1 << 30) ? (tasks > 0 ? tasks : 1) : (1 << 30));
+  return c;
+}
+
+int launch_pass_a(const PassATask& t, const PassAConfig& c, hipStream_t s) {
+  if (t.n_tasks <= 0) return SK_OK;
+  const int grid = (int)(c.grid < t.n_tasks ? c.grid : t.n_tasks);
+  switch (c.vec) {
+    case 16: return launch_vec<16>(t, c.lpr, grid, s);
+    case 4: return launch_vec<4>(t, c.lpr, grid, s);
+    case 1: return launch_vec<1>(t, c.lpr, grid, s);
+  }
+  set_error("pass A: unsupported vector width %d", c.vec);
+  return SK_ERR_INVALID_ARG;
+}
+
+}  // namespace sk

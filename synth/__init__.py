@@ -14,7 +14,7 @@ on-sky data of Sec. 3.2 is not available):
                  tones in 2 channels, 20 impulsive 8-sample bursts (amplitude 7)
                  in 1 channel (Sec. 3.1: the Pathfinder has 256 receivers).
 * ``chime``      N=2048, F=4, T=2^18, sigma_i ~ U[1.5, 3.5], a tone whose offset
-                 sweeps across 1 channel, and on/off noise bursts in 5 % of the
+                 sweeps across 1 channel in the middle third of T, and on/off noise bursts in 5 % of the
                  256-sample blocks (Sec. 3.1: each CHIME GPU chip sees all 2048
                  receivers).
 * ``batched``    32 problems, N in {64,256,1024,2048}, M in {64,256,1024},
@@ -177,7 +177,8 @@ def chime(seed: int = 3, block_len: int = 256) -> Workload:
     rng = np.random.default_rng(seed)
     sigma = rng.uniform(1.5, 3.5, size=N)
     sweep_ch = int(rng.integers(0, F))
-    ev = [Event(TONE, sweep_ch, 0, T, 5.0, -0.5, 0.5)]
+    # The tone's offset sweeps across the channel during the middle third of T.
+    ev = [Event(TONE, sweep_ch, T // 3, 2 * T // 3, 5.0, -0.5, 0.5)]
     # On/off noise bursts: 5 % of (channel, 256-sample block) cells, in runs.
     G = 256
     nb = T // G

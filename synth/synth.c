@@ -102,8 +102,20 @@ typedef struct {
   const syn_desc* d;
   uint8_t* out;
   const uint32_t* thr;   /* [N][2*clip] */
+  const uint8_t* bin;    /* [N][256]: value for top byte of u (bit 7 set: straddles a threshold) */
   int64_t t_begin, t_end;
 } syn_job;
+
+/* Component value for uniform u: -clip + #{k : thr[k] <= u}. The per-input
+ * table answers directly for the 256-bin of u's top byte unless a threshold
+ * falls inside that bin; the result is the same either way. */
+static inline int syn_component(uint32_t u, const uint32_t* th, const uint8_t* bin, int C) {
+  uint8_t b = bin[u >> 24];
+  if (!(b & 0x80)) return (int)b - C;
+  int v = -C;
+  for (int k = 0; k < 2 * C; ++k) v += (th[k] <= u);
+  return v;
+}
 
 static void* syn_worker(void* arg) {
   syn_job* j = (syn_job*)arg;
@@ -125,9 +137,8 @@ static void* syn_worker(void* arg) {
           uint64_t r = syn_draw(kbg, base + i);
           uint32_t ure = (uint32_t)(r >> 32), uim = (uint32_t)r;
           const uint32_t* th = j->thr + (size_t)i * NT;
-          int re = -C, im = -C;
-          for (int k = 0; k < NT; ++k) { re += (th[k] <= ure); im += (th[k] <= uim); }
-          row[i] = syn_encode(re, im);
+          const uint8_t* bn = j->bin + (size_t)i * 256;
+          row[i] = syn_encode(syn_component(ure, th, bn, C), syn_component(uim, th, bn, C));
         }
         continue;
       }
@@ -170,20 +181,32 @@ int synth_fill(const syn_desc* d, uint8_t* out, int nthreads) {
   if (N <= 0 || d->n_channels <= 0 || d->n_samples < 0 || d->clip < 1 || d->clip > 7) return -1;
   uint32_t* thr = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)N * NT);
   if (!thr) return -2;
-  for (int i = 0; i < N; ++i) synth_thresholds(d->sigma[i], d->clip, thr + (size_t)i * NT);
+  uint8_t* bin = (uint8_t*)malloc((size_t)N * 256);
+  if (!bin) { free(thr); return -2; }
+  for (int i = 0; i < N; ++i) {
+    const uint32_t* th = thr + (size_t)i * NT;
+    synth_thresholds(d->sigma[i], d->clip, thr + (size_t)i * NT);
+    for (int hb = 0; hb < 256; ++hb) {
+      uint32_t lo = (uint32_t)hb << 24, hi = lo | 0xFFFFFFu;
+      int vlo = 0, vhi = 0;
+      for (int k = 0; k < NT; ++k) { vlo += (th[k] <= lo); vhi += (th[k] <= hi); }
+      bin[(size_t)i * 256 + hb] = (uint8_t)(vlo == vhi ? vlo : 0x80);
+    }
+  }
   if (nthreads < 1) nthreads = 1;
   if (nthreads > 256) nthreads = 256;
   pthread_t th[256];
   syn_job jobs[256];
   int64_t T = d->n_samples;
   for (int k = 0; k < nthreads; ++k) {
-    jobs[k].d = d; jobs[k].out = out; jobs[k].thr = thr;
+    jobs[k].d = d; jobs[k].out = out; jobs[k].thr = thr; jobs[k].bin = bin;
     jobs[k].t_begin = T * k / nthreads; jobs[k].t_end = T * (k + 1) / nthreads;
   }
   for (int k = 1; k < nthreads; ++k) pthread_create(&th[k], NULL, syn_worker, &jobs[k]);
   syn_worker(&jobs[0]);
   for (int k = 1; k < nthreads; ++k) pthread_join(th[k], NULL);
   free(thr);
+  free(bin);
   /* Impulsive bursts: overwrite with round(A e^{i phi}) on every input. */
   const uint64_t kph = syn_key(d->seed, 3);
   for (int e = 0; e < d->n_events; ++e) {

@@ -1,0 +1,268 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Small shapes span several tiles and ragged tails; the workload tests run the
+Pathfinder- and CHIME-shaped inputs at their full sizes in the launch
+configuration the benchmark times.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from parity import check_result
+
+torch = pytest.importorskip("torch")
+sk = pytest.importorskip("paper_1808_10365_amd")
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def run_gpu(x, M, L=1, est=0, k=5.0, delta=0.0, sigma_override=0.0, mask=None, lpr=0):
+    T, F, N = x.shape
+    plan = sk.Plan(N, F, T, M, norm_window=L, estimator=est, k_sigma=k, expect_offset=delta,
+                   sigma_override=sigma_override)
+    if lpr:
+        plan.set_pass_a_tile(lpr)
+    xd = torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+    md = None if mask is None else torch.from_numpy(np.ascontiguousarray(mask)).to(DEV)
+    out = plan.compute(xd, mask=md)
+    torch.cuda.synchronize()
+    plan.close()
+    return out
+
+
+def both(x, M, L=1, est=0, what="", **kw):
+    _say(f"case {what}: shape={x.shape} M={M} L={L} est={est}")
+    g = run_gpu(x, M, L, est, **kw)
+    mask = kw.get("mask")
+    r = oracle.sk(x, M, L, est, kw.get("k", 5.0), kw.get("delta", 0.0), kw.get("sigma_override", 0.0), mask)
+    check_result(g, r, M, L, est, kw.get("k", 5.0), kw.get("delta", 0.0), kw.get("sigma_override", 0.0), what)
+    return g, r
+
+
+# ----------------------------------------------------------------------------- tiny workload
+
+@pytest.mark.parametrize("L,est", [(1, 0), (1, 1), (4, 0), (0, 0), (2, 0), (16, 0)])
+def test_tiny_workload(L, est):
+    w = synth.tiny(seed=1)
+    x = synth.generate(w, nthreads=1)
+    g, r = both(x, w.block_len, L, est, what=f"tiny L={L}")
+    # The tone in blocks 3-5 is flagged low (a tone lowers the estimator).
+    if L in (1, 0):
+        assert np.all(r.flags[0, 3:6] & 1)
+
+
+# ----------------------------------------------------------------------------- ragged shapes
+
+RAGGED = [
+    # (T, F, N, M)      covers: 1-byte lanes, 4-byte lanes, 16-byte lanes, odd row counts, tails
+    (2 * 3, 1, 1, 3),
+    (64, 3, 5, 16),
+    (99, 2, 17, 33),
+    (128, 1, 48, 64),
+    (256, 3, 100, 32),
+    (96, 5, 160, 24),
+    (64, 2, 4096, 8),
+    (130, 1, 64, 65),
+    (40, 7, 2064, 10),
+]
+
+
+@pytest.mark.parametrize("shape", RAGGED)
+@pytest.mark.parametrize("L", [0, 1, 3])
+def test_ragged_random_bytes(shape, L):
+    # Uniform random bytes: every code, including code 0 (decodes to -8).
+    T, F, N, M = shape
+    rng = np.random.default_rng(T * 7 + F * 3 + N + M + L)
+    x = rng.integers(0, 256, size=(T, F, N), dtype=np.uint8)
+    both(x, M, L, what=f"ragged {shape}")
+
+
+@pytest.mark.parametrize("lpr", [1, 2, 4, 8, 16, 32, 64, 128, 256])
+def test_every_pass_a_tile(lpr):
+    rng = np.random.default_rng(lpr)
+    T, F, N, M = 96, 3, 512, 48
+    x = rng.integers(0, 256, size=(T, F, N), dtype=np.uint8)
+    both(x, M, 2, what=f"tile lpr={lpr}", lpr=lpr)
+
+
+def test_unaligned_input_pointer():
+    # An input view starting one byte into an allocation takes the 1-byte lane path.
+    rng = np.random.default_rng(3)
+    T, F, N, M = 64, 2, 32, 16
+    x = rng.integers(0, 256, size=(T * F * N + 1,), dtype=np.uint8)
+    xd = torch.from_numpy(x).to(DEV)[1:].view(T, F, N)
+    plan = sk.Plan(N, F, T, M, norm_window=1)
+    out = plan.compute(xd)
+    torch.cuda.synchronize()
+    r = oracle.sk(x[1:].reshape(T, F, N), M, 1)
+    check_result(out, r, M, 1, what="unaligned")
+
+
+def test_mask_and_dead_inputs():
+    T, F, N, M = 512, 3, 64, 64
+    w = synth.Workload("m", N, F, T, M, 77, np.full(N, 2.0), [])
+    x = synth.generate(w, nthreads=2)
+    x[:, :, 5] = 0x88           # zero power
+    x[:128, 1, 9] = 0x88        # zero power for two blocks of channel 1
+    mask = np.ones((F, N), np.uint8)
+    mask[0, :7] = 0
+    mask[2, 60] = 0
+    for L in (0, 1, 2, 4):
+        both(x, M, L, what=f"mask L={L}", mask=mask)
+    # Fully masked channel: invalid everywhere.
+    mask[1, :] = 0
+    g, r = both(x, M, 1, what="masked channel", mask=mask)
+    assert np.all(g.flags.cpu().numpy()[1] == sk.FLAG_INVALID)
+
+
+def test_cw_lattice_gives_zero():
+    x = synth.lattice_cw(n_inputs=32, n_channels=2, n_samples=64 * 16, seed=5)
+    for L in (0, 1, 4):
+        g, r = both(x, 64, L, what=f"cw L={L}")
+        v = g.v.cpu().numpy()
+        full = np.arange(v.shape[1]) >= max(L - 1, 0)
+        assert np.all(v[:, full] == 0.0)
+
+
+def test_gain_invariance_gpu():
+    T, F, N, M = 64 * 8, 2, 32, 64
+    re, im = synth.uniform_small(N, F, T, seed=21, vmax=3)
+    a = run_gpu(synth.encode(re, im), M, 3)
+    re[:, :, [1, 4, 17]] *= 2
+    im[:, :, [1, 4, 17]] *= 2
+    b = run_gpu(synth.encode(re, im), M, 3)
+    assert np.array_equal(a.v.cpu().numpy(), b.v.cpu().numpy())
+
+
+def test_flag_parameters():
+    w = synth.tiny(seed=9)
+    x = synth.generate(w, nthreads=1)
+    for kw in (dict(k=3.0), dict(k=5.0, delta=-0.06), dict(k=2.0, sigma_override=0.02)):
+        both(x, 256, 1, what=f"flags {kw}", **kw)
+        both(x, 256, 1, 1, what=f"flags tilde {kw}", **kw)
+
+
+def test_flags_entry_point():
+    rng = np.random.default_rng(4)
+    v = rng.normal(1.0, 0.05, size=(3, 1000)).astype(np.float32)
+    v[0, :5] = np.nan
+    ne = rng.integers(0, 64, size=(3, 1000)).astype(np.int32)
+    plan = sk.Plan(64, 3, 0, 256, norm_window=1, k_sigma=3.0, expect_offset=0.01)
+    fl = plan.flags(torch.from_numpy(v).to(DEV), torch.from_numpy(ne).to(DEV)).cpu().numpy()
+    ref = oracle.flags(v.astype(np.float64), ne, 256, 1, 0, 3.0, 0.01)
+    assert np.array_equal(fl, ref)
+
+
+def test_largest_block_no_overflow():
+    # M = 131071 with every sample at power 128: S2 = M * 2^14 = 2^31 - 2^14.
+    T, F, N, M = 131071 * 2, 1, 16, 131071
+    x = np.zeros((T, F, N), np.uint8)
+    x[:, :, 1::2] = 0xFF
+    g, r = both(x, M, 1, what="max M")
+    assert int(g.s2.cpu().numpy()[0, 0, 0]) == M * 128 * 128
+
+
+def test_empty_call():
+    plan = sk.Plan(16, 1, 0, 256, norm_window=4)
+    out = plan.compute(torch.empty((0, 1, 16), dtype=torch.uint8, device=DEV))
+    torch.cuda.synchronize()
+    assert out.v.numel() == 0
+
+
+# ----------------------------------------------------------------------------- stream semantics
+
+@pytest.mark.parametrize("L", [2, 5, 64])
+def test_stream_frames_equal_one_shot(L):
+    # Any cut of the stream into frames gives the outputs of one long call.
+    N, F, M = 48, 3, 32
+    cuts = [4, 1, 7, 2, 16, 3]                # frame lengths in blocks
+    T = sum(cuts) * M
+    w = synth.Workload("s", N, F, T, M, 31, np.random.default_rng(2).uniform(1.5, 3.5, N), [])
+    x = synth.generate(w, nthreads=2)
+    ref = oracle.sk(x, M, L)
+    t0 = 0
+    got_v, got_s1 = [], []
+    plans = {}
+    for c in cuts:
+        if c not in plans:
+            plans[c] = sk.Plan(N, F, c * M, M, norm_window=L)
+    state = None
+    for c in cuts:
+        p = plans[c]
+        if state is not None:
+            p.import_state(state)
+        out = p.compute(torch.from_numpy(x[t0:t0 + c * M].copy()).to(DEV))
+        torch.cuda.synchronize()
+        state = p.export_state()
+        got_v.append(out.v.cpu().numpy())
+        got_s1.append(out.s1.cpu().numpy())
+        t0 += c * M
+    v = np.concatenate(got_v, axis=1)
+    err = np.abs(v - ref.V) / np.maximum(1, np.abs(ref.V))
+    assert err.max() <= 1e-6
+    assert np.array_equal(np.concatenate(got_s1, axis=1), ref.S1)
+
+
+def test_state_reset_and_continuation():
+    N, F, M, L = 32, 2, 64, 8
+    T = 6 * M
+    x = synth.generate(synth.Workload("r", N, F, 2 * T, M, 5, np.full(N, 2.0), []), nthreads=2)
+    p = sk.Plan(N, F, T, M, norm_window=L)
+    a = p.compute(torch.from_numpy(x[:T].copy()).to(DEV))
+    b = p.compute(torch.from_numpy(x[T:].copy()).to(DEV))
+    torch.cuda.synchronize()
+    ref = oracle.sk(x, M, L)
+    assert np.allclose(np.concatenate([a.v.cpu().numpy(), b.v.cpu().numpy()], 1), ref.V, rtol=0, atol=1e-6)
+    p.reset()
+    c = p.compute(torch.from_numpy(x[T:].copy()).to(DEV))
+    torch.cuda.synchronize()
+    ref2 = oracle.sk(x[T:], M, L)
+    assert np.allclose(c.v.cpu().numpy(), ref2.V, rtol=0, atol=1e-6)
+    # A blob from another shape is refused.
+    q = sk.Plan(N + 1, F, T, M, norm_window=L)
+    with pytest.raises(sk.SKError):
+        q.import_state(p.export_state())
+
+
+# ----------------------------------------------------------------------------- full-size workloads
+
+def _workload_parity(w, L, reps=1):
+    _say(f"generate {w.name}: N={w.n_inputs} F={w.n_channels} T={w.n_samples} M={w.block_len} L={L}")
+    x = synth.generate(w)
+    delta, sig = sk.digitised_expectation(w.sigma, w.block_len)
+    plan = sk.Plan(w.n_inputs, w.n_channels, w.n_samples, w.block_len, norm_window=L, k_sigma=5.0,
+                   expect_offset=delta, sigma_override=sig)
+    xd = torch.from_numpy(x).to(DEV)
+    out = plan.compute(xd)
+    torch.cuda.synchronize()
+    _say(f"oracle {w.name}")
+    ref = oracle.sk(x, w.block_len, L, 0, 5.0, delta, sig)
+    clear, total = check_result(out, ref, w.block_len, L, 0, 5.0, delta, sig, w.name)
+    _say(f"{w.name}: parity ok, flags compared on {clear}/{total}, flagged {(ref.flags != 0).mean():.3%}")
+    plan.close()
+    return out, ref
+
+
+def test_pathfinder_full():
+    w = synth.pathfinder(seed=2)
+    out, ref = _workload_parity(w, w.norm_window)
+    # Sanity (not parity): the tone channels are flagged nearly everywhere.
+    tone_ch = [e.channel for e in w.events if e.kind == synth.TONE]
+    for c in tone_ch:
+        assert (ref.flags[c] != 0).mean() > 0.9
+
+
+@pytest.mark.parametrize("M", [256, 1024])
+def test_chime_full(M):
+    w = synth.chime(seed=3, block_len=M)
+    _workload_parity(w, w.norm_window)
