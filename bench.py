@@ -38,6 +38,10 @@ def parse():
     ap.add_argument("--cpu-sample-blocks", type=int, default=0,
                     help="blocks per channel in the oracle's timed sample (0: pick ~10-30 s of work)")
     ap.add_argument("--lpr", type=int, default=0, help="force pass A lanes per row")
+    ap.add_argument("--variant", type=int, default=-1, help="force pass A row batching variant (0..3)")
+    ap.add_argument("--grid", type=int, default=0, help="force pass A workgroup count (persistent loop)")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="after timing, run one device copy of this many MiB (counter calibration)")
     return ap.parse_args()
 
 
@@ -120,6 +124,8 @@ def main():
                    k_sigma=5.0, expect_offset=delta, sigma_override=sig)
     if args.lpr:
         plan.set_pass_a_tile(args.lpr)
+    if args.variant >= 0 or args.grid:
+        plan.set_pass_a_variant(max(args.variant, 0), args.grid)
     # Inputs resident in HBM. Inputs smaller than the 256 MB last-level cache
     # rotate over enough copies that repeats cannot be served from it.
     nbuf = max(1, int(np.ceil(1.0e9 / x.nbytes))) if x.nbytes < 1 << 30 else 1
@@ -152,6 +158,19 @@ def main():
     ms_a = np.array(ms_a[:n.value], dtype=np.float64)
     ms_b = np.array(ms_b[:n.value], dtype=np.float64)
     lib.sk_profile_enable(plan.handle, 0)
+
+    if args.copy_probe_mib > 0:
+        # A plain device copy of known size: its counter readings give the
+        # scale between the HBM byte counters and bytes moved.
+        nb = args.copy_probe_mib << 20
+        src = torch.empty(nb, dtype=torch.uint8, device=dev)
+        dst = torch.empty(nb, dtype=torch.uint8, device=dev)
+        src.fill_(7)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"# copy probe: {nb} bytes read, {nb} bytes written", file=sys.stderr, flush=True)
+        del src, dst
 
     vec, lpr, wgs = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
     lib.sk_plan_get_pass_a_tile(plan.handle, ctypes.c_void_p(xd[0].data_ptr()), ctypes.byref(vec),

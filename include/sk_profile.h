@@ -29,6 +29,12 @@ int sk_profile_read(sk_plan_t plan, float* ms_pass_a, float* ms_pass_b, int32_t 
 /* Force pass A's lanes per row (power of two, 1..256; 0 = library choice). */
 int sk_plan_set_pass_a_tile(sk_plan_t plan, int32_t lanes_per_row);
 
+/* Pass A's row batching variant (0: 8 rows per batch; 1: 8 rows with the
+ * next batch's loads issued before the current batch is reduced; 2: 4 rows
+ * with that prefetch; 3: 16 rows) and workgroup count (0: one per task;
+ * fewer: workgroups loop over tasks). */
+int sk_plan_set_pass_a_variant(sk_plan_t plan, int32_t variant, int32_t grid);
+
 /* Pass A's lanes per row and workgroup count for the next call (after
  * sk_plan_set_pass_a_tile or the library's choice), for reporting. */
 int sk_plan_get_pass_a_tile(sk_plan_t plan, const uint8_t* d_packed, int32_t* vec_bytes,

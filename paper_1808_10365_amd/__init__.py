@@ -72,12 +72,13 @@ def load_library():
     lib.sk_digitised_expectation.argtypes = [VP, I32, I32, I32, ctypes.POINTER(F64), ctypes.POINTER(F64)]
     lib.sk_plan_set_pass_a_tile.argtypes = [VP, I32]
     lib.sk_plan_get_pass_a_tile.argtypes = [VP, VP, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I64)]
+    lib.sk_plan_set_pass_a_variant.argtypes = [VP, I32, I32]
     lib.sk_profile_enable.argtypes = [VP, I32]
     lib.sk_profile_read.argtypes = [VP, VP, VP, I32, ctypes.POINTER(I32)]
     for name in ("sk_plan_create", "sk_plan_destroy", "sk_plan_device_bytes", "sk_compute", "sk_flags",
                  "sk_state_reset", "sk_state_size", "sk_state_export", "sk_state_import",
                  "sk_digitised_expectation", "sk_plan_set_pass_a_tile", "sk_plan_get_pass_a_tile",
-                 "sk_profile_enable", "sk_profile_read"):
+                 "sk_profile_enable", "sk_profile_read", "sk_plan_set_pass_a_variant"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -157,6 +158,10 @@ class Plan:
 
     def set_pass_a_tile(self, lanes_per_row: int):
         _check(self._lib.sk_plan_set_pass_a_tile(self.handle, int(lanes_per_row)))
+
+    def set_pass_a_variant(self, variant: int, grid: int = 0):
+        """Row batching variant of pass A (0..3) and workgroup count (0: one per task)."""
+        _check(self._lib.sk_plan_set_pass_a_variant(self.handle, int(variant), int(grid)))
 
     def alloc_outputs(self, device, want: Sequence[str] = ALL_OUTPUTS) -> Result:
         F, N, B = self.desc.n_channels, self.desc.n_inputs, self.n_blocks

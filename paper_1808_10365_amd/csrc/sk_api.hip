@@ -42,12 +42,18 @@ struct sk_plan_s {
   int32_t s1_s2_owned;
   int32_t* s1;             // [F][B][N] scratch
   int32_t* s2;
-  int64_t* chunk_sum;      // [F][n_chunks_max][N]
-  int64_t* chunk_prefix;   // [F][n_chunks_max + 1][N]
+  int32_t* chunk_sum;      // [F][n_chunks_max][N]
+  double* part_a;          // [F][n_groups_max][B] per-group partial sums of pass B
+  double* part_q;
+  int64_t* part_r1;
+  int64_t* part_r2;
+  int32_t* part_n;
   int32_t* hist[2];        // [F][hist_cap][N], ping-pong
   int32_t cur;             // index of the live history buffer
   size_t bytes;
   int pass_a_lpr;          // 0 = heuristic
+  int pass_a_variant;      // row batching variant of pass A
+  int pass_a_grid;         // 0 = one workgroup per task
   std::vector<hipEvent_t> prof;   // 3 events per recorded call
   int32_t prof_max, prof_n;
 };
@@ -94,7 +100,11 @@ static void free_plan_memory(sk_plan_s* p) {
     if (p->s2) (void)hipFree(p->s2);
   }
   if (p->chunk_sum) (void)hipFree(p->chunk_sum);
-  if (p->chunk_prefix) (void)hipFree(p->chunk_prefix);
+  if (p->part_a) (void)hipFree(p->part_a);
+  if (p->part_q) (void)hipFree(p->part_q);
+  if (p->part_r1) (void)hipFree(p->part_r1);
+  if (p->part_r2) (void)hipFree(p->part_r2);
+  if (p->part_n) (void)hipFree(p->part_n);
   if (p->hist[0]) (void)hipFree(p->hist[0]);
   if (p->hist[1]) (void)hipFree(p->hist[1]);
 }
@@ -133,20 +143,34 @@ int sk_plan_create(const sk_plan_desc* desc, sk_plan_t* out) {
   const int L = desc->norm_window_blocks;
   p->hist_cap = L >= 2 ? L - 1 : 0;
   p->hist_len = 0;
-  // Chunk length: about 512 combine workgroups, 1..64 blocks each.
+  // Chunk length R: a wavefront of the partial kernel reads about L/R chunk
+  // sums to start its window and 3R rows in its main loop, so R near
+  // sqrt(L) keeps the start-up cost small; R shrinks while there are too few
+  // wavefronts to fill the device.
   const int64_t seq = p->hist_cap + p->n_blocks;
-  int32_t R = pow2_floor(seq * F / 512);
-  if (R > 64) R = 64;
-  if (R < 1) R = 1;
+  const int64_t groups = (N + 63) / 64;   // upper bound (1 input per lane)
+  int32_t R = 1, R_min = 1;
+  if (L >= 2) {
+    while (R < 64 && (int64_t)R * R * 2 < L) R *= 2;          // L/R <= 2R
+    while (R_min < R && (int64_t)R_min * R_min * 8 < L) R_min *= 2;   // L/R <= 8R
+  } else {
+    R = 16;
+  }
+  while (R > R_min && ((seq + R - 1) / R) * F * ((N + 255) / 256) < 2048) R /= 2;
   p->chunk = R;
   p->n_chunks_max = (int32_t)((seq + R - 1) / R);
   p->s1_s2_owned = 1;
   const size_t fbn = (size_t)F * p->n_blocks * N;
   SK_ALLOC(p->s1, fbn * sizeof(int32_t));
   SK_ALLOC(p->s2, fbn * sizeof(int32_t));
+  const size_t fgb = (size_t)F * groups * p->n_blocks;
+  SK_ALLOC(p->part_a, fgb * sizeof(double));
+  SK_ALLOC(p->part_q, fgb * sizeof(double));
+  SK_ALLOC(p->part_r1, fgb * sizeof(int64_t));
+  SK_ALLOC(p->part_r2, fgb * sizeof(int64_t));
+  SK_ALLOC(p->part_n, fgb * sizeof(int32_t));
   if (L >= 2) {
-    SK_ALLOC(p->chunk_sum, (size_t)F * p->n_chunks_max * N * sizeof(int64_t));
-    SK_ALLOC(p->chunk_prefix, (size_t)F * (p->n_chunks_max + 1) * N * sizeof(int64_t));
+    SK_ALLOC(p->chunk_sum, (size_t)F * p->n_chunks_max * N * sizeof(int32_t));
     SK_ALLOC(p->hist[0], (size_t)F * p->hist_cap * N * sizeof(int32_t));
     SK_ALLOC(p->hist[1], (size_t)F * p->hist_cap * N * sizeof(int32_t));
   }
@@ -186,11 +210,20 @@ static PassAConfig plan_pass_a_config(const sk_plan_s* p, const uint8_t* d_packe
   t->n_blocks = (int32_t)B;
   PassAConfig c = default_pass_a_config(vec, t->row_bytes, B);
   if (p->pass_a_lpr) c.lpr = p->pass_a_lpr;
+  c.variant = p->pass_a_variant;
   t->col_groups = (int32_t)(t->row_bytes / vec);
   t->chunks = (t->col_groups + c.lpr - 1) / c.lpr;
   t->n_tasks = B * t->chunks;
   c.grid = (int)(t->n_tasks < (1 << 30) ? t->n_tasks : (1 << 30));
+  if (p->pass_a_grid > 0 && p->pass_a_grid < c.grid) c.grid = p->pass_a_grid;
   return c;
+}
+
+int sk_plan_set_pass_a_variant(sk_plan_t p, int32_t variant, int32_t grid) {
+  if (!p || variant < 0 || variant > 3 || grid < 0) { set_error("bad variant"); return SK_ERR_INVALID_ARG; }
+  p->pass_a_variant = variant;
+  p->pass_a_grid = grid;
+  return SK_OK;
 }
 
 int sk_plan_get_pass_a_tile(sk_plan_t p, const uint8_t* d_packed, int32_t* vec, int32_t* lpr, int64_t* wgs) {
@@ -263,7 +296,11 @@ int sk_compute(sk_plan_t p, const uint8_t* d_packed, const uint8_t* d_mask, cons
   a.hist = p->hist[p->cur];
   a.hist_next = p->hist[1 - p->cur];
   a.chunk_sum = p->chunk_sum;
-  a.chunk_prefix = p->chunk_prefix;
+  a.part_a = p->part_a;
+  a.part_q = p->part_q;
+  a.part_r1 = p->part_r1;
+  a.part_r2 = p->part_r2;
+  a.part_n = p->part_n;
   a.mask = d_mask;
   a.r1 = outs->r1;
   a.r2 = outs->r2;
@@ -277,8 +314,16 @@ int sk_compute(sk_plan_t p, const uint8_t* d_packed, const uint8_t* d_mask, cons
   a.window = d.norm_window_blocks;
   a.hist_len = p->hist_len;
   a.hist_cap = p->hist_cap;
+  {
+    const int64_t total = p->hist_len + B;
+    a.hist_next_len = (int32_t)(total < p->hist_cap ? total : p->hist_cap);
+  }
   a.chunk = p->chunk;
   a.n_chunks = (int32_t)((p->hist_len + B + p->chunk - 1) / p->chunk);
+  // Four inputs per lane need 16-byte aligned rows of the sums.
+  a.vec = pass_b_vec((int32_t)N);
+  if (((uintptr_t)s1 | (uintptr_t)s2) % 16 != 0) a.vec = 1;
+  a.n_groups = (int32_t)((N + 64 * a.vec - 1) / (64 * a.vec));
   a.estimator = d.estimator;
   a.k_sigma = d.k_sigma;
   a.expect_offset = d.expect_offset;

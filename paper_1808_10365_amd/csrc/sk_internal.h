@@ -48,6 +48,7 @@ struct PassATask {
 struct PassAConfig {
   int vec;     // 16, 4 or 1 bytes per lane per row
   int lpr;     // lanes per row: power of two, 1..256
+  int variant; // row batching variant (0..3, 16-byte path)
   int grid;    // workgroups launched (<= tasks; grid-stride beyond)
 };
 
@@ -67,20 +68,25 @@ struct PassBArgs {
   const int32_t* s1;      // [F][B][N]
   const int32_t* s2;      // [F][B][N]
   const int32_t* hist;    // [F][Hcap][N], entries 0..H-1 valid (oldest first)
-  int32_t* hist_next;     // [F][Hcap][N] next history (written by the update kernel)
-  int64_t* chunk_sum;     // [F][nchunks][N]
-  int64_t* chunk_prefix;  // [F][nchunks + 1][N]
+  int32_t* hist_next;     // [F][Hcap][N] history for the next call
+  int32_t* chunk_sum;     // [F][n_chunks][N] sums of S1 over chunks of the sequence
+  double* part_a;         // [F][n_groups][B] per-group partial sums
+  double* part_q;
+  int64_t* part_r1;
+  int64_t* part_r2;
+  int32_t* part_n;
   const uint8_t* mask;    // [F][N] or null
   int64_t* r1;            // [F][B] or null
   int64_t* r2;
   float* v;
   uint8_t* flags;
   int32_t* n_eff;
-  int32_t n_inputs, n_channels, n_blocks, block_len, window, hist_len, hist_cap;
-  int32_t chunk, n_chunks, estimator;
+  int32_t n_inputs, n_channels, n_blocks, block_len, window, hist_len, hist_cap, hist_next_len;
+  int32_t chunk, n_chunks, n_groups, vec, estimator;
   double k_sigma, expect_offset, sigma_override;
 };
 
+int pass_b_vec(int32_t n_inputs);
 int launch_pass_b(const PassBArgs& a, hipStream_t s);
 
 struct FlagArgs {

@@ -69,7 +69,56 @@ __device__ __forceinline__ void accumulate_one(const Row<VEC>& r0, const uint16_
   }
 }
 
-template <int VEC, int LPR>
+// Rows of this lane in batches of U: r = ph, ph + RP, ... (< M). With PF the
+// loads of the next batch are issued before the current batch is reduced, so
+// each wavefront keeps a batch of rows in flight while it computes.
+template <int VEC, int RP, int U, bool PF>
+__device__ __forceinline__ void sum_rows(const uint8_t* base, int64_t G, int M, int ph,
+                                         const uint16_t* lut, uint32_t* s1, uint32_t* s2) {
+  const int nrow = ph < M ? (M - ph + RP - 1) / RP : 0;
+  const int nb = nrow / U;
+  int r = ph;
+  if constexpr (PF) {
+    Row<VEC> cur[U], nxt[U];
+    if (nb > 0) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) cur[u].load(base + (int64_t)(r + u * RP) * G);
+    }
+    for (int bt = 0; bt < nb; ++bt) {
+      if (bt + 1 < nb) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) nxt[u].load(base + (int64_t)(r + (U + u) * RP) * G);
+      }
+#pragma unroll
+      for (int u = 0; u < U / 2; ++u) accumulate_pair<VEC>(cur[2 * u], cur[2 * u + 1], lut, s1, s2);
+#pragma unroll
+      for (int u = 0; u < U; ++u) cur[u] = nxt[u];
+      r += U * RP;
+    }
+  } else {
+    for (int bt = 0; bt < nb; ++bt) {
+      Row<VEC> q[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) q[u].load(base + (int64_t)(r + u * RP) * G);
+#pragma unroll
+      for (int u = 0; u < U / 2; ++u) accumulate_pair<VEC>(q[2 * u], q[2 * u + 1], lut, s1, s2);
+      r += U * RP;
+    }
+  }
+  for (; r + RP < M; r += 2 * RP) {
+    Row<VEC> q0, q1;
+    q0.load(base + (int64_t)r * G);
+    q1.load(base + (int64_t)(r + RP) * G);
+    accumulate_pair<VEC>(q0, q1, lut, s1, s2);
+  }
+  if (r < M) {
+    Row<VEC> q0;
+    q0.load(base + (int64_t)r * G);
+    accumulate_one<VEC>(q0, lut, s1, s2);
+  }
+}
+
+template <int VEC, int LPR, int U, bool PF>
 __global__ __launch_bounds__(256) void pass_a_kernel(PassATask t) {
   constexpr int RP = 256 / LPR;         // row phases per workgroup
   constexpr int W = 2 * VEC + 1;        // LDS stride of one lane's partials (odd: no bank conflicts)
@@ -93,29 +142,8 @@ __global__ __launch_bounds__(256) void pass_a_kernel(PassATask t) {
 #pragma unroll
     for (int k = 0; k < VEC; ++k) s1[k] = s2[k] = 0;
 
-    if (g < t.col_groups) {
-      const uint8_t* base = t.x + (int64_t)b * M * G + (int64_t)g * VEC;
-      int r = ph;
-      // Four row pairs per trip: eight independent loads in flight.
-      for (; r + 7 * RP < M; r += 8 * RP) {
-        Row<VEC> q[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) q[u].load(base + (int64_t)(r + u * RP) * G);
-#pragma unroll
-        for (int u = 0; u < 4; ++u) accumulate_pair<VEC>(q[2 * u], q[2 * u + 1], lut, s1, s2);
-      }
-      for (; r + RP < M; r += 2 * RP) {
-        Row<VEC> q0, q1;
-        q0.load(base + (int64_t)r * G);
-        q1.load(base + (int64_t)(r + RP) * G);
-        accumulate_pair<VEC>(q0, q1, lut, s1, s2);
-      }
-      if (r < M) {
-        Row<VEC> q0;
-        q0.load(base + (int64_t)r * G);
-        accumulate_one<VEC>(q0, lut, s1, s2);
-      }
-    }
+    if (g < t.col_groups)
+      sum_rows<VEC, RP, U, PF>(t.x + (int64_t)b * M * G + (int64_t)g * VEC, G, M, ph, lut, s1, s2);
 
     const int N = t.n_inputs;
     const int B = t.n_blocks;
@@ -149,7 +177,7 @@ __global__ __launch_bounds__(256) void pass_a_kernel(PassATask t) {
       for (int o = tid; o < LPR * 2 * VEC; o += 256) {
         const int l = o / (2 * VEC), k = o % (2 * VEC);
         uint32_t s = 0;
-#pragma unroll
+#pragma unroll 8
         for (int p = 0; p < RP; ++p) s += red[(p * LPR + l) * W + k];
         const int gg = ch * LPR + l;
         if (gg < t.col_groups) {
@@ -164,30 +192,46 @@ __global__ __launch_bounds__(256) void pass_a_kernel(PassATask t) {
   }
 }
 
-template <int VEC, int LPR>
+template <int VEC, int LPR, int U, bool PF>
 static int launch_one(const PassATask& t, int grid, hipStream_t s) {
   constexpr int RP = 256 / LPR;
   const size_t lds = RP > 1 ? sizeof(uint32_t) * 256 * (2 * VEC + 1) : 0;
-  pass_a_kernel<VEC, LPR><<<dim3(grid), dim3(256), lds, s>>>(t);
+  pass_a_kernel<VEC, LPR, U, PF><<<dim3(grid), dim3(256), lds, s>>>(t);
   SK_HIP_TRY(hipGetLastError());
   return SK_OK;
 }
 
-template <int VEC>
-static int launch_vec(const PassATask& t, int lpr, int grid, hipStream_t s) {
+template <int VEC, int U, bool PF>
+static int launch_lpr(const PassATask& t, int lpr, int grid, hipStream_t s) {
   switch (lpr) {
-    case 1: return launch_one<VEC, 1>(t, grid, s);
-    case 2: return launch_one<VEC, 2>(t, grid, s);
-    case 4: return launch_one<VEC, 4>(t, grid, s);
-    case 8: return launch_one<VEC, 8>(t, grid, s);
-    case 16: return launch_one<VEC, 16>(t, grid, s);
-    case 32: return launch_one<VEC, 32>(t, grid, s);
-    case 64: return launch_one<VEC, 64>(t, grid, s);
-    case 128: return launch_one<VEC, 128>(t, grid, s);
-    case 256: return launch_one<VEC, 256>(t, grid, s);
+    case 1: return launch_one<VEC, 1, U, PF>(t, grid, s);
+    case 2: return launch_one<VEC, 2, U, PF>(t, grid, s);
+    case 4: return launch_one<VEC, 4, U, PF>(t, grid, s);
+    case 8: return launch_one<VEC, 8, U, PF>(t, grid, s);
+    case 16: return launch_one<VEC, 16, U, PF>(t, grid, s);
+    case 32: return launch_one<VEC, 32, U, PF>(t, grid, s);
+    case 64: return launch_one<VEC, 64, U, PF>(t, grid, s);
+    case 128: return launch_one<VEC, 128, U, PF>(t, grid, s);
+    case 256: return launch_one<VEC, 256, U, PF>(t, grid, s);
   }
   set_error("pass A: unsupported lanes-per-row %d", lpr);
   return SK_ERR_INVALID_ARG;
+}
+
+// Row batching variants (the 16-byte path only; others use variant 0):
+//   0: 8 rows per batch            1: 8 rows, next batch prefetched
+//   2: 4 rows, prefetched          3: 16 rows per batch
+template <int VEC>
+static int launch_vec(const PassATask& t, int lpr, int variant, int grid, hipStream_t s) {
+  if constexpr (VEC == 16) {
+    switch (variant) {
+      case 1: return launch_lpr<VEC, 8, true>(t, lpr, grid, s);
+      case 2: return launch_lpr<VEC, 4, true>(t, lpr, grid, s);
+      case 3: return launch_lpr<VEC, 16, false>(t, lpr, grid, s);
+      default: break;
+    }
+  }
+  return launch_lpr<VEC, 8, false>(t, lpr, grid, s);
 }
 
 int pick_vec(const uint8_t* x, int32_t n_inputs) {
@@ -208,6 +252,7 @@ PassAConfig default_pass_a_config(int vec, int64_t row_bytes, int64_t n_blocks) 
   PassAConfig c;
   c.vec = vec;
   c.lpr = lpr;
+  c.variant = 0;
   c.grid = (int)(tasks < (1 << 30) ? (tasks > 0 ? tasks : 1) : (1 << 30));
   return c;
 }
@@ -216,9 +261,9 @@ int launch_pass_a(const PassATask& t, const PassAConfig& c, hipStream_t s) {
   if (t.n_tasks <= 0) return SK_OK;
   const int grid = (int)(c.grid < t.n_tasks ? c.grid : t.n_tasks);
   switch (c.vec) {
-    case 16: return launch_vec<16>(t, c.lpr, grid, s);
-    case 4: return launch_vec<4>(t, c.lpr, grid, s);
-    case 1: return launch_vec<1>(t, c.lpr, grid, s);
+    case 16: return launch_vec<16>(t, c.lpr, c.variant, grid, s);
+    case 4: return launch_vec<4>(t, c.lpr, c.variant, grid, s);
+    case 1: return launch_vec<1>(t, c.lpr, c.variant, grid, s);
   }
   set_error("pass A: unsupported vector width %d", c.vec);
   return SK_ERR_INVALID_ARG;

@@ -8,16 +8,21 @@
 // of a (channel, block) and cancels in the estimator, so the weights are
 // 1/P_i (Eq. normedSum1, normedSum2).
 //
-// Kernels, in launch order for L >= 2:
-//   chunk_sum_kernel     sum of S1 over each chunk of R consecutive e
-//   chunk_scan_kernel    exclusive prefix over chunks (int64)
-//   combine_kernel       one workgroup per (chunk, channel): window sums by
-//                        sliding P += S1[e] - S1[e-L] from a start value made
-//                        of two prefix lookups; per block, FP64 A and Bq and
-//                        int64 R1, R2 summed over inputs in a fixed order
-//                        (lane-sequential, then a fixed tree), then V and flags
-//   hist_update_kernel   keep the last min(L-1, H+B) blocks for the next call
-// For L <= 1 only combine_kernel runs (P is the block's own S1).
+// Kernels:
+//   chunk_sum_kernel   (L >= 2) sum of S1 over each chunk of R consecutive e.
+//   partial_kernel     one wavefront per (chunk, channel, 64*V inputs): the
+//                      window start of the chunk from chunk sums plus fewer
+//                      than R edge reads, then per block the sliding update
+//                      P += S1[e] - S1[e-L] and the lane's FP64 A, Bq and
+//                      int64 R1, R2 over its V inputs, a butterfly reduction
+//                      across the wavefront, one partial per (block, group).
+//                      It also writes the blocks that form the next history.
+//   finalize_kernel    one thread per (channel, block): sums the partials in
+//                      group order, then the estimator and the flags.
+//   hist_copy_kernel   only when a call has fewer than L-1 blocks: carries the
+//                      still-needed old history entries forward.
+// Every sum runs in a fixed order (lane-sequential, butterfly, group order),
+// so results are identical from call to call.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -25,74 +30,233 @@
 
 namespace sk {
 
-__device__ __forceinline__ int32_t seq_s1(const PassBArgs& a, int f, int64_t e, int i) {
-  if (e < a.hist_len) return a.hist[((int64_t)f * a.hist_cap + e) * a.n_inputs + i];
-  return a.s1[((int64_t)f * a.n_blocks + (e - a.hist_len)) * a.n_inputs + i];
+template <int V>
+struct IVec;
+template <>
+struct IVec<1> {
+  int32_t v[1];
+  __device__ __forceinline__ void load(const int32_t* p) { v[0] = *p; }
+  __device__ __forceinline__ void store(int32_t* p) const { *p = v[0]; }
+};
+template <>
+struct IVec<4> {
+  int32_t v[4];
+  __device__ __forceinline__ void load(const int32_t* p) {
+    const int4 q = *reinterpret_cast<const int4*>(p);
+    v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+  }
+  __device__ __forceinline__ void store(int32_t* p) const {
+    *reinterpret_cast<int4*>(p) = make_int4(v[0], v[1], v[2], v[3]);
+  }
+};
+
+// Row of S1 for sequence position e (history or this call), channel f.
+__device__ __forceinline__ const int32_t* seq_row(const PassBArgs& a, int f, int64_t e) {
+  if (e < a.hist_len) return a.hist + ((int64_t)f * a.hist_cap + e) * a.n_inputs;
+  return a.s1 + ((int64_t)f * a.n_blocks + (e - a.hist_len)) * a.n_inputs;
 }
 
+template <int V>
 __global__ __launch_bounds__(256) void chunk_sum_kernel(PassBArgs a) {
   const int c = blockIdx.x, f = blockIdx.y;
-  const int i = blockIdx.z * 256 + threadIdx.x;
-  if (i >= a.n_inputs) return;
+  const int i0 = (blockIdx.z * 256 + threadIdx.x) * V;
+  if (i0 >= a.n_inputs) return;
   const int64_t total = (int64_t)a.hist_len + a.n_blocks;
   const int64_t e0 = (int64_t)c * a.chunk;
   const int64_t e1 = e0 + a.chunk < total ? e0 + a.chunk : total;
-  int64_t s = 0;
-  for (int64_t e = e0; e < e1; ++e) s += seq_s1(a, f, e, i);
-  a.chunk_sum[((int64_t)f * a.n_chunks + c) * a.n_inputs + i] = s;
+  IVec<V> s;
+#pragma unroll
+  for (int k = 0; k < V; ++k) s.v[k] = 0;
+  for (int64_t e = e0; e < e1; ++e) {
+    IVec<V> x;
+    x.load(seq_row(a, f, e) + i0);
+#pragma unroll
+    for (int k = 0; k < V; ++k) s.v[k] += x.v[k];
+  }
+  s.store(a.chunk_sum + ((int64_t)f * a.n_chunks + c) * a.n_inputs + i0);
 }
 
-__global__ __launch_bounds__(256) void chunk_scan_kernel(PassBArgs a) {
-  const int f = blockIdx.x;
-  const int i = blockIdx.y * 256 + threadIdx.x;
-  if (i >= a.n_inputs) return;
-  const int64_t N = a.n_inputs;
-  int64_t run = 0;
-  int64_t* out = a.chunk_prefix + (int64_t)f * (a.n_chunks + 1) * N + i;
-  const int64_t* in = a.chunk_sum + (int64_t)f * a.n_chunks * N + i;
-  out[0] = 0;
-  for (int c = 0; c < a.n_chunks; ++c) {
-    run += in[(int64_t)c * N];
-    out[(int64_t)(c + 1) * N] = run;
+// Sum of S1 over sequence positions [lo, hi) for V inputs at i0.
+template <int V>
+__device__ void window_sum(const PassBArgs& a, int f, int64_t lo, int64_t hi, int i0, int32_t* out) {
+#pragma unroll
+  for (int k = 0; k < V; ++k) out[k] = 0;
+  if (hi <= lo) return;
+  const int64_t R = a.chunk;
+  const int64_t cs = (lo + R - 1) / R;   // first chunk fully inside
+  const int64_t ce = hi / R;             // one past the last chunk fully inside
+  int64_t edge_hi = hi;
+  if (cs < ce) {
+#pragma unroll 8
+    for (int64_t c = cs; c < ce; ++c) {
+      IVec<V> t;
+      t.load(a.chunk_sum + ((int64_t)f * a.n_chunks + c) * a.n_inputs + i0);
+#pragma unroll
+      for (int k = 0; k < V; ++k) out[k] += t.v[k];
+    }
+    for (int64_t e = ce * R; e < hi; ++e) {
+      IVec<V> x;
+      x.load(seq_row(a, f, e) + i0);
+#pragma unroll
+      for (int k = 0; k < V; ++k) out[k] += x.v[k];
+    }
+    edge_hi = cs * R;
+  }
+  for (int64_t e = lo; e < edge_hi; ++e) {
+    IVec<V> x;
+    x.load(seq_row(a, f, e) + i0);
+#pragma unroll
+    for (int k = 0; k < V; ++k) out[k] += x.v[k];
   }
 }
 
-// Exclusive prefix of S1 over the sequence up to (not including) x.
-__device__ int64_t seq_prefix(const PassBArgs& a, int f, int64_t x, int i) {
-  const int64_t q = x / a.chunk;
-  int64_t s = a.chunk_prefix[((int64_t)f * (a.n_chunks + 1) + q) * a.n_inputs + i];
-  for (int64_t e = q * a.chunk; e < x; ++e) s += seq_s1(a, f, e, i);
-  return s;
+// Wavefront sums with DPP lane moves (VALU only, no LDS). Butterflies
+// inside each row of 16 lanes (quad_perm xor 1, xor 2, half-row mirror, row
+// mirror), then row_bcast:15 and row_bcast:31 fold the four rows; the total
+// lands in lane 63. The order of additions is fixed.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint32_t dpp_mov(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, 0xF, false);
 }
 
-struct Partial {
-  double a, q;
-  int64_t r1, r2;
-  int32_t n;
-};
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_step(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = dpp_mov<CTRL, ROW_MASK>((uint32_t)u);
+  const uint32_t hi = dpp_mov<CTRL, ROW_MASK>((uint32_t)(u >> 32));
+  return v + __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
 
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ int64_t dpp_step(int64_t v) {
+  const uint64_t u = (uint64_t)v;
+  const uint32_t lo = dpp_mov<CTRL, ROW_MASK>((uint32_t)u);
+  const uint32_t hi = dpp_mov<CTRL, ROW_MASK>((uint32_t)(u >> 32));
+  return v + (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ int32_t dpp_step(int32_t v) {
+  return v + (int32_t)dpp_mov<CTRL, ROW_MASK>((uint32_t)v);
+}
+
+// Sum over the 64 lanes, valid in lane 63.
 template <typename T>
-__device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+__device__ __forceinline__ T wave_sum_to_last(T v) {
+  v = dpp_step<0xB1, 0xF>(v);    // quad_perm [1,0,3,2]
+  v = dpp_step<0x4E, 0xF>(v);    // quad_perm [2,3,0,1]
+  v = dpp_step<0x141, 0xF>(v);   // row_half_mirror
+  v = dpp_step<0x140, 0xF>(v);   // row_mirror
+  v = dpp_step<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
+  v = dpp_step<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
   return v;
 }
 
+template <int V>
+__global__ __launch_bounds__(256) void partial_kernel(PassBArgs a) {
+  constexpr int U = 4;                                         // blocks loaded together
+  const int c = blockIdx.x, f = blockIdx.y;
+  const int lane = threadIdx.x & 63;
+  const int g = blockIdx.z * 4 + (threadIdx.x >> 6);          // input group of 64*V
+  const int N = a.n_inputs, L = a.window, H = a.hist_len;
+  const int i0 = (g * 64 + lane) * V;
+  if (g >= a.n_groups) return;                                 // whole wavefront exits
+  const bool active = i0 < N;
+  const int64_t total = (int64_t)H + a.n_blocks;
+  int64_t e0 = (int64_t)c * a.chunk;
+  if (e0 < H) e0 = H;
+  int64_t e1 = (int64_t)(c + 1) * a.chunk;
+  if (e1 > total) e1 = total;
+  if (e0 >= e1) return;
+  const int64_t hist_from = total - a.hist_next_len;          // first e of the next history
+
+  int32_t P[V];
+#pragma unroll
+  for (int k = 0; k < V; ++k) P[k] = 0;
+  uint32_t use_mask = 0;
+  if (active) {
+    if (L >= 2) window_sum<V>(a, f, e0 - L > 0 ? e0 - L : 0, e0, i0, P);
+#pragma unroll
+    for (int k = 0; k < V; ++k)
+      if (a.mask == nullptr || a.mask[(int64_t)f * N + i0 + k] != 0) use_mask |= 1u << k;
+  }
+
+  for (int64_t eb = e0; eb < e1; eb += U) {
+    IVec<V> x1[U], x2[U], old[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t e = eb + u;
+#pragma unroll
+      for (int k = 0; k < V; ++k) x1[u].v[k] = x2[u].v[k] = old[u].v[k] = 0;
+      if (active && e < e1) {
+        const int64_t row = ((int64_t)f * a.n_blocks + (e - H)) * N + i0;
+        x1[u].load(a.s1 + row);
+        x2[u].load(a.s2 + row);
+        if (L >= 2 && e - L >= 0) old[u].load(seq_row(a, f, e - L) + i0);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t e = eb + u;
+      if (e >= e1) break;
+      double pa = 0.0, pq = 0.0;
+      int64_t r1 = 0, r2 = 0;
+      int32_t n = 0;
+      if (active) {
+        if (L >= 2) {
+#pragma unroll
+          for (int k = 0; k < V; ++k) P[k] += x1[u].v[k] - old[u].v[k];
+          if (e >= hist_from) x1[u].store(a.hist_next + ((int64_t)f * a.hist_cap + (e - hist_from)) * N + i0);
+        } else {
+#pragma unroll
+          for (int k = 0; k < V; ++k) P[k] = x1[u].v[k];
+        }
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+          if ((use_mask >> k & 1u) && P[k] > 0) {
+            n += 1;
+            r1 += x1[u].v[k];
+            r2 += x2[u].v[k];
+            if (L >= 1) {
+              const double pd = (double)P[k];
+              pa += (double)x1[u].v[k] / pd;
+              pq += (double)x2[u].v[k] / (pd * pd);
+            }
+          }
+        }
+      }
+      pa = wave_sum_to_last(pa);
+      pq = wave_sum_to_last(pq);
+      r1 = wave_sum_to_last(r1);
+      r2 = wave_sum_to_last(r2);
+      n = wave_sum_to_last(n);
+      if (lane == 63) {
+        const int64_t o = ((int64_t)f * a.n_groups + g) * a.n_blocks + (e - H);
+        a.part_a[o] = pa;
+        a.part_q[o] = pq;
+        a.part_r1[o] = r1;
+        a.part_r2[o] = r2;
+        a.part_n[o] = n;
+      }
+    }
+  }
+}
+
 // Estimator and flags from the combined sums (Eq. avgSK, final; Sec. 3.2).
-// Written with contraction off so the rounding steps are the plain ones.
-__device__ void finish(const PassBArgs& a, int f, int b, const Partial& p) {
+// Contraction is off so the rounding steps are the plain ones.
+__device__ void finish(const PassBArgs& a, int f, int b, double A, double Bq, int64_t R1, int64_t R2,
+                       int32_t n) {
 #pragma clang fp contract(off)
-  const int64_t K = (int64_t)p.n * a.block_len;
+  const int64_t K = (int64_t)n * a.block_len;
   const double Kd = (double)K, Md = (double)a.block_len;
   bool invalid = K < 2;
   double V = 0.0;
-  double A = p.a, Bq = p.q;
   if (a.window == 0) {
-    invalid = invalid || p.r1 == 0;
+    invalid = invalid || R1 == 0;
     if (!invalid) {
       // Eq. (2) over all K samples, numerator K R2 - R1^2 formed exactly.
-      const __int128 num = (__int128)K * (__int128)p.r2 - (__int128)p.r1 * (__int128)p.r1;
-      const __int128 den = (__int128)p.r1 * (__int128)p.r1;
+      const __int128 num = (__int128)K * (__int128)R2 - (__int128)R1 * (__int128)R1;
+      const __int128 den = (__int128)R1 * (__int128)R1;
       const double nd = (double)(int64_t)(num >> 64) * 18446744073709551616.0 + (double)(uint64_t)num;
       const double dd = (double)(int64_t)(den >> 64) * 18446744073709551616.0 + (double)(uint64_t)den;
       V = (Kd + 1.0) / (Kd - 1.0) * (nd / dd);
@@ -101,7 +265,7 @@ __device__ void finish(const PassBArgs& a, int f, int b, const Partial& p) {
     invalid = invalid || A == 0.0;
     if (!invalid) {
       if (a.estimator == SK_EST_TILDE)
-        V = (Md + 1.0) / (Md - 1.0) * (Md * Bq / (double)p.n - 1.0);
+        V = (Md + 1.0) / (Md - 1.0) * (Md * Bq / (double)n - 1.0);
       else
         V = (Kd + 1.0) / (Kd - 1.0) * (Kd * Bq / (A * A) - 1.0);
     }
@@ -119,119 +283,66 @@ __device__ void finish(const PassBArgs& a, int f, int b, const Partial& p) {
     fl = (V < lo ? SK_FLAG_LOW : 0) | (V > hi ? SK_FLAG_HIGH : 0);
   }
   const int64_t o = (int64_t)f * a.n_blocks + b;
-  if (a.r1) a.r1[o] = p.r1;
-  if (a.r2) a.r2[o] = p.r2;
+  if (a.r1) a.r1[o] = R1;
+  if (a.r2) a.r2[o] = R2;
   if (a.v) a.v[o] = (float)V;
   if (a.flags) a.flags[o] = fl;
-  if (a.n_eff) a.n_eff[o] = p.n;
+  if (a.n_eff) a.n_eff[o] = n;
 }
 
-__global__ __launch_bounds__(256) void combine_kernel(PassBArgs a) {
-  extern __shared__ int32_t pwin[];          // [N] running window sums (L >= 2)
-  __shared__ Partial wpart[4];
-
-  const int c = blockIdx.x, f = blockIdx.y;
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  const int N = a.n_inputs, L = a.window, H = a.hist_len;
-  const int64_t total = (int64_t)H + a.n_blocks;
-  int64_t e0 = (int64_t)c * a.chunk;
-  if (e0 < H) e0 = H;
-  int64_t e1 = (int64_t)(c + 1) * a.chunk;
-  if (e1 > total) e1 = total;
-  if (e0 >= e1) return;
-
-  if (L >= 2) {
-    for (int i = tid; i < N; i += 256) {
-      const int64_t lo = e0 - L > 0 ? e0 - L : 0;
-      pwin[i] = (int32_t)(seq_prefix(a, f, e0, i) - seq_prefix(a, f, lo, i));
-    }
+__global__ __launch_bounds__(256) void finalize_kernel(PassBArgs a) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= (int64_t)a.n_channels * a.n_blocks) return;
+  const int f = (int)(j / a.n_blocks), b = (int)(j % a.n_blocks);
+  double A = 0.0, Bq = 0.0;
+  int64_t R1 = 0, R2 = 0;
+  int32_t n = 0;
+  for (int g = 0; g < a.n_groups; ++g) {
+    const int64_t o = ((int64_t)f * a.n_groups + g) * a.n_blocks + b;
+    A += a.part_a[o];
+    Bq += a.part_q[o];
+    R1 += a.part_r1[o];
+    R2 += a.part_r2[o];
+    n += a.part_n[o];
   }
-
-  for (int64_t e = e0; e < e1; ++e) {
-    const int b = (int)(e - H);
-    Partial p = {0.0, 0.0, 0, 0, 0};
-    const int32_t* r1p = a.s1 + ((int64_t)f * a.n_blocks + b) * N;
-    const int32_t* r2p = a.s2 + ((int64_t)f * a.n_blocks + b) * N;
-    for (int i = tid; i < N; i += 256) {
-      const int32_t x1 = r1p[i], x2 = r2p[i];
-      int32_t P = x1;
-      if (L >= 2) {
-        const int32_t old = e - L >= 0 ? seq_s1(a, f, e - L, i) : 0;
-        P = pwin[i] + x1 - old;
-        pwin[i] = P;
-      }
-      const bool use = (a.mask == nullptr || a.mask[(int64_t)f * N + i] != 0) && P > 0;
-      if (use) {
-        p.n += 1;
-        p.r1 += x1;
-        p.r2 += x2;
-        if (L >= 1) {
-          const double pd = (double)P;
-          p.a += (double)x1 / pd;
-          p.q += (double)x2 / (pd * pd);
-        }
-      }
-    }
-    p.a = wave_sum(p.a);
-    p.q = wave_sum(p.q);
-    p.r1 = wave_sum(p.r1);
-    p.r2 = wave_sum(p.r2);
-    p.n = wave_sum(p.n);
-    if (lane == 0) wpart[wid] = p;
-    __syncthreads();
-    if (tid == 0) {
-      Partial s = wpart[0];
-      for (int w = 1; w < 4; ++w) {
-        s.a += wpart[w].a;
-        s.q += wpart[w].q;
-        s.r1 += wpart[w].r1;
-        s.r2 += wpart[w].r2;
-        s.n += wpart[w].n;
-      }
-      finish(a, f, b, s);
-    }
-    __syncthreads();
-  }
+  finish(a, f, b, A, Bq, R1, R2, n);
 }
 
-__global__ __launch_bounds__(256) void hist_update_kernel(PassBArgs a, int new_len) {
+__global__ __launch_bounds__(256) void hist_copy_kernel(PassBArgs a, int n_old) {
   const int j = blockIdx.x, f = blockIdx.y;
   const int i = blockIdx.z * 256 + threadIdx.x;
   if (i >= a.n_inputs) return;
-  const int64_t e = (int64_t)a.hist_len + a.n_blocks - new_len + j;
-  a.hist_next[((int64_t)f * a.hist_cap + j) * a.n_inputs + i] = seq_s1(a, f, e, i);
+  const int64_t src = (int64_t)a.hist_len + a.n_blocks - a.hist_next_len + j;   // < hist_len
+  a.hist_next[((int64_t)f * a.hist_cap + j) * a.n_inputs + i] =
+      a.hist[((int64_t)f * a.hist_cap + src) * a.n_inputs + i];
 }
 
-int launch_pass_b(const PassBArgs& a, hipStream_t s) {
-  const int N = a.n_inputs, F = a.n_channels;
-  const int ig = (N + 255) / 256;
-  if (a.n_blocks <= 0) return SK_OK;
+template <int V>
+static int launch_v(const PassBArgs& a, hipStream_t s) {
+  const int F = a.n_channels;
+  const int zc = (a.n_inputs + 256 * V - 1) / (256 * V);
   if (a.window >= 2) {
-    chunk_sum_kernel<<<dim3(a.n_chunks, F, ig), dim3(256), 0, s>>>(a);
+    chunk_sum_kernel<V><<<dim3(a.n_chunks, F, zc), dim3(256), 0, s>>>(a);
     SK_HIP_TRY(hipGetLastError());
-    chunk_scan_kernel<<<dim3(F, ig), dim3(256), 0, s>>>(a);
-    SK_HIP_TRY(hipGetLastError());
-  }
-  const size_t lds = a.window >= 2 ? sizeof(int32_t) * (size_t)N : 0;
-  if (lds > 48 * 1024) {
-    static bool raised = false;
-    if (!raised) {
-      SK_HIP_TRY(hipFuncSetAttribute((const void*)combine_kernel,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024));
-      raised = true;
-    }
-  }
-  combine_kernel<<<dim3(a.n_chunks, F), dim3(256), lds, s>>>(a);
-  SK_HIP_TRY(hipGetLastError());
-  if (a.window >= 2) {
-    const int64_t total = (int64_t)a.hist_len + a.n_blocks;
-    const int new_len = (int)(total < a.hist_cap ? total : a.hist_cap);
-    if (new_len > 0) {
-      hist_update_kernel<<<dim3(new_len, F, ig), dim3(256), 0, s>>>(a, new_len);
+    const int n_old = a.hist_next_len - a.n_blocks;
+    if (n_old > 0) {
+      hist_copy_kernel<<<dim3(n_old, F, (a.n_inputs + 255) / 256), dim3(256), 0, s>>>(a, n_old);
       SK_HIP_TRY(hipGetLastError());
     }
   }
+  partial_kernel<V><<<dim3(a.n_chunks, F, (a.n_groups + 3) / 4), dim3(256), 0, s>>>(a);
+  SK_HIP_TRY(hipGetLastError());
+  const int64_t fb = (int64_t)F * a.n_blocks;
+  finalize_kernel<<<dim3((unsigned)((fb + 255) / 256)), dim3(256), 0, s>>>(a);
+  SK_HIP_TRY(hipGetLastError());
   return SK_OK;
+}
+
+int pass_b_vec(int32_t n_inputs) { return n_inputs % 4 == 0 ? 4 : 1; }
+
+int launch_pass_b(const PassBArgs& a, hipStream_t s) {
+  if (a.n_blocks <= 0) return SK_OK;
+  return a.vec == 4 ? launch_v<4>(a, s) : launch_v<1>(a, s);
 }
 
 __global__ __launch_bounds__(256) void flags_kernel(FlagArgs a) {

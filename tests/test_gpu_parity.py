@@ -26,12 +26,14 @@ def _say(msg):
     sys.stdout.flush()
 
 
-def run_gpu(x, M, L=1, est=0, k=5.0, delta=0.0, sigma_override=0.0, mask=None, lpr=0):
+def run_gpu(x, M, L=1, est=0, k=5.0, delta=0.0, sigma_override=0.0, mask=None, lpr=0, variant=0, grid=0):
     T, F, N = x.shape
     plan = sk.Plan(N, F, T, M, norm_window=L, estimator=est, k_sigma=k, expect_offset=delta,
                    sigma_override=sigma_override)
     if lpr:
         plan.set_pass_a_tile(lpr)
+    if variant or grid:
+        plan.set_pass_a_variant(variant, grid)
     xd = torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
     md = None if mask is None else torch.from_numpy(np.ascontiguousarray(mask)).to(DEV)
     out = plan.compute(xd, mask=md)
@@ -88,11 +90,24 @@ def test_ragged_random_bytes(shape, L):
 
 
 @pytest.mark.parametrize("lpr", [1, 2, 4, 8, 16, 32, 64, 128, 256])
-def test_every_pass_a_tile(lpr):
-    rng = np.random.default_rng(lpr)
-    T, F, N, M = 96, 3, 512, 48
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+def test_every_pass_a_tile(lpr, variant):
+    # M = 48 and M = 100 leave partial batches and odd row counts for every
+    # row-phase count.
+    rng = np.random.default_rng(lpr + 7 * variant)
+    for T, F, N, M in ((96, 3, 512, 48), (200, 2, 256, 100)):
+        x = rng.integers(0, 256, size=(T, F, N), dtype=np.uint8)
+        both(x, M, 2, what=f"tile lpr={lpr} variant={variant}", lpr=lpr, variant=variant)
+
+
+@pytest.mark.parametrize("grid", [1, 3, 7])
+def test_pass_a_persistent_grid(grid):
+    # Fewer workgroups than tasks: each loops over several (block, chunk) tasks.
+    rng = np.random.default_rng(grid)
+    T, F, N, M = 512, 2, 1024, 64
     x = rng.integers(0, 256, size=(T, F, N), dtype=np.uint8)
-    both(x, M, 2, what=f"tile lpr={lpr}", lpr=lpr)
+    for variant in (0, 1):
+        both(x, M, 3, what=f"grid={grid}", lpr=64, variant=variant, grid=grid)
 
 
 def test_unaligned_input_pointer():
