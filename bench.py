@@ -40,6 +40,10 @@ def parse():
     ap.add_argument("--lpr", type=int, default=0, help="force pass A lanes per row")
     ap.add_argument("--variant", type=int, default=-1, help="force pass A row batching variant (0..3)")
     ap.add_argument("--grid", type=int, default=0, help="force pass A workgroup count (persistent loop)")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--serving-frames", type=int, default=10000)
+    ap.add_argument("--serving-loads", default="0.3,0.6,0.9",
+                    help="offered loads as fractions of the measured saturated frame rate")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after timing, run one device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -98,6 +102,91 @@ def cpu_baseline(x, w, L, delta, sig, sample_blocks):
     return {"value": nbytes / dt / 1e9, "unit": "GB/s", "cores": 1, "kind": "oracle",
             "sample": f"first {sample_blocks} blocks of every channel ({nbytes} bytes, T={T}), "
                       f"whole path single-threaded, {dt:.1f} s"}
+
+
+def serving_bench(args, dev):
+    """Serving: Poisson frame arrivals from two arrays (N=256 and N=2048),
+    F=4, 49152 samples per frame, M=256, running normaliser over 2^16 samples.
+    Frames already sit in HBM when they arrive (device-resident arrival); a
+    short host-staged run (pinned host frames copied over PCIe) is reported
+    separately. Latency = completion observed - scheduled arrival."""
+    import numpy as np
+    import torch
+    import paper_1808_10365_amd as sk
+    import synth
+    arrays = []
+    for N, nfr in ((256, 8), (2048, 3)):
+        w = synth.serving_array(N)
+        frames = []
+        for k in range(nfr):
+            wk = synth.serving_array(N, frame=k)
+            frames.append(torch.from_numpy(synth.generate(wk)).to(dev))
+        delta, sig = sk.digitised_expectation(w.sigma, w.block_len)
+        arrays.append(dict(N=N, w=w, frames=frames, kw=dict(n_inputs=N, n_channels=w.n_channels,
+                      n_samples=w.n_samples, block_len=w.block_len, norm_window=w.norm_window,
+                      k_sigma=5.0, expect_offset=delta, sigma_override=sig)))
+    torch.cuda.synchronize()
+    frame_bytes = [a["w"].nbytes for a in arrays]
+
+    def run(rate_hz, n_frames, host=False, seed=5):
+        srv = sk.Server(hbm_budget_bytes=8 << 30, max_inflight=16, n_streams=4, queue_capacity=1 << 16)
+        ids = [srv.add_array(**a["kw"]) for a in arrays]
+        ring = 32
+        outs = [[srv.alloc_outputs(i, dev, want=("v", "flags", "n_eff", "r1", "r2")) for _ in range(ring)] for i in ids]
+        srcs = [[f.cpu().pin_memory() for f in a["frames"]] for a in arrays] if host else [a["frames"] for a in arrays]
+        rng = np.random.default_rng(seed)
+        which = rng.integers(0, 2, size=n_frames)
+        if rate_hz > 0:
+            gaps = rng.exponential(1.0 / rate_hz, size=n_frames)
+        else:
+            gaps = np.zeros(n_frames)
+        cnt = [0, 0]
+        tickets = []
+        t0 = srv.now() + 0.01
+        sched = t0 + np.cumsum(gaps)
+        for j in range(n_frames):
+            a = int(which[j])
+            while srv.now() < sched[j]:
+                pass
+            k = cnt[a]
+            cnt[a] += 1
+            t = None
+            while t is None:
+                t = srv.submit(ids[a], srcs[a][k % len(srcs[a])], outs[a][k % ring], tag=j)
+            tickets.append((j, a, t))
+        srv.drain()
+        lat, busy = [], srv.stats()
+        t_first, t_last = None, None
+        for j, a, t in tickets:
+            r = srv.poll(t)
+            assert r.status == 0
+            lat.append(r.t_done - sched[j])
+            t_last = r.t_done if t_last is None else max(t_last, r.t_done)
+        span = t_last - sched[0]
+        nbytes = sum(frame_bytes[a] for _, a, _ in tickets)
+        srv.close()
+        lat = np.array(lat) * 1e3
+        return {"offered_frames_per_s": round(rate_hz, 1) if rate_hz > 0 else "saturating burst",
+                "frames": n_frames, "p50_ms": round(float(np.percentile(lat, 50)), 4),
+                "p99_ms": round(float(np.percentile(lat, 99)), 4), "mean_ms": round(float(lat.mean()), 4),
+                "achieved_GBps": round(nbytes / span / 1e9, 1), "frames_per_s": round(n_frames / span, 1),
+                "peak_inflight": int(busy.peak_inflight)}
+
+    sat = run(0.0, min(2000, args.serving_frames))
+    cap = sat["frames_per_s"]
+    res = {"arrays": [{"n_inputs": a["N"], "n_channels": a["w"].n_channels, "frame_samples": a["w"].n_samples,
+                       "block_len": a["w"].block_len, "norm_window_blocks": a["w"].norm_window,
+                       "frame_bytes": a["w"].nbytes} for a in arrays],
+           "arrival": "Poisson, arrays chosen 50/50, frames resident in HBM on arrival",
+           "saturated": sat, "runs": []}
+    for load in [float(v) for v in args.serving_loads.split(",") if v]:
+        res["runs"].append(dict(load=load, **run(load * cap, args.serving_frames, seed=int(load * 100))))
+    # Host-staged arrival: frames in pinned host memory, copied over PCIe by the
+    # server. Its own saturated rate first, then half of it.
+    hsat = run(0.0, 200, host=True, seed=76)
+    res["host_staged"] = {"saturated": hsat,
+                          "run": dict(load=0.5, **run(0.5 * hsat["frames_per_s"], 500, host=True, seed=77))}
+    return res
 
 
 def main():
@@ -224,6 +313,11 @@ def main():
                      "algorithmic_bytes_per_launch": pass_a_bytes},
         "flagged_fraction": round(flagged, 5),
     }
+    if not args.no_serving:
+        print("# serving: Poisson arrivals from two arrays", file=sys.stderr, flush=True)
+        del xd
+        torch.cuda.empty_cache()
+        res["serving"] = serving_bench(args, dev)
     if not args.no_cpu_baseline:
         print("# timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(x, w, L, delta, sig, args.cpu_sample_blocks)

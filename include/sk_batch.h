@@ -1,0 +1,63 @@
+/*
+ * sk_batch.h - many independent spectral-kurtosis problems in one launch.
+ *
+ * Each problem is a full plan description (its own N, F, T, M, window,
+ * estimator and flag parameters, Sec. 2.2.1 and Sec. 3.2) with its own input,
+ * outputs and normaliser state. sk_batch_compute runs one call of every
+ * problem: pass A for all problems is one persistent kernel whose workgroups
+ * take (problem, block, column chunk) tasks from a device work queue, largest
+ * tasks first; pass B for all problems follows in a few more persistent
+ * kernels; the whole sequence is captured once into a HIP graph, so one call
+ * is one graph launch. Pass A's lanes per row are chosen per problem shape by
+ * the library's autotuner (timed trial launches on the device), cached in a
+ * JSON file keyed by (device arch, N, F, T, M).
+ *
+ * Requirements: every problem has N % 16 == 0 and a 16-byte aligned input.
+ * Errors as in sk.h.
+ */
+#ifndef SK_BATCH_H
+#define SK_BATCH_H
+
+#include <stdint.h>
+
+#include "sk.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sk_batch_s* sk_batch_t;
+
+typedef struct {
+  int32_t autotune;        /* 1: time candidate tiles on the device (cached); 0: heuristic */
+  int32_t use_graph;       /* 1: capture the launch sequence into a HIP graph */
+  const char* tune_cache;  /* JSON tuning cache path; NULL: env SK_TUNE_CACHE, or none */
+} sk_batch_opts;
+
+/* descs[j], d_inputs[j] ([T][F][N] device bytes) and outs[j] (device output
+ * pointers, any may be NULL) for j < n. Allocates per-problem scratch and
+ * state on the current device, tunes, and captures the graph on `stream`'s
+ * device. The inputs and outputs must stay valid while the batch is used. */
+int sk_batch_create(const sk_plan_desc* descs, int32_t n, const sk_batch_opts* opts,
+                    const uint8_t* const* d_inputs, const sk_outputs* outs, sk_batch_t* batch);
+
+/* One call of every problem, enqueued on `stream`. d_inputs may be NULL (use
+ * the pointers given at creation) or a new set of n input pointers of the
+ * same shapes; new pointers are written into the device problem table before
+ * the graph runs. */
+int sk_batch_compute(sk_batch_t batch, const uint8_t* const* d_inputs, void* stream);
+
+/* Forget every problem's normaliser history. Synchronises `stream`. */
+int sk_batch_state_reset(sk_batch_t batch, void* stream);
+
+/* Lanes per row chosen for problem j (after tuning) and the persistent
+ * workgroup count of pass A. */
+int sk_batch_get_tiles(sk_batch_t batch, int32_t j, int32_t* lanes_per_row, int32_t* pass_a_grid);
+
+int sk_batch_destroy(sk_batch_t batch);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SK_BATCH_H */

@@ -24,7 +24,8 @@ from typing import Optional
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "liboracle_sk.so")
+# A test may point the oracle at a deliberately broken build (mutation test).
+_LIB_PATH = os.environ.get("SK_ORACLE_LIB") or os.path.join(_HERE, "liboracle_sk.so")
 _lib = None
 
 EST_HAT, EST_TILDE = 0, 1

@@ -47,6 +47,25 @@ class Outputs(ctypes.Structure):
                 ("n_eff", ctypes.c_void_p)]
 
 
+class ServerDesc(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_inflight", ctypes.c_int32),
+                ("n_streams", ctypes.c_int32), ("queue_capacity", ctypes.c_int32)]
+
+
+class ServerResult(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64), ("array_id", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("rejected_full", ctypes.c_uint64),
+                ("peak_inflight", ctypes.c_int32), ("peak_bytes", ctypes.c_size_t), ("busy_seconds", ctypes.c_double)]
+
+
+class BatchOpts(ctypes.Structure):
+    _fields_ = [("autotune", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("tune_cache", ctypes.c_char_p)]
+
+
 _lib = None
 
 
@@ -75,6 +94,24 @@ def load_library():
     lib.sk_plan_set_pass_a_variant.argtypes = [VP, I32, I32]
     lib.sk_profile_enable.argtypes = [VP, I32]
     lib.sk_profile_read.argtypes = [VP, VP, VP, I32, ctypes.POINTER(I32)]
+    lib.sk_batch_create.argtypes = [ctypes.POINTER(PlanDesc), I32, ctypes.POINTER(BatchOpts), VP, ctypes.POINTER(Outputs), ctypes.POINTER(VP)]
+    lib.sk_batch_compute.argtypes = [VP, VP, VP]
+    lib.sk_batch_state_reset.argtypes = [VP, VP]
+    lib.sk_batch_get_tiles.argtypes = [VP, I32, ctypes.POINTER(I32), ctypes.POINTER(I32)]
+    lib.sk_batch_destroy.argtypes = [VP]
+    lib.sk_server_now.restype = ctypes.c_double
+    lib.sk_server_create.argtypes = [ctypes.POINTER(ServerDesc), ctypes.POINTER(VP)]
+    lib.sk_server_add_array.argtypes = [VP, ctypes.POINTER(PlanDesc), ctypes.POINTER(I32)]
+    lib.sk_stream_submit.argtypes = [VP, I32, VP, I32, ctypes.POINTER(Outputs), ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)]
+    lib.sk_stream_poll.argtypes = [VP, ctypes.c_uint64, ctypes.POINTER(ServerResult)]
+    lib.sk_server_drain.argtypes = [VP]
+    lib.sk_server_get_stats.argtypes = [VP, ctypes.POINTER(ServerStats)]
+    lib.sk_server_destroy.argtypes = [VP]
+    for name in ("sk_server_create", "sk_server_add_array", "sk_stream_submit", "sk_stream_poll",
+                 "sk_server_drain", "sk_server_get_stats", "sk_server_destroy"):
+        getattr(lib, name).restype = ctypes.c_int
+    for name in ("sk_batch_create", "sk_batch_compute", "sk_batch_state_reset", "sk_batch_get_tiles", "sk_batch_destroy"):
+        getattr(lib, name).restype = ctypes.c_int
     for name in ("sk_plan_create", "sk_plan_destroy", "sk_plan_device_bytes", "sk_compute", "sk_flags",
                  "sk_state_reset", "sk_state_size", "sk_state_export", "sk_state_import",
                  "sk_digitised_expectation", "sk_plan_set_pass_a_tile", "sk_plan_get_pass_a_tile",
@@ -213,6 +250,148 @@ class Plan:
     def import_state(self, blob: bytes, stream: Optional[torch.cuda.Stream] = None):
         buf = ctypes.create_string_buffer(blob, len(blob))
         _check(self._lib.sk_state_import(self.handle, buf, len(blob), _stream_handle(stream)))
+
+
+class Batch:
+    """Many independent problems in one graph launch per call (``sk_batch_t``).
+
+    ``plans`` is a list of dicts with the Plan keyword arguments; ``inputs`` the
+    device tensors [T][F][N]; outputs are allocated here (all kinds)."""
+
+    def __init__(self, plans, inputs, autotune: bool = True, use_graph: bool = True,
+                 tune_cache: Optional[str] = None):
+        self._lib = load_library()
+        n = len(plans)
+        self.descs = (PlanDesc * n)()
+        self.outputs = []
+        outs = (Outputs * n)()
+        for j, (kw, x) in enumerate(zip(plans, inputs)):
+            d = PlanDesc(kw["n_inputs"], kw["n_channels"], kw["n_samples"], kw["block_len"],
+                         kw.get("norm_window", 1), kw.get("estimator", EST_HAT), kw.get("k_sigma", 5.0),
+                         kw.get("expect_offset", 0.0), kw.get("sigma_override", 0.0))
+            self.descs[j] = d
+            T, F, N, M = d.n_samples, d.n_channels, d.n_inputs, d.block_len
+            if x.dtype != torch.uint8 or tuple(x.shape) != (T, F, N) or not x.is_contiguous():
+                raise ValueError(f"input {j} must be a contiguous uint8 tensor of shape {(T, F, N)}")
+            B = T // M
+            r = Result(torch.empty((F, B, N), dtype=torch.int32, device=x.device),
+                       torch.empty((F, B, N), dtype=torch.int32, device=x.device),
+                       torch.empty((F, B), dtype=torch.int64, device=x.device),
+                       torch.empty((F, B), dtype=torch.int64, device=x.device),
+                       torch.empty((F, B), dtype=torch.float32, device=x.device),
+                       torch.empty((F, B), dtype=torch.uint8, device=x.device),
+                       torch.empty((F, B), dtype=torch.int32, device=x.device))
+            self.outputs.append(r)
+            outs[j] = Outputs(*[_ptr(getattr(r, k)) for k in ALL_OUTPUTS])
+        self._inputs = list(inputs)
+        ptrs = (ctypes.c_void_p * n)(*[x.data_ptr() for x in inputs])
+        opts = BatchOpts(int(autotune), int(use_graph), tune_cache.encode() if tune_cache else None)
+        h = ctypes.c_void_p()
+        _check(self._lib.sk_batch_create(self.descs, n, ctypes.byref(opts), ptrs, outs, ctypes.byref(h)))
+        self.handle = h
+        self.n = n
+
+    def compute(self, inputs=None, stream: Optional[torch.cuda.Stream] = None):
+        ptrs = None
+        if inputs is not None:
+            self._inputs = list(inputs)
+            ptrs = (ctypes.c_void_p * self.n)(*[x.data_ptr() for x in inputs])
+        _check(self._lib.sk_batch_compute(self.handle, ptrs, _stream_handle(stream)))
+        return self.outputs
+
+    def reset(self, stream: Optional[torch.cuda.Stream] = None):
+        _check(self._lib.sk_batch_state_reset(self.handle, _stream_handle(stream)))
+
+    def tiles(self, j: int):
+        lpr, grid = ctypes.c_int32(), ctypes.c_int32()
+        _check(self._lib.sk_batch_get_tiles(self.handle, j, ctypes.byref(lpr), ctypes.byref(grid)))
+        return lpr.value, grid.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _check(self._lib.sk_batch_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching server (``sk_server_t``): arrays submit frames as they arrive."""
+
+    def __init__(self, hbm_budget_bytes: int, max_inflight: int = 8, n_streams: int = 4, queue_capacity: int = 1024):
+        self._lib = load_library()
+        d = ServerDesc(int(hbm_budget_bytes), int(max_inflight), int(n_streams), int(queue_capacity))
+        h = ctypes.c_void_p()
+        _check(self._lib.sk_server_create(ctypes.byref(d), ctypes.byref(h)))
+        self.handle = h
+        self.arrays = []
+        self._keep = {}
+
+    def add_array(self, **kw) -> int:
+        d = PlanDesc(kw["n_inputs"], kw["n_channels"], kw["n_samples"], kw["block_len"], kw.get("norm_window", 1),
+                     kw.get("estimator", EST_HAT), kw.get("k_sigma", 5.0), kw.get("expect_offset", 0.0),
+                     kw.get("sigma_override", 0.0))
+        aid = ctypes.c_int32()
+        _check(self._lib.sk_server_add_array(self.handle, ctypes.byref(d), ctypes.byref(aid)))
+        self.arrays.append(d)
+        return aid.value
+
+    def alloc_outputs(self, array_id: int, device, want: Sequence[str] = ALL_OUTPUTS) -> Result:
+        d = self.arrays[array_id]
+        F, N, B = d.n_channels, d.n_inputs, d.n_samples // d.block_len
+        shapes = {"s1": ((F, B, N), torch.int32), "s2": ((F, B, N), torch.int32), "r1": ((F, B), torch.int64),
+                  "r2": ((F, B), torch.int64), "v": ((F, B), torch.float32), "flags": ((F, B), torch.uint8),
+                  "n_eff": ((F, B), torch.int32)}
+        return Result(**{k: (torch.empty(shapes[k][0], dtype=shapes[k][1], device=device) if k in want else None)
+                         for k in ALL_OUTPUTS})
+
+    def submit(self, array_id: int, frame: torch.Tensor, out: Result, tag: int = 0) -> Optional[int]:
+        """Returns the ticket, or None when the queue is full."""
+        o = Outputs(*[_ptr(getattr(out, k)) for k in ALL_OUTPUTS])
+        t = ctypes.c_uint64()
+        rc = self._lib.sk_stream_submit(self.handle, array_id, ctypes.c_void_p(frame.data_ptr()),
+                                        0 if frame.is_cuda else 1, ctypes.byref(o), tag, ctypes.byref(t))
+        if rc == SK_ERR_AGAIN:
+            return None
+        _check(rc)
+        self._keep[t.value] = (frame, out)
+        return t.value
+
+    def poll(self, ticket: int) -> Optional[ServerResult]:
+        r = ServerResult()
+        rc = self._lib.sk_stream_poll(self.handle, ticket, ctypes.byref(r))
+        if rc == SK_ERR_AGAIN:
+            return None
+        _check(rc)
+        self._keep.pop(ticket, None)
+        return r
+
+    def drain(self):
+        _check(self._lib.sk_server_drain(self.handle))
+
+    def stats(self) -> ServerStats:
+        st = ServerStats()
+        _check(self._lib.sk_server_get_stats(self.handle, ctypes.byref(st)))
+        return st
+
+    def now(self) -> float:
+        return self._lib.sk_server_now()
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _check(self._lib.sk_server_destroy(self.handle))
+            self.handle = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def build(verbose: bool = False) -> str:

@@ -66,7 +66,8 @@ struct StateHeader {
   int32_t n_inputs, n_channels, block_len, window, hist_len, pad;
 };
 
-static int validate(const sk_plan_desc* d) {
+namespace sk {
+int validate_desc(const sk_plan_desc* d) {
   if (!d) { set_error("desc is NULL"); return SK_ERR_INVALID_ARG; }
   if (d->n_inputs < 1 || d->n_inputs > 16384) { set_error("n_inputs %d outside [1, 16384]", d->n_inputs); return SK_ERR_SHAPE; }
   if (d->n_channels < 1) { set_error("n_channels %d < 1", d->n_channels); return SK_ERR_SHAPE; }
@@ -80,6 +81,7 @@ static int validate(const sk_plan_desc* d) {
   if (cells < 0 || (double)d->n_channels * (double)d->n_samples * (double)d->n_inputs > 9.0e18) { set_error("input too large"); return SK_ERR_SHAPE; }
   return SK_OK;
 }
+}  // namespace sk
 
 static int32_t pow2_floor(int64_t v) {
   int32_t r = 1;
@@ -132,7 +134,7 @@ int sk_plan_create(const sk_plan_desc* desc, sk_plan_t* out) {
   clear_error();
   if (!out) { set_error("out is NULL"); return SK_ERR_INVALID_ARG; }
   *out = nullptr;
-  int rc = validate(desc);
+  int rc = validate_desc(desc);
   if (rc) return rc;
   sk_plan_s* p = new (std::nothrow) sk_plan_s();
   if (!p) { set_error("host allocation failed"); return SK_ERR_NOMEM; }

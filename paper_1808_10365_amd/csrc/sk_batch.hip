@@ -1,0 +1,643 @@
+// Batched form: many independent problems per launch (persistent kernels,
+// device work queue, HIP graph) and the pass A tile autotuner.
+#include <hip/hip_runtime.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "sk_batch.h"
+#include "sk_internal.h"
+#include "sk_pass_a_dev.h"
+#include "sk_pass_b_dev.h"
+
+namespace sk {
+
+int validate_desc(const sk_plan_desc* d);
+
+// One problem as the batched kernels see it (device table entry).
+struct BatchProb {
+  PassATask a;                 // pass A task geometry (x, s1, s2, shapes, chunks, n_tasks)
+  int32_t lpr;                 // pass A lanes per row
+  int32_t window, hist_cap, chunk, n_chunks_max, n_groups, estimator, pad;
+  double k_sigma, expect_offset, sigma_override;
+  int32_t* hist[2];
+  int32_t* chunk_sum;
+  double* part_a;
+  double* part_q;
+  int64_t* part_r1;
+  int64_t* part_r2;
+  int32_t* part_n;
+  const uint8_t* mask;
+  int64_t* r1;
+  int64_t* r2;
+  float* v;
+  uint8_t* flags;
+  int32_t* n_eff;
+  // Task ranges of each kernel over the whole batch.
+  int64_t a_begin, cs_begin, cs_count, hc_begin, hc_count, pt_begin, pt_count, fn_begin, fn_count;
+};
+
+// Per-problem normaliser state kept on the device between calls.
+struct BatchState {
+  int32_t hist_len;
+  int32_t parity;
+};
+
+__device__ __forceinline__ PassBArgs make_args(const BatchProb& P, const BatchState& S) {
+  PassBArgs a;
+  a.s1 = P.a.s1;
+  a.s2 = P.a.s2;
+  a.hist = P.hist[S.parity];
+  a.hist_next = P.hist[S.parity ^ 1];
+  a.chunk_sum = P.chunk_sum;
+  a.part_a = P.part_a;
+  a.part_q = P.part_q;
+  a.part_r1 = P.part_r1;
+  a.part_r2 = P.part_r2;
+  a.part_n = P.part_n;
+  a.mask = P.mask;
+  a.r1 = P.r1;
+  a.r2 = P.r2;
+  a.v = P.v;
+  a.flags = P.flags;
+  a.n_eff = P.n_eff;
+  a.n_inputs = P.a.n_inputs;
+  a.n_channels = (int32_t)(P.a.row_bytes / P.a.n_inputs);
+  a.n_blocks = P.a.n_blocks;
+  a.block_len = P.a.block_len;
+  a.window = P.window;
+  a.hist_len = S.hist_len;
+  a.hist_cap = P.hist_cap;
+  const int64_t total = (int64_t)S.hist_len + P.a.n_blocks;
+  a.hist_next_len = (int32_t)(total < P.hist_cap ? total : P.hist_cap);
+  a.chunk = P.chunk;
+  a.n_chunks = (int32_t)((total + P.chunk - 1) / P.chunk);
+  a.n_groups = P.n_groups;
+  a.vec = 4;
+  a.estimator = P.estimator;
+  a.k_sigma = P.k_sigma;
+  a.expect_offset = P.expect_offset;
+  a.sigma_override = P.sigma_override;
+  return a;
+}
+
+// Index of the last problem whose range starts at or before `task`.
+template <int64_t BatchProb::*BEGIN>
+__device__ __forceinline__ int find_prob(const BatchProb* probs, int n, int64_t task) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (probs[mid].*BEGIN <= task) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Pass A, one task, lanes per row known at run time.
+template <int U>
+__device__ void pass_a_task_rt(const PassATask& t, int lpr, int64_t task, const uint16_t* lut, uint32_t* red) {
+  constexpr int VEC = 16, W = 2 * VEC + 1;
+  const int tid = threadIdx.x;
+  const int rp = 256 / lpr;
+  const int lc = tid % lpr, ph = tid / lpr;
+  const int M = t.block_len;
+  const int64_t G = t.row_bytes;
+  const int b = (int)(task / t.chunks);
+  const int ch = (int)(task % t.chunks);
+  const int g = ch * lpr + lc;
+  uint32_t s1[VEC], s2[VEC];
+#pragma unroll
+  for (int k = 0; k < VEC; ++k) s1[k] = s2[k] = 0;
+  if (g < t.col_groups) sum_rows_rt<VEC, U>(t.x + (int64_t)b * M * G + (int64_t)g * VEC, G, M, ph, rp, lut, s1, s2);
+  const int N = t.n_inputs, B = t.n_blocks;
+  if (rp == 1) {
+    if (g < t.col_groups) {
+      const int64_t col = (int64_t)g * VEC;
+      const int64_t f = col / N, i = col % N;
+      int32_t* d1 = t.s1 + (f * B + b) * N + i;
+      int32_t* d2 = t.s2 + (f * B + b) * N + i;
+#pragma unroll
+      for (int k = 0; k < VEC; k += 4) {
+        u32x4 x1 = {s1[k], s1[k + 1], s1[k + 2], s1[k + 3]};
+        u32x4 x2 = {s2[k], s2[k + 1], s2[k + 2], s2[k + 3]};
+        *reinterpret_cast<u32x4*>(d1 + k) = x1;
+        *reinterpret_cast<u32x4*>(d2 + k) = x2;
+      }
+    }
+  } else {
+    uint32_t* mine = red + (ph * lpr + lc) * W;
+#pragma unroll
+    for (int k = 0; k < VEC; ++k) {
+      mine[k] = s1[k];
+      mine[VEC + k] = s2[k];
+    }
+    __syncthreads();
+    for (int o = tid; o < lpr * 2 * VEC; o += 256) {
+      const int l = o / (2 * VEC), k = o % (2 * VEC);
+      uint32_t s = 0;
+      for (int p = 0; p < rp; ++p) s += red[(p * lpr + l) * W + k];
+      const int gg = ch * lpr + l;
+      if (gg < t.col_groups) {
+        const int64_t col = (int64_t)gg * VEC + (k % VEC);
+        const int64_t f = col / N, i = col % N;
+        int32_t* dst = k < VEC ? t.s1 : t.s2;
+        dst[(f * B + b) * N + i] = (int32_t)s;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Persistent pass A over the whole batch: every workgroup takes tasks from
+// one device counter until the queue is empty (every wavefront then exits).
+__global__ __launch_bounds__(256) void batch_pass_a_kernel(const BatchProb* __restrict__ probs, int n,
+                                                           int64_t total, uint32_t* counter) {
+  __shared__ uint16_t lut[256];
+  __shared__ int64_t s_task;
+  extern __shared__ uint32_t red[];
+  const int tid = threadIdx.x;
+  lut[tid] = (uint16_t)code_power((uint32_t)tid);
+  for (;;) {
+    if (tid == 0) s_task = (int64_t)atomicAdd(counter, 1u);
+    __syncthreads();
+    const int64_t task = s_task;
+    __syncthreads();
+    if (task >= total) break;
+    const int p = find_prob<&BatchProb::a_begin>(probs, n, task);
+    const BatchProb& P = probs[p];
+    pass_a_task_rt<8>(P.a, P.lpr, task - P.a_begin, lut, red);
+  }
+}
+
+__global__ __launch_bounds__(256) void batch_chunk_sum_kernel(const BatchProb* __restrict__ probs,
+                                                              const BatchState* __restrict__ st, int n) {
+  const int64_t task = blockIdx.x;
+  const int p = find_prob<&BatchProb::cs_begin>(probs, n, task);
+  const BatchProb& P = probs[p];
+  const int64_t lt = task - P.cs_begin;
+  if (lt >= P.cs_count) return;
+  const PassBArgs a = make_args(P, st[p]);
+  const int c = (int)(lt % P.n_chunks_max);
+  const int64_t rest = lt / P.n_chunks_max;
+  const int f = (int)(rest % a.n_channels), z = (int)(rest / a.n_channels);
+  if (c >= a.n_chunks) return;
+  chunk_sum_body<4>(a, c, f, z);
+}
+
+__global__ __launch_bounds__(256) void batch_hist_copy_kernel(const BatchProb* __restrict__ probs,
+                                                              const BatchState* __restrict__ st, int n) {
+  const int64_t task = blockIdx.x;
+  const int p = find_prob<&BatchProb::hc_begin>(probs, n, task);
+  const BatchProb& P = probs[p];
+  const int64_t lt = task - P.hc_begin;
+  if (lt >= P.hc_count) return;
+  const PassBArgs a = make_args(P, st[p]);
+  const int zc = (a.n_inputs + 255) / 256;
+  const int z = (int)(lt % zc);
+  const int64_t rest = lt / zc;
+  const int f = (int)(rest % a.n_channels), j = (int)(rest / a.n_channels);
+  hist_copy_body(a, j, f, z);
+}
+
+__global__ __launch_bounds__(256) void batch_partial_kernel(const BatchProb* __restrict__ probs,
+                                                            const BatchState* __restrict__ st, int n) {
+  const int64_t task = blockIdx.x;
+  const int p = find_prob<&BatchProb::pt_begin>(probs, n, task);
+  const BatchProb& P = probs[p];
+  const int64_t lt = task - P.pt_begin;
+  if (lt >= P.pt_count) return;
+  const PassBArgs a = make_args(P, st[p]);
+  const int c = (int)(lt % P.n_chunks_max);
+  const int64_t rest = lt / P.n_chunks_max;
+  const int f = (int)(rest % a.n_channels), z = (int)(rest / a.n_channels);
+  if (c >= a.n_chunks) return;
+  partial_body<4>(a, c, f, z);
+}
+
+__global__ __launch_bounds__(256) void batch_finalize_kernel(const BatchProb* __restrict__ probs,
+                                                             const BatchState* __restrict__ st, int n) {
+  const int64_t task = blockIdx.x;
+  const int p = find_prob<&BatchProb::fn_begin>(probs, n, task);
+  const BatchProb& P = probs[p];
+  const int64_t lt = task - P.fn_begin;
+  if (lt >= P.fn_count) return;
+  finalize_body(make_args(P, st[p]), lt);
+}
+
+// Last node: advance every problem's history and rearm the work queue.
+__global__ __launch_bounds__(256) void batch_state_kernel(const BatchProb* __restrict__ probs,
+                                                          BatchState* st, int n, uint32_t* counter) {
+  for (int p = threadIdx.x; p < n; p += 256) {
+    if (probs[p].window >= 2) {
+      const int64_t total = (int64_t)st[p].hist_len + probs[p].a.n_blocks;
+      st[p].hist_len = (int32_t)(total < probs[p].hist_cap ? total : probs[p].hist_cap);
+      st[p].parity ^= 1;
+    }
+  }
+  if (threadIdx.x == 0) *counter = 0u;
+}
+
+}  // namespace sk
+
+using namespace sk;
+
+// ------------------------------------------------------------------ tuning cache
+
+namespace {
+
+std::string cache_path(const sk_batch_opts* o) {
+  if (o && o->tune_cache) return o->tune_cache;
+  const char* e = getenv("SK_TUNE_CACHE");
+  return e ? e : "";
+}
+
+// Flat JSON object of "key": integer pairs, one per line.
+std::map<std::string, int> load_cache(const std::string& path) {
+  std::map<std::string, int> m;
+  if (path.empty()) return m;
+  FILE* f = fopen(path.c_str(), "r");
+  if (!f) return m;
+  char line[512];
+  while (fgets(line, sizeof line, f)) {
+    char key[400];
+    int v;
+    if (sscanf(line, " \"%399[^\"]\" : %d", key, &v) == 2) m[key] = v;
+  }
+  fclose(f);
+  return m;
+}
+
+void save_cache(const std::string& path, const std::map<std::string, int>& m) {
+  if (path.empty()) return;
+  const std::string tmp = path + ".tmp";
+  FILE* f = fopen(tmp.c_str(), "w");
+  if (!f) return;
+  fprintf(f, "{\n");
+  size_t k = 0;
+  for (const auto& kv : m) fprintf(f, "  \"%s\": %d%s\n", kv.first.c_str(), kv.second, ++k < m.size() ? "," : "");
+  fprintf(f, "}\n");
+  fclose(f);
+  rename(tmp.c_str(), path.c_str());
+}
+
+}  // namespace
+
+struct sk_batch_s {
+  int n = 0;
+  int device = 0;
+  std::string arch;
+  std::vector<sk_plan_desc> desc;
+  std::vector<BatchProb> host;     // host copy of the table
+  std::vector<int> order;          // table position -> caller's problem index
+  BatchProb* d_probs = nullptr;
+  BatchState* d_state = nullptr;
+  uint32_t* d_counter = nullptr;
+  std::vector<void*> owned;
+  int64_t total_a = 0, total_cs = 0, total_hc = 0, total_pt = 0, total_fn = 0;
+  int grid_a = 0;
+  size_t lds_a = 0;
+  bool use_graph = false;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+static void batch_free(sk_batch_s* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  for (void* p : b->owned) (void)hipFree(p);
+  if (b->d_probs) (void)hipFree(b->d_probs);
+  if (b->d_state) (void)hipFree(b->d_state);
+  if (b->d_counter) (void)hipFree(b->d_counter);
+  delete b;
+}
+
+static int batch_alloc(sk_batch_s* b, void** p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) return SK_OK;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    set_error("hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    return SK_ERR_NOMEM;
+  }
+  b->owned.push_back(*p);
+  return SK_OK;
+}
+
+static int launch_sequence(sk_batch_s* b, hipStream_t s) {
+  batch_pass_a_kernel<<<dim3(b->grid_a), dim3(256), b->lds_a, s>>>(b->d_probs, b->n, b->total_a, b->d_counter);
+  SK_HIP_TRY(hipGetLastError());
+  if (b->total_cs > 0) {
+    batch_chunk_sum_kernel<<<dim3((unsigned)b->total_cs), dim3(256), 0, s>>>(b->d_probs, b->d_state, b->n);
+    SK_HIP_TRY(hipGetLastError());
+  }
+  if (b->total_hc > 0) {
+    batch_hist_copy_kernel<<<dim3((unsigned)b->total_hc), dim3(256), 0, s>>>(b->d_probs, b->d_state, b->n);
+    SK_HIP_TRY(hipGetLastError());
+  }
+  batch_partial_kernel<<<dim3((unsigned)b->total_pt), dim3(256), 0, s>>>(b->d_probs, b->d_state, b->n);
+  SK_HIP_TRY(hipGetLastError());
+  batch_finalize_kernel<<<dim3((unsigned)b->total_fn), dim3(256), 0, s>>>(b->d_probs, b->d_state, b->n);
+  SK_HIP_TRY(hipGetLastError());
+  batch_state_kernel<<<dim3(1), dim3(256), 0, s>>>(b->d_probs, b->d_state, b->n, b->d_counter);
+  SK_HIP_TRY(hipGetLastError());
+  return SK_OK;
+}
+
+// Time batched pass A on problem j alone for one lanes-per-row value.
+static float time_pass_a_alone(sk_batch_s* b, const BatchProb& prob, int lpr, hipStream_t s) {
+  BatchProb one = prob;
+  one.lpr = lpr;
+  one.a.chunks = (one.a.col_groups + lpr - 1) / lpr;
+  one.a.n_tasks = (int64_t)one.a.n_blocks * one.a.chunks;
+  one.a_begin = 0;
+  BatchProb* d_one = nullptr;
+  uint32_t* d_cnt = nullptr;
+  if (hipMalloc((void**)&d_one, sizeof one) != hipSuccess) return 1e30f;
+  if (hipMalloc((void**)&d_cnt, sizeof(uint32_t)) != hipSuccess) { (void)hipFree(d_one); return 1e30f; }
+  (void)hipMemcpyAsync(d_one, &one, sizeof one, hipMemcpyHostToDevice, s);
+  hipEvent_t e0, e1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  const int grid = (int)std::min<int64_t>(one.a.n_tasks, b->grid_a);
+  float best = 1e30f;
+  for (int rep = 0; rep < 4; ++rep) {
+    (void)hipMemsetAsync(d_cnt, 0, sizeof(uint32_t), s);
+    (void)hipEventRecord(e0, s);
+    batch_pass_a_kernel<<<dim3(grid), dim3(256), b->lds_a, s>>>(d_one, 1, one.a.n_tasks, d_cnt);
+    (void)hipEventRecord(e1, s);
+    (void)hipEventSynchronize(e1);
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (rep > 0) best = std::min(best, ms);   // first run warms up
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(d_one);
+  (void)hipFree(d_cnt);
+  return best;
+}
+
+extern "C" {
+
+int sk_batch_create(const sk_plan_desc* descs, int32_t n, const sk_batch_opts* opts,
+                    const uint8_t* const* d_inputs, const sk_outputs* outs, sk_batch_t* out) {
+  clear_error();
+  if (!out || !descs || !d_inputs || !outs || n < 1) { set_error("bad arguments"); return SK_ERR_INVALID_ARG; }
+  *out = nullptr;
+  for (int j = 0; j < n; ++j) {
+    int rc = validate_desc(&descs[j]);
+    if (rc) { std::string m = sk_last_error(); set_error("problem %d: %s", j, m.c_str()); return rc; }
+    if (descs[j].n_inputs % 16 != 0 || ((uintptr_t)d_inputs[j] % 16) != 0) {
+      set_error("problem %d: batched problems need N %% 16 == 0 and 16-byte aligned inputs", j);
+      return SK_ERR_SHAPE;
+    }
+  }
+  sk_batch_s* b = new sk_batch_s();
+  b->n = n;
+  b->desc.assign(descs, descs + n);
+  if (hipGetDevice(&b->device) != hipSuccess) { batch_free(b); set_error("no HIP device"); return SK_ERR_DEVICE; }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, b->device) != hipSuccess) { batch_free(b); set_error("device query failed"); return SK_ERR_DEVICE; }
+  b->arch = prop.gcnArchName;
+  b->lds_a = sizeof(uint32_t) * 256 * 33;
+  int occ = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, batch_pass_a_kernel, 256, b->lds_a) != hipSuccess || occ < 1) occ = 4;
+  b->grid_a = occ * prop.multiProcessorCount;
+  b->use_graph = !opts || opts->use_graph;
+
+  // Largest pass A tasks first (task cost ~ M rows x 4 KiB per lane group).
+  b->order.resize(n);
+  std::iota(b->order.begin(), b->order.end(), 0);
+  std::stable_sort(b->order.begin(), b->order.end(), [&](int x, int y) {
+    return (int64_t)descs[x].block_len * descs[x].n_inputs * descs[x].n_channels >
+           (int64_t)descs[y].block_len * descs[y].n_inputs * descs[y].n_channels;
+  });
+
+  b->host.resize(n);
+  int rc = SK_OK;
+  for (int q = 0; q < n && rc == SK_OK; ++q) {
+    const int j = b->order[q];
+    const sk_plan_desc& d = descs[j];
+    BatchProb& P = b->host[q];
+    memset(&P, 0, sizeof P);
+    const int64_t N = d.n_inputs, F = d.n_channels, B = d.n_samples / d.block_len;
+    const int L = d.norm_window_blocks;
+    P.a.x = d_inputs[j];
+    P.a.row_bytes = F * N;
+    P.a.n_inputs = (int32_t)N;
+    P.a.block_len = d.block_len;
+    P.a.n_blocks = (int32_t)B;
+    P.a.col_groups = (int32_t)(F * N / 16);
+    PassAConfig c = default_pass_a_config(16, F * N, B);
+    P.lpr = c.lpr;
+    P.window = L;
+    P.hist_cap = L >= 2 ? L - 1 : 0;
+    P.estimator = d.estimator;
+    P.k_sigma = d.k_sigma;
+    P.expect_offset = d.expect_offset;
+    P.sigma_override = d.sigma_override;
+    const int64_t seq = P.hist_cap + B;
+    int32_t R = 1, Rmin = 1;
+    if (L >= 2) {
+      while (R < 64 && (int64_t)R * R * 2 < L) R *= 2;
+      while (Rmin < R && (int64_t)Rmin * Rmin * 8 < L) Rmin *= 2;
+    } else {
+      R = 16;
+    }
+    while (R > Rmin && ((seq + R - 1) / R) * F * ((N + 255) / 256) < 512) R /= 2;
+    P.chunk = R;
+    P.n_chunks_max = (int32_t)((seq + R - 1) / R);
+    P.n_groups = (int32_t)((N + 255) / 256);
+    P.mask = nullptr;
+    const sk_outputs& o = outs[j];
+    const size_t fbn = (size_t)F * B * N;
+    void* p = nullptr;
+    if (o.s1) P.a.s1 = o.s1; else { rc = batch_alloc(b, &p, fbn * 4); P.a.s1 = (int32_t*)p; }
+    if (rc) break;
+    if (o.s2) P.a.s2 = o.s2; else { rc = batch_alloc(b, &p, fbn * 4); P.a.s2 = (int32_t*)p; }
+    if (rc) break;
+    if (((uintptr_t)P.a.s1 | (uintptr_t)P.a.s2) % 16) { set_error("problem %d: outputs s1/s2 must be 16-byte aligned", j); rc = SK_ERR_INVALID_ARG; break; }
+    const size_t fgb = (size_t)F * P.n_groups * B;
+    if ((rc = batch_alloc(b, &p, fgb * 8))) break;
+    P.part_a = (double*)p;
+    if ((rc = batch_alloc(b, &p, fgb * 8))) break;
+    P.part_q = (double*)p;
+    if ((rc = batch_alloc(b, &p, fgb * 8))) break;
+    P.part_r1 = (int64_t*)p;
+    if ((rc = batch_alloc(b, &p, fgb * 8))) break;
+    P.part_r2 = (int64_t*)p;
+    if ((rc = batch_alloc(b, &p, fgb * 4))) break;
+    P.part_n = (int32_t*)p;
+    if (L >= 2) {
+      if ((rc = batch_alloc(b, &p, (size_t)F * P.n_chunks_max * N * 4))) break;
+      P.chunk_sum = (int32_t*)p;
+      if ((rc = batch_alloc(b, &p, (size_t)F * P.hist_cap * N * 4))) break;
+      P.hist[0] = (int32_t*)p;
+      if ((rc = batch_alloc(b, &p, (size_t)F * P.hist_cap * N * 4))) break;
+      P.hist[1] = (int32_t*)p;
+    }
+    P.r1 = o.r1;
+    P.r2 = o.r2;
+    P.v = o.v;
+    P.flags = o.flags;
+    P.n_eff = o.n_eff;
+  }
+  if (rc) { batch_free(b); return rc; }
+
+  hipStream_t s = nullptr;
+  if (hipStreamCreate(&b->cap_stream) != hipSuccess) { batch_free(b); set_error("stream create failed"); return SK_ERR_DEVICE; }
+  s = b->cap_stream;
+
+  // Autotune pass A lanes per row per problem shape (cached).
+  const bool tune = !opts || opts->autotune;
+  const std::string path = cache_path(opts);
+  std::map<std::string, int> cache = load_cache(path);
+  bool cache_dirty = false;
+  if (tune) {
+    std::map<std::string, int> seen;
+    for (int q = 0; q < n; ++q) {
+      BatchProb& P = b->host[q];
+      const sk_plan_desc& d = b->desc[b->order[q]];
+      char key[256];
+      snprintf(key, sizeof key, "%s|pass_a_batch|N=%d|F=%d|T=%lld|M=%d", b->arch.c_str(), d.n_inputs,
+               d.n_channels, (long long)d.n_samples, d.block_len);
+      auto it = cache.find(key);
+      if (it != cache.end()) { P.lpr = it->second; continue; }
+      auto sn = seen.find(key);
+      if (sn != seen.end()) { P.lpr = sn->second; continue; }
+      int best_lpr = P.lpr;
+      float best = 1e30f;
+      for (int lpr : {32, 64, 128, 256}) {
+        if (lpr > 2 * P.a.col_groups && lpr != 32) continue;
+        const float ms = time_pass_a_alone(b, P, lpr, s);
+        if (ms < best) { best = ms; best_lpr = lpr; }
+      }
+      P.lpr = best_lpr;
+      seen[key] = best_lpr;
+      cache[key] = best_lpr;
+      cache_dirty = true;
+    }
+  }
+  if (cache_dirty) save_cache(path, cache);
+
+  // Task ranges.
+  int64_t ta = 0, tcs = 0, thc = 0, tpt = 0, tfn = 0;
+  for (int q = 0; q < n; ++q) {
+    BatchProb& P = b->host[q];
+    const int64_t F = P.a.row_bytes / P.a.n_inputs;
+    P.a.chunks = (P.a.col_groups + P.lpr - 1) / P.lpr;
+    P.a.n_tasks = (int64_t)P.a.n_blocks * P.a.chunks;
+    P.a_begin = ta;
+    ta += P.a.n_tasks;
+    const int zc = (P.a.n_inputs + 1023) / 1024;
+    P.cs_begin = tcs;
+    P.cs_count = P.window >= 2 ? (int64_t)P.n_chunks_max * F * zc : 0;
+    tcs += P.cs_count;
+    P.hc_begin = thc;
+    P.hc_count = (P.window >= 2 && P.a.n_blocks < P.hist_cap)
+                     ? (int64_t)(P.hist_cap - P.a.n_blocks) * F * ((P.a.n_inputs + 255) / 256) : 0;
+    thc += P.hc_count;
+    P.pt_begin = tpt;
+    P.pt_count = (int64_t)P.n_chunks_max * F * ((P.n_groups + 3) / 4);
+    tpt += P.pt_count;
+    P.fn_begin = tfn;
+    P.fn_count = (F * P.a.n_blocks + 255) / 256;
+    tfn += P.fn_count;
+  }
+  if (ta >= (int64_t)UINT32_MAX || tcs >= (1LL << 31) || tpt >= (1LL << 31) || tfn >= (1LL << 31) || thc >= (1LL << 31)) {
+    batch_free(b);
+    set_error("batch too large");
+    return SK_ERR_SHAPE;
+  }
+  b->total_a = ta;
+  b->total_cs = tcs;
+  b->total_hc = thc;
+  b->total_pt = tpt;
+  b->total_fn = tfn;
+
+  void* p = nullptr;
+  if ((rc = batch_alloc(b, &p, sizeof(BatchProb) * n))) { batch_free(b); return rc; }
+  b->owned.pop_back();
+  b->d_probs = (BatchProb*)p;
+  if ((rc = batch_alloc(b, &p, sizeof(BatchState) * n))) { batch_free(b); return rc; }
+  b->owned.pop_back();
+  b->d_state = (BatchState*)p;
+  if ((rc = batch_alloc(b, &p, sizeof(uint32_t)))) { batch_free(b); return rc; }
+  b->owned.pop_back();
+  b->d_counter = (uint32_t*)p;
+  std::vector<BatchState> st(n, BatchState{0, 0});
+  if (hipMemcpyAsync(b->d_probs, b->host.data(), sizeof(BatchProb) * n, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(b->d_state, st.data(), sizeof(BatchState) * n, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemsetAsync(b->d_counter, 0, sizeof(uint32_t), s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
+    batch_free(b);
+    set_error("batch table upload failed");
+    return SK_ERR_DEVICE;
+  }
+
+  if (b->use_graph) {
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) { batch_free(b); set_error("graph capture failed"); return SK_ERR_DEVICE; }
+    rc = launch_sequence(b, s);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(s, &g);
+    if (rc || e != hipSuccess) { if (g) (void)hipGraphDestroy(g); batch_free(b); if (!rc) set_error("graph capture failed"); return rc ? rc : SK_ERR_DEVICE; }
+    b->graph = g;
+    if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess) { batch_free(b); set_error("graph instantiate failed"); return SK_ERR_DEVICE; }
+  }
+  *out = b;
+  return SK_OK;
+}
+
+int sk_batch_compute(sk_batch_t b, const uint8_t* const* d_inputs, void* stream) {
+  clear_error();
+  if (!b) { set_error("NULL batch"); return SK_ERR_INVALID_ARG; }
+  hipStream_t s = (hipStream_t)stream;
+  if (d_inputs) {
+    bool changed = false;
+    for (int q = 0; q < b->n; ++q) {
+      const uint8_t* x = d_inputs[b->order[q]];
+      if (!x || (uintptr_t)x % 16) { set_error("input %d is NULL or not 16-byte aligned", b->order[q]); return SK_ERR_INVALID_ARG; }
+      if (x != b->host[q].a.x) { b->host[q].a.x = x; changed = true; }
+    }
+    if (changed) SK_HIP_TRY(hipMemcpyAsync(b->d_probs, b->host.data(), sizeof(BatchProb) * b->n, hipMemcpyHostToDevice, s));
+  }
+  if (b->exec) {
+    SK_HIP_TRY(hipGraphLaunch(b->exec, s));
+    return SK_OK;
+  }
+  return launch_sequence(b, s);
+}
+
+int sk_batch_state_reset(sk_batch_t b, void* stream) {
+  clear_error();
+  if (!b) { set_error("NULL batch"); return SK_ERR_INVALID_ARG; }
+  std::vector<BatchState> st(b->n, BatchState{0, 0});
+  hipStream_t s = (hipStream_t)stream;
+  SK_HIP_TRY(hipMemcpyAsync(b->d_state, st.data(), sizeof(BatchState) * b->n, hipMemcpyHostToDevice, s));
+  SK_HIP_TRY(hipStreamSynchronize(s));
+  return SK_OK;
+}
+
+int sk_batch_get_tiles(sk_batch_t b, int32_t j, int32_t* lpr, int32_t* grid) {
+  if (!b || j < 0 || j >= b->n || !lpr || !grid) { set_error("bad arguments"); return SK_ERR_INVALID_ARG; }
+  for (int q = 0; q < b->n; ++q)
+    if (b->order[q] == j) *lpr = b->host[q].lpr;
+  *grid = b->grid_a;
+  return SK_OK;
+}
+
+int sk_batch_destroy(sk_batch_t b) {
+  clear_error();
+  if (!b) return SK_OK;
+  (void)hipDeviceSynchronize();
+  batch_free(b);
+  return SK_OK;
+}
+
+}  // extern "C"

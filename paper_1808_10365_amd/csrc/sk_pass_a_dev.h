@@ -1,0 +1,141 @@
+// Pass A device code shared by the single-plan and batched kernels:
+// decode, power table, and the per-lane row walk (Eq. singlesums).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sk {
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+// Power of one offset-encoded byte: high nibble = Re + 8, low = Im + 8.
+__device__ __forceinline__ uint32_t code_power(uint32_t c) {
+  const int re = (int)(c >> 4) - 8;
+  const int im = (int)(c & 15u) - 8;
+  return (uint32_t)(re * re + im * im);
+}
+
+template <int VEC>
+struct Row {
+  static constexpr int DW = VEC >= 4 ? VEC / 4 : 1;
+  uint32_t w[DW];
+  __device__ __forceinline__ void load(const uint8_t* p) {
+    if constexpr (VEC == 16) {
+      const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p));
+      w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
+    } else if constexpr (VEC == 4) {
+      w[0] = __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(p));
+    } else {
+      w[0] = *p;
+    }
+  }
+  __device__ __forceinline__ uint32_t byte(int k) const {
+    return (w[k >> 2] >> (8 * (k & 3))) & 0xFFu;
+  }
+};
+
+template <int VEC>
+__device__ __forceinline__ void accumulate_pair(const Row<VEC>& r0, const Row<VEC>& r1,
+                                                const uint16_t* lut, uint32_t* s1, uint32_t* s2) {
+  const u16x2 ones = {1, 1};
+#pragma unroll
+  for (int k = 0; k < VEC; ++k) {
+    const uint32_t pp = (uint32_t)lut[r0.byte(k)] | ((uint32_t)lut[r1.byte(k)] << 16);
+    const u16x2 P = __builtin_bit_cast(u16x2, pp);
+    s2[k] = __builtin_amdgcn_udot2(P, P, s2[k], false);
+    s1[k] = __builtin_amdgcn_udot2(P, ones, s1[k], false);
+  }
+}
+
+template <int VEC>
+__device__ __forceinline__ void accumulate_one(const Row<VEC>& r0, const uint16_t* lut,
+                                               uint32_t* s1, uint32_t* s2) {
+#pragma unroll
+  for (int k = 0; k < VEC; ++k) {
+    const uint32_t p = lut[r0.byte(k)];
+    s1[k] += p;
+    s2[k] += p * p;
+  }
+}
+
+// Rows of this lane in batches of U: r = ph, ph + RP, ... (< M). With PF the
+// loads of the next batch are issued before the current batch is reduced, so
+// each wavefront keeps a batch of rows in flight while it computes.
+template <int VEC, int RP, int U, bool PF>
+__device__ __forceinline__ void sum_rows(const uint8_t* base, int64_t G, int M, int ph,
+                                         const uint16_t* lut, uint32_t* s1, uint32_t* s2) {
+  const int nrow = ph < M ? (M - ph + RP - 1) / RP : 0;
+  const int nb = nrow / U;
+  int r = ph;
+  if constexpr (PF) {
+    Row<VEC> cur[U], nxt[U];
+    if (nb > 0) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) cur[u].load(base + (int64_t)(r + u * RP) * G);
+    }
+    for (int bt = 0; bt < nb; ++bt) {
+      if (bt + 1 < nb) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) nxt[u].load(base + (int64_t)(r + (U + u) * RP) * G);
+      }
+#pragma unroll
+      for (int u = 0; u < U / 2; ++u) accumulate_pair<VEC>(cur[2 * u], cur[2 * u + 1], lut, s1, s2);
+#pragma unroll
+      for (int u = 0; u < U; ++u) cur[u] = nxt[u];
+      r += U * RP;
+    }
+  } else {
+    for (int bt = 0; bt < nb; ++bt) {
+      Row<VEC> q[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) q[u].load(base + (int64_t)(r + u * RP) * G);
+#pragma unroll
+      for (int u = 0; u < U / 2; ++u) accumulate_pair<VEC>(q[2 * u], q[2 * u + 1], lut, s1, s2);
+      r += U * RP;
+    }
+  }
+  for (; r + RP < M; r += 2 * RP) {
+    Row<VEC> q0, q1;
+    q0.load(base + (int64_t)r * G);
+    q1.load(base + (int64_t)(r + RP) * G);
+    accumulate_pair<VEC>(q0, q1, lut, s1, s2);
+  }
+  if (r < M) {
+    Row<VEC> q0;
+    q0.load(base + (int64_t)r * G);
+    accumulate_one<VEC>(q0, lut, s1, s2);
+  }
+}
+
+
+// The same row walk with the row-phase count known only at run time.
+template <int VEC, int U>
+__device__ __forceinline__ void sum_rows_rt(const uint8_t* base, int64_t G, int M, int ph, int rp,
+                                            const uint16_t* lut, uint32_t* s1, uint32_t* s2) {
+  const int nrow = ph < M ? (M - ph + rp - 1) / rp : 0;
+  const int nb = nrow / U;
+  int r = ph;
+  for (int bt = 0; bt < nb; ++bt) {
+    Row<VEC> q[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) q[u].load(base + (int64_t)(r + u * rp) * G);
+#pragma unroll
+    for (int u = 0; u < U / 2; ++u) accumulate_pair<VEC>(q[2 * u], q[2 * u + 1], lut, s1, s2);
+    r += U * rp;
+  }
+  for (; r + rp < M; r += 2 * rp) {
+    Row<VEC> q0, q1;
+    q0.load(base + (int64_t)r * G);
+    q1.load(base + (int64_t)(r + rp) * G);
+    accumulate_pair<VEC>(q0, q1, lut, s1, s2);
+  }
+  if (r < M) {
+    Row<VEC> q0;
+    q0.load(base + (int64_t)r * G);
+    accumulate_one<VEC>(q0, lut, s1, s2);
+  }
+}
+
+}  // namespace sk

@@ -1,0 +1,298 @@
+// Pass B device code shared by the single-plan and batched kernels:
+// window sums, array combine, estimator and flags (Eq. discreteMean,
+// normedSum1/2, avgSK, final; Sec. 3.2).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "sk_internal.h"
+
+namespace sk {
+
+template <int V>
+struct IVec;
+template <>
+struct IVec<1> {
+  int32_t v[1];
+  __device__ __forceinline__ void load(const int32_t* p) { v[0] = *p; }
+  __device__ __forceinline__ void store(int32_t* p) const { *p = v[0]; }
+};
+template <>
+struct IVec<4> {
+  int32_t v[4];
+  __device__ __forceinline__ void load(const int32_t* p) {
+    const int4 q = *reinterpret_cast<const int4*>(p);
+    v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+  }
+  __device__ __forceinline__ void store(int32_t* p) const {
+    *reinterpret_cast<int4*>(p) = make_int4(v[0], v[1], v[2], v[3]);
+  }
+};
+
+// Row of S1 for sequence position e (history or this call), channel f.
+__device__ __forceinline__ const int32_t* seq_row(const PassBArgs& a, int f, int64_t e) {
+  if (e < a.hist_len) return a.hist + ((int64_t)f * a.hist_cap + e) * a.n_inputs;
+  return a.s1 + ((int64_t)f * a.n_blocks + (e - a.hist_len)) * a.n_inputs;
+}
+
+template <int V>
+__device__ __forceinline__ void chunk_sum_body(const PassBArgs& a, int c, int f, int z) {
+  const int i0 = (z * 256 + threadIdx.x) * V;
+  if (i0 >= a.n_inputs) return;
+  const int64_t total = (int64_t)a.hist_len + a.n_blocks;
+  const int64_t e0 = (int64_t)c * a.chunk;
+  const int64_t e1 = e0 + a.chunk < total ? e0 + a.chunk : total;
+  IVec<V> s;
+#pragma unroll
+  for (int k = 0; k < V; ++k) s.v[k] = 0;
+  for (int64_t e = e0; e < e1; ++e) {
+    IVec<V> x;
+    x.load(seq_row(a, f, e) + i0);
+#pragma unroll
+    for (int k = 0; k < V; ++k) s.v[k] += x.v[k];
+  }
+  s.store(a.chunk_sum + ((int64_t)f * a.n_chunks + c) * a.n_inputs + i0);
+}
+
+// Sum of S1 over sequence positions [lo, hi) for V inputs at i0.
+template <int V>
+__device__ void window_sum(const PassBArgs& a, int f, int64_t lo, int64_t hi, int i0, int32_t* out) {
+#pragma unroll
+  for (int k = 0; k < V; ++k) out[k] = 0;
+  if (hi <= lo) return;
+  const int64_t R = a.chunk;
+  const int64_t cs = (lo + R - 1) / R;   // first chunk fully inside
+  const int64_t ce = hi / R;             // one past the last chunk fully inside
+  int64_t edge_hi = hi;
+  if (cs < ce) {
+#pragma unroll 8
+    for (int64_t c = cs; c < ce; ++c) {
+      IVec<V> t;
+      t.load(a.chunk_sum + ((int64_t)f * a.n_chunks + c) * a.n_inputs + i0);
+#pragma unroll
+      for (int k = 0; k < V; ++k) out[k] += t.v[k];
+    }
+    for (int64_t e = ce * R; e < hi; ++e) {
+      IVec<V> x;
+      x.load(seq_row(a, f, e) + i0);
+#pragma unroll
+      for (int k = 0; k < V; ++k) out[k] += x.v[k];
+    }
+    edge_hi = cs * R;
+  }
+  for (int64_t e = lo; e < edge_hi; ++e) {
+    IVec<V> x;
+    x.load(seq_row(a, f, e) + i0);
+#pragma unroll
+    for (int k = 0; k < V; ++k) out[k] += x.v[k];
+  }
+}
+
+// Wavefront sums with DPP lane moves (VALU only, no LDS). Butterflies
+// inside each row of 16 lanes (quad_perm xor 1, xor 2, half-row mirror, row
+// mirror), then row_bcast:15 and row_bcast:31 fold the four rows; the total
+// lands in lane 63. The order of additions is fixed.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint32_t dpp_mov(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, 0xF, false);
+}
+
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_step(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = dpp_mov<CTRL, ROW_MASK>((uint32_t)u);
+  const uint32_t hi = dpp_mov<CTRL, ROW_MASK>((uint32_t)(u >> 32));
+  return v + __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ int64_t dpp_step(int64_t v) {
+  const uint64_t u = (uint64_t)v;
+  const uint32_t lo = dpp_mov<CTRL, ROW_MASK>((uint32_t)u);
+  const uint32_t hi = dpp_mov<CTRL, ROW_MASK>((uint32_t)(u >> 32));
+  return v + (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ int32_t dpp_step(int32_t v) {
+  return v + (int32_t)dpp_mov<CTRL, ROW_MASK>((uint32_t)v);
+}
+
+// Sum over the 64 lanes, valid in lane 63.
+template <typename T>
+__device__ __forceinline__ T wave_sum_to_last(T v) {
+  v = dpp_step<0xB1, 0xF>(v);    // quad_perm [1,0,3,2]
+  v = dpp_step<0x4E, 0xF>(v);    // quad_perm [2,3,0,1]
+  v = dpp_step<0x141, 0xF>(v);   // row_half_mirror
+  v = dpp_step<0x140, 0xF>(v);   // row_mirror
+  v = dpp_step<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
+  v = dpp_step<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
+  return v;
+}
+
+template <int V>
+__device__ __forceinline__ void partial_body(const PassBArgs& a, int c, int f, int z) {
+  constexpr int U = 4;                                         // blocks loaded together
+  const int lane = threadIdx.x & 63;
+  const int g = z * 4 + (threadIdx.x >> 6);                   // input group of 64*V
+  const int N = a.n_inputs, L = a.window, H = a.hist_len;
+  const int i0 = (g * 64 + lane) * V;
+  if (g >= a.n_groups) return;                                 // whole wavefront exits
+  const bool active = i0 < N;
+  const int64_t total = (int64_t)H + a.n_blocks;
+  int64_t e0 = (int64_t)c * a.chunk;
+  if (e0 < H) e0 = H;
+  int64_t e1 = (int64_t)(c + 1) * a.chunk;
+  if (e1 > total) e1 = total;
+  if (e0 >= e1) return;
+  const int64_t hist_from = total - a.hist_next_len;          // first e of the next history
+
+  int32_t P[V];
+#pragma unroll
+  for (int k = 0; k < V; ++k) P[k] = 0;
+  uint32_t use_mask = 0;
+  if (active) {
+    if (L >= 2) window_sum<V>(a, f, e0 - L > 0 ? e0 - L : 0, e0, i0, P);
+#pragma unroll
+    for (int k = 0; k < V; ++k)
+      if (a.mask == nullptr || a.mask[(int64_t)f * N + i0 + k] != 0) use_mask |= 1u << k;
+  }
+
+  for (int64_t eb = e0; eb < e1; eb += U) {
+    IVec<V> x1[U], x2[U], old[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t e = eb + u;
+#pragma unroll
+      for (int k = 0; k < V; ++k) x1[u].v[k] = x2[u].v[k] = old[u].v[k] = 0;
+      if (active && e < e1) {
+        const int64_t row = ((int64_t)f * a.n_blocks + (e - H)) * N + i0;
+        x1[u].load(a.s1 + row);
+        x2[u].load(a.s2 + row);
+        if (L >= 2 && e - L >= 0) old[u].load(seq_row(a, f, e - L) + i0);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t e = eb + u;
+      if (e >= e1) break;
+      double pa = 0.0, pq = 0.0;
+      int64_t r1 = 0, r2 = 0;
+      int32_t n = 0;
+      if (active) {
+        if (L >= 2) {
+#pragma unroll
+          for (int k = 0; k < V; ++k) P[k] += x1[u].v[k] - old[u].v[k];
+          if (e >= hist_from) x1[u].store(a.hist_next + ((int64_t)f * a.hist_cap + (e - hist_from)) * N + i0);
+        } else {
+#pragma unroll
+          for (int k = 0; k < V; ++k) P[k] = x1[u].v[k];
+        }
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+          if ((use_mask >> k & 1u) && P[k] > 0) {
+            n += 1;
+            r1 += x1[u].v[k];
+            r2 += x2[u].v[k];
+            if (L >= 1) {
+              const double pd = (double)P[k];
+              pa += (double)x1[u].v[k] / pd;
+              pq += (double)x2[u].v[k] / (pd * pd);
+            }
+          }
+        }
+      }
+      pa = wave_sum_to_last(pa);
+      pq = wave_sum_to_last(pq);
+      r1 = wave_sum_to_last(r1);
+      r2 = wave_sum_to_last(r2);
+      n = wave_sum_to_last(n);
+      if (lane == 63) {
+        const int64_t o = ((int64_t)f * a.n_groups + g) * a.n_blocks + (e - H);
+        a.part_a[o] = pa;
+        a.part_q[o] = pq;
+        a.part_r1[o] = r1;
+        a.part_r2[o] = r2;
+        a.part_n[o] = n;
+      }
+    }
+  }
+}
+
+// Estimator and flags from the combined sums (Eq. avgSK, final; Sec. 3.2).
+// Contraction is off so the rounding steps are the plain ones.
+__device__ __forceinline__ void finish(const PassBArgs& a, int f, int b, double A, double Bq, int64_t R1, int64_t R2,
+                       int32_t n) {
+#pragma clang fp contract(off)
+  const int64_t K = (int64_t)n * a.block_len;
+  const double Kd = (double)K, Md = (double)a.block_len;
+  bool invalid = K < 2;
+  double V = 0.0;
+  if (a.window == 0) {
+    invalid = invalid || R1 == 0;
+    if (!invalid) {
+      // Eq. (2) over all K samples, numerator K R2 - R1^2 formed exactly.
+      const __int128 num = (__int128)K * (__int128)R2 - (__int128)R1 * (__int128)R1;
+      const __int128 den = (__int128)R1 * (__int128)R1;
+      const double nd = (double)(int64_t)(num >> 64) * 18446744073709551616.0 + (double)(uint64_t)num;
+      const double dd = (double)(int64_t)(den >> 64) * 18446744073709551616.0 + (double)(uint64_t)den;
+      V = (Kd + 1.0) / (Kd - 1.0) * (nd / dd);
+    }
+  } else {
+    invalid = invalid || A == 0.0;
+    if (!invalid) {
+      if (a.estimator == SK_EST_TILDE)
+        V = (Md + 1.0) / (Md - 1.0) * (Md * Bq / (double)n - 1.0);
+      else
+        V = (Kd + 1.0) / (Kd - 1.0) * (Kd * Bq / (A * A) - 1.0);
+    }
+  }
+  uint8_t fl;
+  if (invalid) {
+    V = __builtin_nan("");
+    fl = SK_FLAG_INVALID;
+  } else {
+    double e0 = 1.0;
+    if (a.estimator == SK_EST_HAT && a.window == 1) e0 = ((Kd + 1.0) * (Md - 1.0)) / ((Kd - 1.0) * (Md + 1.0));
+    const double E = e0 + a.expect_offset;
+    const double s = a.sigma_override > 0.0 ? a.sigma_override : sqrt(4.0 / Kd);
+    const double lo = E - a.k_sigma * s, hi = E + a.k_sigma * s;
+    fl = (V < lo ? SK_FLAG_LOW : 0) | (V > hi ? SK_FLAG_HIGH : 0);
+  }
+  const int64_t o = (int64_t)f * a.n_blocks + b;
+  if (a.r1) a.r1[o] = R1;
+  if (a.r2) a.r2[o] = R2;
+  if (a.v) a.v[o] = (float)V;
+  if (a.flags) a.flags[o] = fl;
+  if (a.n_eff) a.n_eff[o] = n;
+}
+
+__device__ __forceinline__ void finalize_body(const PassBArgs& a, int64_t blk) {
+  const int64_t j = blk * 256 + threadIdx.x;
+  if (j >= (int64_t)a.n_channels * a.n_blocks) return;
+  const int f = (int)(j / a.n_blocks), b = (int)(j % a.n_blocks);
+  double A = 0.0, Bq = 0.0;
+  int64_t R1 = 0, R2 = 0;
+  int32_t n = 0;
+  for (int g = 0; g < a.n_groups; ++g) {
+    const int64_t o = ((int64_t)f * a.n_groups + g) * a.n_blocks + b;
+    A += a.part_a[o];
+    Bq += a.part_q[o];
+    R1 += a.part_r1[o];
+    R2 += a.part_r2[o];
+    n += a.part_n[o];
+  }
+  finish(a, f, b, A, Bq, R1, R2, n);
+}
+
+__device__ __forceinline__ void hist_copy_body(const PassBArgs& a, int j, int f, int z) {
+  const int i = z * 256 + threadIdx.x;
+  if (i >= a.n_inputs || j >= a.hist_next_len - a.n_blocks) return;
+  const int64_t src = (int64_t)a.hist_len + a.n_blocks - a.hist_next_len + j;   // < hist_len
+  a.hist_next[((int64_t)f * a.hist_cap + j) * a.n_inputs + i] =
+      a.hist[((int64_t)f * a.hist_cap + src) * a.n_inputs + i];
+}
+
+}  // namespace sk

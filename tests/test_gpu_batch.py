@@ -1,0 +1,87 @@
+"""GPU parity of the batched form: many uneven problems per graph launch.
+
+Every problem's results equal its own single-plan results bit for bit (the
+integer sums are exact and the FP64 combine runs in the same fixed order),
+and match the CPU oracle over the concatenated stream to the usual bar."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from parity import check_result
+
+torch = pytest.importorskip("torch")
+sk = pytest.importorskip("paper_1808_10365_amd")
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _problems(seed, n, max_t=1 << 12):
+    rng = np.random.default_rng(seed)
+    out = []
+    for p in range(n):
+        N = int(rng.choice([16, 64, 256, 1024]))
+        M = int(rng.choice([16, 64, 256]))
+        F = int(rng.choice([1, 3, 4]))
+        T = M * int(rng.integers(1, max_t // M + 1))
+        L = int(rng.choice([0, 1, 2, 5, 64]))
+        est = 1 if (L == 1 and rng.random() < 0.5) else 0
+        w = synth.Workload(f"p{p}", N, F, 2 * T, M, seed * 100 + p, rng.uniform(1.5, 3.5, N), [])
+        out.append((w, dict(n_inputs=N, n_channels=F, n_samples=T, block_len=M, norm_window=L, estimator=est,
+                            k_sigma=4.0, expect_offset=-0.05, sigma_override=0.0)))
+    return out
+
+
+@pytest.mark.parametrize("graph,autotune", [(True, True), (False, False), (True, False)])
+def test_batch_two_calls_match_oracle_and_plans(graph, autotune, tmp_path):
+    probs = _problems(11, 9)
+    xs = [synth.generate(w, nthreads=2) for w, _ in probs]
+    first = [torch.from_numpy(np.ascontiguousarray(x[:kw["n_samples"]])).to(DEV) for x, (_, kw) in zip(xs, probs)]
+    second = [torch.from_numpy(np.ascontiguousarray(x[kw["n_samples"]:])).to(DEV) for x, (_, kw) in zip(xs, probs)]
+    batch = sk.Batch([kw for _, kw in probs], first, autotune=autotune, use_graph=graph,
+                     tune_cache=str(tmp_path / "tune.json"))
+    plans = [sk.Plan(**kw) for _, kw in probs]
+    res_batch, res_plan = [], []
+    for inputs in (first, second):
+        outs = batch.compute(inputs)
+        torch.cuda.synchronize()
+        res_batch.append([{k: getattr(o, k).cpu().numpy().copy() for k in sk.ALL_OUTPUTS} for o in outs])
+        res_plan.append([{k: getattr(p.compute(x), k).cpu().numpy() for k in sk.ALL_OUTPUTS}
+                         for p, x in zip(plans, inputs)])
+        torch.cuda.synchronize()
+    for j, (w, kw) in enumerate(probs):
+        M, L, est = kw["block_len"], kw["norm_window"], kw["estimator"]
+        for call in range(2):
+            for k in sk.ALL_OUTPUTS:
+                a, b = res_batch[call][j][k], res_plan[call][j][k]
+                assert np.array_equal(a, b, equal_nan=(k == "v")), (j, call, k)
+        ref = oracle.sk(xs[j], M, L, est, 4.0, -0.05, 0.0)
+        B = kw["n_samples"] // M
+
+        class G:
+            pass
+        g = G()
+        for k in sk.ALL_OUTPUTS:
+            full = np.concatenate([res_batch[0][j][k], res_batch[1][j][k]], axis=1)
+            setattr(g, k, torch.from_numpy(full))
+        check_result(g, ref, M, L, est, 4.0, -0.05, 0.0, what=f"batch problem {j} {kw}")
+
+
+def test_batch_tiles_and_cache(tmp_path):
+    probs = _problems(5, 4)
+    xs = [torch.from_numpy(synth.generate(w, nthreads=2)[:kw["n_samples"]].copy()).to(DEV) for w, kw in probs]
+    cache = tmp_path / "tune.json"
+    b1 = sk.Batch([kw for _, kw in probs], xs, autotune=True, tune_cache=str(cache))
+    tiles = [b1.tiles(j) for j in range(len(probs))]
+    assert cache.exists() and cache.read_text().count("pass_a_batch") >= 1
+    b2 = sk.Batch([kw for _, kw in probs], xs, autotune=True, tune_cache=str(cache))
+    assert [b2.tiles(j) for j in range(len(probs))] == tiles
+    for lpr, grid in tiles:
+        assert lpr in (32, 64, 128, 256) and grid > 0
+
+
+def test_batch_rejects_unsupported():
+    x = torch.zeros((64, 1, 20), dtype=torch.uint8, device=DEV)
+    with pytest.raises(sk.SKError):
+        sk.Batch([dict(n_inputs=20, n_channels=1, n_samples=64, block_len=16)], [x])
