@@ -29,6 +29,8 @@
  *   v              float  [F][B]      NaN where invalid
  *   flags          uint8  [F][B]      bit0 low, bit1 high, bit2 invalid
  *   n_eff          int32  [F][B]      inputs used (mask set and P_i > 0)
+ *   sk_i           float  [F][B][N]   per-input estimate SK_i (Eq. originalSK), NaN if S1_i = 0
+ *   significance   float  [F][B]      detection significance (V - E) / sigma (Sec. 3.2)
  *
  * Ownership: the caller owns every input and output buffer (device memory,
  * e.g. torch tensors). A plan owns its scratch and its normaliser state
@@ -92,6 +94,8 @@ typedef struct {
   float* v;
   uint8_t* flags;
   int32_t* n_eff;
+  float* sk_i;
+  float* significance;
 } sk_outputs;
 
 typedef struct sk_plan_s* sk_plan_t;

@@ -71,6 +71,7 @@ def _load():
                                VP, VP, VP, VP, VP, VP, VP, VP]
         lib.orc_sk.restype = ctypes.c_int
         lib.orc_quantised_power_moments.argtypes = [F64, I32, VP]
+        lib.orc_significance.argtypes = [VP, VP, I64, I64, I64, I32, F64, F64, VP]
         _lib = lib
     return _lib
 
@@ -199,6 +200,16 @@ def flags(V: np.ndarray, n_eff: np.ndarray, M: int, L: int, est: int = EST_HAT, 
     ne = np.ascontiguousarray(n_eff, dtype=np.int32)
     out = np.empty(V.shape, np.uint8)
     _load().orc_flags(_ptr(V), _ptr(ne), V.size, M, L, est, k, delta, sigma_override, _ptr(out))
+    return out
+
+
+def significance(V: np.ndarray, n_eff: np.ndarray, M: int, L: int, est: int = EST_HAT, delta: float = 0.0,
+                 sigma_override: float = 0.0) -> np.ndarray:
+    """Detection significance (Sec. 3.2): (V - E) / sigma."""
+    V = np.ascontiguousarray(V, dtype=np.float64)
+    ne = np.ascontiguousarray(n_eff, dtype=np.int32)
+    out = np.empty(V.shape, np.float64)
+    _load().orc_significance(_ptr(V), _ptr(ne), V.size, M, L, est, delta, sigma_override, _ptr(out))
     return out
 
 

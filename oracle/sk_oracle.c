@@ -159,6 +159,22 @@ uint8_t orc_flag_one(double V, int64_t n_eff, int64_t M, int64_t L, int est, dou
   return fl;
 }
 
+/* Detection significance (Sec. 3.2): (V - E) / sigma, NaN where invalid. */
+double orc_significance_one(double V, int64_t n_eff, int64_t M, int64_t L, int est, double delta,
+                            double sigma_override) {
+  int64_t K = n_eff * M;
+  if (K < 2 || isnan(V)) return NAN;
+  double E, s;
+  orc_expectation(K, M, L, est, delta, sigma_override, &E, &s);
+  return (V - E) / s;
+}
+
+void orc_significance(const double* V, const int32_t* n_eff, int64_t n, int64_t M, int64_t L, int est,
+                      double delta, double sigma_override, double* out) {
+  for (int64_t j = 0; j < n; ++j)
+    out[j] = orc_significance_one(V[j], n_eff[j], M, L, est, delta, sigma_override);
+}
+
 void orc_flags(const double* V, const int32_t* n_eff, int64_t n, int64_t M, int64_t L, int est,
                double k, double delta, double sigma_override, uint8_t* flags) {
   for (int64_t j = 0; j < n; ++j)

@@ -44,7 +44,7 @@ class PlanDesc(ctypes.Structure):
 class Outputs(ctypes.Structure):
     _fields_ = [("s1", ctypes.c_void_p), ("s2", ctypes.c_void_p), ("r1", ctypes.c_void_p),
                 ("r2", ctypes.c_void_p), ("v", ctypes.c_void_p), ("flags", ctypes.c_void_p),
-                ("n_eff", ctypes.c_void_p)]
+                ("n_eff", ctypes.c_void_p), ("sk_i", ctypes.c_void_p), ("significance", ctypes.c_void_p)]
 
 
 class ServerDesc(ctypes.Structure):
@@ -155,9 +155,12 @@ class Result:
     v: Optional[torch.Tensor]
     flags: Optional[torch.Tensor]
     n_eff: Optional[torch.Tensor]
+    sk_i: Optional[torch.Tensor] = None
+    significance: Optional[torch.Tensor] = None
 
 
-ALL_OUTPUTS = ("s1", "s2", "r1", "r2", "v", "flags", "n_eff")
+ALL_OUTPUTS = ("s1", "s2", "r1", "r2", "v", "flags", "n_eff", "sk_i", "significance")
+DEFAULT_OUTPUTS = ("s1", "s2", "r1", "r2", "v", "flags", "n_eff")
 
 
 class Plan:
@@ -200,7 +203,7 @@ class Plan:
         """Row batching variant of pass A (0..3) and workgroup count (0: one per task)."""
         _check(self._lib.sk_plan_set_pass_a_variant(self.handle, int(variant), int(grid)))
 
-    def alloc_outputs(self, device, want: Sequence[str] = ALL_OUTPUTS) -> Result:
+    def alloc_outputs(self, device, want: Sequence[str] = DEFAULT_OUTPUTS) -> Result:
         F, N, B = self.desc.n_channels, self.desc.n_inputs, self.n_blocks
         mk = {
             "s1": lambda: torch.empty((F, B, N), dtype=torch.int32, device=device),
@@ -210,6 +213,8 @@ class Plan:
             "v": lambda: torch.empty((F, B), dtype=torch.float32, device=device),
             "flags": lambda: torch.empty((F, B), dtype=torch.uint8, device=device),
             "n_eff": lambda: torch.empty((F, B), dtype=torch.int32, device=device),
+            "sk_i": lambda: torch.empty((F, B, N), dtype=torch.float32, device=device),
+            "significance": lambda: torch.empty((F, B), dtype=torch.float32, device=device),
         }
         return Result(**{k: (mk[k]() if k in want else None) for k in ALL_OUTPUTS})
 
@@ -225,7 +230,7 @@ class Plan:
         return out
 
     def compute(self, packed: torch.Tensor, mask: Optional[torch.Tensor] = None,
-                want: Sequence[str] = ALL_OUTPUTS, stream: Optional[torch.cuda.Stream] = None) -> Result:
+                want: Sequence[str] = DEFAULT_OUTPUTS, stream: Optional[torch.cuda.Stream] = None) -> Result:
         out = self.alloc_outputs(packed.device, want)
         return self.compute_into(packed, out, mask, stream)
 
@@ -280,7 +285,9 @@ class Batch:
                        torch.empty((F, B), dtype=torch.int64, device=x.device),
                        torch.empty((F, B), dtype=torch.float32, device=x.device),
                        torch.empty((F, B), dtype=torch.uint8, device=x.device),
-                       torch.empty((F, B), dtype=torch.int32, device=x.device))
+                       torch.empty((F, B), dtype=torch.int32, device=x.device),
+                       torch.empty((F, B, N), dtype=torch.float32, device=x.device),
+                       torch.empty((F, B), dtype=torch.float32, device=x.device))
             self.outputs.append(r)
             outs[j] = Outputs(*[_ptr(getattr(r, k)) for k in ALL_OUTPUTS])
         self._inputs = list(inputs)
@@ -340,12 +347,13 @@ class Server:
         self.arrays.append(d)
         return aid.value
 
-    def alloc_outputs(self, array_id: int, device, want: Sequence[str] = ALL_OUTPUTS) -> Result:
+    def alloc_outputs(self, array_id: int, device, want: Sequence[str] = DEFAULT_OUTPUTS) -> Result:
         d = self.arrays[array_id]
         F, N, B = d.n_channels, d.n_inputs, d.n_samples // d.block_len
         shapes = {"s1": ((F, B, N), torch.int32), "s2": ((F, B, N), torch.int32), "r1": ((F, B), torch.int64),
                   "r2": ((F, B), torch.int64), "v": ((F, B), torch.float32), "flags": ((F, B), torch.uint8),
-                  "n_eff": ((F, B), torch.int32)}
+                  "n_eff": ((F, B), torch.int32), "sk_i": ((F, B, N), torch.float32),
+                  "significance": ((F, B), torch.float32)}
         return Result(**{k: (torch.empty(shapes[k][0], dtype=shapes[k][1], device=device) if k in want else None)
                          for k in ALL_OUTPUTS})
 

@@ -309,6 +309,8 @@ int sk_compute(sk_plan_t p, const uint8_t* d_packed, const uint8_t* d_mask, cons
   a.v = outs->v;
   a.flags = outs->flags;
   a.n_eff = outs->n_eff;
+  a.sk_i = outs->sk_i;
+  a.significance = outs->significance;
   a.n_inputs = (int32_t)N;
   a.n_channels = (int32_t)F;
   a.n_blocks = (int32_t)B;
@@ -324,7 +326,7 @@ int sk_compute(sk_plan_t p, const uint8_t* d_packed, const uint8_t* d_mask, cons
   a.n_chunks = (int32_t)((p->hist_len + B + p->chunk - 1) / p->chunk);
   // Four inputs per lane need 16-byte aligned rows of the sums.
   a.vec = pass_b_vec((int32_t)N);
-  if (((uintptr_t)s1 | (uintptr_t)s2) % 16 != 0) a.vec = 1;
+  if (((uintptr_t)s1 | (uintptr_t)s2 | (uintptr_t)outs->sk_i) % 16 != 0) a.vec = 1;
   a.n_groups = (int32_t)((N + 64 * a.vec - 1) / (64 * a.vec));
   a.estimator = d.estimator;
   a.k_sigma = d.k_sigma;

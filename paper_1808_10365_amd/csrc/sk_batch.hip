@@ -39,6 +39,8 @@ struct BatchProb {
   float* v;
   uint8_t* flags;
   int32_t* n_eff;
+  float* sk_i;
+  float* significance;
   // Task ranges of each kernel over the whole batch.
   int64_t a_begin, cs_begin, cs_count, hc_begin, hc_count, pt_begin, pt_count, fn_begin, fn_count;
 };
@@ -67,6 +69,8 @@ __device__ __forceinline__ PassBArgs make_args(const BatchProb& P, const BatchSt
   a.v = P.v;
   a.flags = P.flags;
   a.n_eff = P.n_eff;
+  a.sk_i = P.sk_i;
+  a.significance = P.significance;
   a.n_inputs = P.a.n_inputs;
   a.n_channels = (int32_t)(P.a.row_bytes / P.a.n_inputs);
   a.n_blocks = P.a.n_blocks;
@@ -488,6 +492,9 @@ int sk_batch_create(const sk_plan_desc* descs, int32_t n, const sk_batch_opts* o
     P.v = o.v;
     P.flags = o.flags;
     P.n_eff = o.n_eff;
+    P.sk_i = o.sk_i;
+    P.significance = o.significance;
+    if ((uintptr_t)P.sk_i % 16) { set_error("problem %d: output sk_i must be 16-byte aligned", j); rc = SK_ERR_INVALID_ARG; break; }
   }
   if (rc) { batch_free(b); return rc; }
 

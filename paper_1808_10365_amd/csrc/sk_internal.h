@@ -81,6 +81,8 @@ struct PassBArgs {
   float* v;
   uint8_t* flags;
   int32_t* n_eff;
+  float* sk_i;            // [F][B][N] or null
+  float* significance;    // [F][B] or null
   int32_t n_inputs, n_channels, n_blocks, block_len, window, hist_len, hist_cap, hist_next_len;
   int32_t chunk, n_chunks, n_groups, vec, estimator;
   double k_sigma, expect_offset, sigma_override;

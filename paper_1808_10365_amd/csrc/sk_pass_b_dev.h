@@ -132,6 +132,14 @@ __device__ __forceinline__ T wave_sum_to_last(T v) {
   return v;
 }
 
+// Eq. originalSK: (M+1)/(M-1) (M S2 / S1^2 - 1), NaN where S1 = 0.
+__device__ __forceinline__ float per_input_sk(int32_t s1, int32_t s2, int32_t block_len) {
+#pragma clang fp contract(off)
+  if (s1 == 0) return __builtin_nanf("");
+  const double Md = (double)block_len, x = (double)s1;
+  return (float)((Md + 1.0) / (Md - 1.0) * (Md * (double)s2 / (x * x) - 1.0));
+}
+
 template <int V>
 __device__ __forceinline__ void partial_body(const PassBArgs& a, int c, int f, int z) {
   constexpr int U = 4;                                         // blocks loaded together
@@ -189,6 +197,15 @@ __device__ __forceinline__ void partial_body(const PassBArgs& a, int c, int f, i
         } else {
 #pragma unroll
           for (int k = 0; k < V; ++k) P[k] = x1[u].v[k];
+        }
+        if (a.sk_i) {
+          // Eq. originalSK for every input of this block (masked or not).
+          float ski[V];
+#pragma unroll
+          for (int k = 0; k < V; ++k) ski[k] = per_input_sk(x1[u].v[k], x2[u].v[k], a.block_len);
+          float* dst = a.sk_i + ((int64_t)f * a.n_blocks + (e - H)) * N + i0;
+#pragma unroll
+          for (int k = 0; k < V; ++k) dst[k] = ski[k];
         }
 #pragma unroll
         for (int k = 0; k < V; ++k) {
@@ -250,6 +267,7 @@ __device__ __forceinline__ void finish(const PassBArgs& a, int f, int b, double 
     }
   }
   uint8_t fl;
+  double sig = __builtin_nan("");
   if (invalid) {
     V = __builtin_nan("");
     fl = SK_FLAG_INVALID;
@@ -260,8 +278,10 @@ __device__ __forceinline__ void finish(const PassBArgs& a, int f, int b, double 
     const double s = a.sigma_override > 0.0 ? a.sigma_override : sqrt(4.0 / Kd);
     const double lo = E - a.k_sigma * s, hi = E + a.k_sigma * s;
     fl = (V < lo ? SK_FLAG_LOW : 0) | (V > hi ? SK_FLAG_HIGH : 0);
+    sig = (V - E) / s;
   }
   const int64_t o = (int64_t)f * a.n_blocks + b;
+  if (a.significance) a.significance[o] = (float)sig;
   if (a.r1) a.r1[o] = R1;
   if (a.r2) a.r2[o] = R2;
   if (a.v) a.v[o] = (float)V;

@@ -80,6 +80,8 @@ static size_t output_bytes(const sk_plan_desc& d, const sk_outputs& o) {
   if (o.v) b += F * B * 4;
   if (o.flags) b += F * B;
   if (o.n_eff) b += F * B * 4;
+  if (o.sk_i) b += F * B * N * 4;
+  if (o.significance) b += F * B * 4;
   return b;
 }
 

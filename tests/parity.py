@@ -31,6 +31,24 @@ def check_result(gpu, ref, M, L, est=0, k=5.0, delta=0.0, sigma_override=0.0, wh
         err = np.abs(v[ok] - ref.V[ok]) / np.maximum(1.0, np.abs(ref.V[ok]))
         if err.size:
             assert err.max() <= V_TOL, f"{tag}V max rel err {err.max():.3e} at {np.argwhere(ok)[err.argmax()]}"
+    sk_i = getattr(gpu, "sk_i", None)
+    if sk_i is not None:
+        g = sk_i.cpu().numpy().astype(np.float64)
+        r = oracle.sk_per_input(ref.S1, ref.S2, M)
+        assert np.array_equal(np.isnan(g), np.isnan(r)), f"{tag}sk_i NaN pattern differs"
+        ok = ~np.isnan(r)
+        if ok.any():
+            err = np.abs(g[ok] - r[ok]) / np.maximum(1.0, np.abs(r[ok]))
+            assert err.max() <= V_TOL, f"{tag}sk_i max rel err {err.max():.3e}"
+    sig = getattr(gpu, "significance", None)
+    if sig is not None:
+        g = sig.cpu().numpy().astype(np.float64)
+        r = oracle.significance(ref.V, ref.n_eff, M, L, est, delta, sigma_override)
+        assert np.array_equal(np.isnan(g), np.isnan(r)), f"{tag}significance NaN pattern differs"
+        ok = ~np.isnan(r)
+        if ok.any():
+            err = np.abs(g[ok] - r[ok]) / np.maximum(1.0, np.abs(r[ok]))
+            assert err.max() <= V_TOL, f"{tag}significance max rel err {err.max():.3e}"
     if gpu.flags is not None:
         fl = gpu.flags.cpu().numpy()
         Vr = ref.V

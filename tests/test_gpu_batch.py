@@ -47,7 +47,7 @@ def test_batch_two_calls_match_oracle_and_plans(graph, autotune, tmp_path):
         outs = batch.compute(inputs)
         torch.cuda.synchronize()
         res_batch.append([{k: getattr(o, k).cpu().numpy().copy() for k in sk.ALL_OUTPUTS} for o in outs])
-        res_plan.append([{k: getattr(p.compute(x), k).cpu().numpy() for k in sk.ALL_OUTPUTS}
+        res_plan.append([{k: getattr(p.compute(x, want=sk.ALL_OUTPUTS), k).cpu().numpy() for k in sk.ALL_OUTPUTS}
                          for p, x in zip(plans, inputs)])
         torch.cuda.synchronize()
     for j, (w, kw) in enumerate(probs):

@@ -36,7 +36,7 @@ def run_gpu(x, M, L=1, est=0, k=5.0, delta=0.0, sigma_override=0.0, mask=None, l
         plan.set_pass_a_variant(variant, grid)
     xd = torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
     md = None if mask is None else torch.from_numpy(np.ascontiguousarray(mask)).to(DEV)
-    out = plan.compute(xd, mask=md)
+    out = plan.compute(xd, mask=md, want=sk.ALL_OUTPUTS)
     torch.cuda.synchronize()
     plan.close()
     return out

@@ -38,7 +38,7 @@ def _alone(kw, frames):
     p = sk.Plan(**kw)
     outs = []
     for f in frames:
-        r = p.compute(torch.from_numpy(f).to(DEV))
+        r = p.compute(torch.from_numpy(f).to(DEV), want=sk.ALL_OUTPUTS)
         outs.append({k: getattr(r, k).cpu().numpy() for k in sk.ALL_OUTPUTS})
     torch.cuda.synchronize()
     p.close()
@@ -65,7 +65,7 @@ def test_alone_equals_mix(budget_frames, inflight):
     for a in order:
         k = nxt[a]
         nxt[a] += 1
-        out = srv.alloc_outputs(ids[a], DEV)
+        out = srv.alloc_outputs(ids[a], DEV, want=sk.ALL_OUTPUTS)
         t = srv.submit(ids[a], dev_frames[a][k], out, tag=a * 100 + k)
         assert t is not None
         tickets.append((a, k, t, out))
@@ -104,7 +104,7 @@ def test_host_staged_frames():
     srv = sk.Server(hbm_budget_bytes=1 << 30, max_inflight=4, n_streams=2)
     aid = srv.add_array(**kw)
     pinned = [torch.from_numpy(f).pin_memory() for f in frames]
-    outs = [srv.alloc_outputs(aid, DEV) for _ in frames]
+    outs = [srv.alloc_outputs(aid, DEV, want=sk.ALL_OUTPUTS) for _ in frames]
     ts = [srv.submit(aid, p, o, tag=j) for j, (p, o) in enumerate(zip(pinned, outs))]
     srv.drain()
     for j, (t, o) in enumerate(zip(ts, outs)):
