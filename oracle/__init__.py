@@ -71,6 +71,7 @@ def _load():
                                VP, VP, VP, VP, VP, VP, VP, VP]
         lib.orc_sk.restype = ctypes.c_int
         lib.orc_quantised_power_moments.argtypes = [F64, I32, VP]
+        lib.orc_channel_stats.argtypes = [VP, I64, I64, I64, VP, VP, VP, VP]
         lib.orc_significance.argtypes = [VP, VP, I64, I64, I64, I32, F64, F64, VP]
         _lib = lib
     return _lib
@@ -225,3 +226,14 @@ def stream(frames, M: int, L: int, **kw) -> Result:
     and evaluated in one call, so the window sees every earlier block."""
     x = np.concatenate([np.asarray(f, dtype=np.uint8) for f in frames], axis=0)
     return sk(x, M, L, **kw)
+
+
+def channel_stats(V: np.ndarray, M: int):
+    """App. A diagnostic per channel: mean, unbiased variance of V over blocks,
+    N_eff = 4 / (M var), and the number of valid blocks."""
+    V = np.ascontiguousarray(V, dtype=np.float64)
+    F, B = V.shape
+    mean, var, ne = np.empty(F), np.empty(F), np.empty(F)
+    cnt = np.empty(F, np.int64)
+    _load().orc_channel_stats(_ptr(V), F, B, M, _ptr(mean), _ptr(var), _ptr(ne), _ptr(cnt))
+    return mean, var, ne, cnt

@@ -326,3 +326,27 @@ void orc_quantised_power_moments(double sigma, int clip, double* m) {
       m[3] += w * p * p * p * p;
     }
 }
+
+/* ------------------------------------------------------------------ App. A
+ * Per-channel statistics of the estimator over the blocks of a call: mean,
+ * unbiased variance over the valid (non-NaN) blocks, and the effective number
+ * of independent receivers N_eff = 4 / (M var) (the variance of the
+ * estimator is 4/(nN) for N independent receivers, Eq. final). */
+void orc_channel_stats(const double* V, int64_t F, int64_t B, int64_t M, double* mean, double* var,
+                       double* n_eff_est, int64_t* count) {
+  for (int64_t f = 0; f < F; ++f) {
+    int64_t n = 0;
+    double s = 0.0;
+    for (int64_t b = 0; b < B; ++b)
+      if (!isnan(V[f * B + b])) { s += V[f * B + b]; n += 1; }
+    double m = n > 0 ? s / (double)n : NAN;
+    double q = 0.0;
+    for (int64_t b = 0; b < B; ++b)
+      if (!isnan(V[f * B + b])) { double d = V[f * B + b] - m; q += d * d; }
+    double v = n > 1 ? q / (double)(n - 1) : NAN;
+    mean[f] = m;
+    var[f] = v;
+    n_eff_est[f] = (n > 1 && v > 0.0) ? 4.0 / ((double)M * v) : NAN;
+    count[f] = n;
+  }
+}

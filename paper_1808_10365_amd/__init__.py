@@ -107,6 +107,8 @@ def load_library():
     lib.sk_server_drain.argtypes = [VP]
     lib.sk_server_get_stats.argtypes = [VP, ctypes.POINTER(ServerStats)]
     lib.sk_server_destroy.argtypes = [VP]
+    lib.sk_channel_stats.argtypes = [VP, I32, I64, I32, VP, VP, VP, VP, VP]
+    lib.sk_channel_stats.restype = ctypes.c_int
     for name in ("sk_server_create", "sk_server_add_array", "sk_stream_submit", "sk_stream_poll",
                  "sk_server_drain", "sk_server_get_stats", "sk_server_destroy"):
         getattr(lib, name).restype = ctypes.c_int
@@ -144,6 +146,20 @@ def digitised_expectation(sigma: Sequence[float], block_len: int, clip: int = 7)
     _check(load_library().sk_digitised_expectation(s.ctypes.data, len(s), int(block_len), int(clip),
                                                    ctypes.byref(d), ctypes.byref(sv)))
     return d.value, sv.value
+
+
+def channel_stats(v: torch.Tensor, block_len: int, stream: Optional[torch.cuda.Stream] = None):
+    """App. A diagnostic per channel of v [F][B]: (mean, var, n_eff, count) device tensors."""
+    assert v.dtype == torch.float32 and v.dim() == 2
+    v = v.contiguous()
+    F, B = v.shape
+    mean = torch.empty(F, dtype=torch.float64, device=v.device)
+    var = torch.empty_like(mean)
+    ne = torch.empty_like(mean)
+    cnt = torch.empty(F, dtype=torch.int64, device=v.device)
+    _check(load_library().sk_channel_stats(_ptr(v), F, B, int(block_len), _ptr(mean), _ptr(var), _ptr(ne),
+                                            _ptr(cnt), _stream_handle(stream)))
+    return mean, var, ne, cnt
 
 
 @dataclass

@@ -37,7 +37,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libsynth.so")
 _lib = None
 
-TONE, NOISE, BURST = 1, 2, 3
+TONE, NOISE, BURST, COMMON = 1, 2, 3, 4
 
 
 class _Event(ctypes.Structure):
@@ -252,3 +252,12 @@ def uniform_small(n_inputs: int, n_channels: int, n_samples: int, seed: int, vma
     re = rng.integers(-vmax, vmax + 1, size=(n_samples, n_channels, n_inputs))
     im = rng.integers(-vmax, vmax + 1, size=(n_samples, n_channels, n_inputs))
     return re, im
+
+
+def common_mode(n_inputs: int, n_blocks: int, block_len: int, amplitude: float, seed: int,
+                sigma: float = 2.0, n_channels: int = 1) -> Workload:
+    """Independent Gaussian inputs of RMS ``sigma`` plus a common-mode Gaussian
+    of RMS ``amplitude`` shared by every input (App. A's simulation)."""
+    T = n_blocks * block_len
+    ev = [Event(COMMON, f, 0, T, float(amplitude)) for f in range(n_channels)] if amplitude > 0 else []
+    return Workload(f"cm{amplitude}", n_inputs, n_channels, T, block_len, seed, np.full(n_inputs, float(sigma)), ev, 1)

@@ -21,7 +21,8 @@
  *
  * Outside RFI regions, each component is drawn by inverse CDF against 14
  * per-input integer thresholds (exact and fast). Inside continuous-domain RFI
- * regions (tones, noise bursts) the Gaussian is drawn by Box-Muller in FP64,
+ * regions (tones, noise bursts, a common-mode signal shared by all inputs)
+ * the Gaussian is drawn by Box-Muller in FP64,
  * the interference is added, and the sum is rounded and clipped. Impulsive
  * bursts overwrite samples with a fixed-amplitude phasor.
  */
@@ -52,13 +53,13 @@ static uint64_t syn_key(uint64_t seed, uint64_t stream) {
 uint64_t synth_splitmix64(uint64_t key, uint64_t n) { return syn_draw(key, n); }
 
 /* Event kinds. */
-enum { SYN_TONE = 1, SYN_NOISE = 2, SYN_BURST = 3 };
+enum { SYN_TONE = 1, SYN_NOISE = 2, SYN_BURST = 3, SYN_COMMON = 4 };
 
 typedef struct {
   int32_t kind;
   int32_t channel;
   int64_t t0, t1;     /* [t0, t1) in samples */
-  double amplitude;   /* tone/burst amplitude in counts; noise RMS per component */
+  double amplitude;   /* tone/burst amplitude in counts; noise / common-mode RMS per component */
   double nu0, nu1;    /* tone frequency offset (cycles/sample) at t0 and at t1 (linear sweep) */
 } syn_event;
 
@@ -122,6 +123,7 @@ static void* syn_worker(void* arg) {
   const syn_desc* d = j->d;
   const int N = d->n_inputs, F = d->n_channels, C = d->clip, NT = 2 * d->clip;
   const uint64_t kbg = syn_key(d->seed, 0), knoise = syn_key(d->seed, 1), kph = syn_key(d->seed, 2);
+  const uint64_t kcm = syn_key(d->seed, 4);
   const syn_event* act[64];
   for (int64_t t = j->t_begin; t < j->t_end; ++t) {
     for (int f = 0; f < F; ++f) {
@@ -159,6 +161,14 @@ static void* syn_worker(void* arg) {
             double th = ph0 + 2.0 * M_PI * (cyc - floor(cyc));
             xr += ev->amplitude * cos(th);
             xi += ev->amplitude * sin(th);
+          } else if (ev->kind == SYN_COMMON) {
+            /* One Gaussian draw per (t, f), shared by every input (App. A). */
+            uint64_t q = syn_draw(kcm, (uint64_t)t * F + f);
+            double v1 = ((double)(q >> 32) + 1.0) / 4294967296.0;
+            double v2 = (double)(uint32_t)q / 4294967296.0;
+            double rr = sqrt(-2.0 * log(v1));
+            xr += ev->amplitude * rr * cos(2.0 * M_PI * v2);
+            xi += ev->amplitude * rr * sin(2.0 * M_PI * v2);
           } else if (ev->kind == SYN_NOISE) {
             uint64_t q = syn_draw(knoise, base + i);
             double v1 = ((double)(q >> 32) + 1.0) / 4294967296.0;
