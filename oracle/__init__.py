@@ -71,6 +71,8 @@ def _load():
                                VP, VP, VP, VP, VP, VP, VP, VP]
         lib.orc_sk.restype = ctypes.c_int
         lib.orc_quantised_power_moments.argtypes = [F64, I32, VP]
+        lib.orc_mc_codes.argtypes = [I64, I64, I32, F64, ctypes.c_uint64, I64, I64, VP, VP]
+        lib.orc_mc_calibrate.argtypes = [I64, I64, I32, I32, F64, I64, ctypes.c_uint64, VP]
         lib.orc_channel_stats.argtypes = [VP, I64, I64, I64, VP, VP, VP, VP]
         lib.orc_significance.argtypes = [VP, VP, I64, I64, I64, I32, F64, F64, VP]
         _lib = lib
@@ -237,3 +239,18 @@ def channel_stats(V: np.ndarray, M: int):
     cnt = np.empty(F, np.int64)
     _load().orc_channel_stats(_ptr(V), F, B, M, _ptr(mean), _ptr(var), _ptr(ne), _ptr(cnt))
     return mean, var, ne, cnt
+
+
+def mc_codes(N: int, M: int, sigma: float, seed: int, s: int, i: int, clip: int = 7):
+    """Simulated component codes (re, im) of input i in estimate s (App. B simulation)."""
+    re = np.empty(M, np.int32)
+    im = np.empty(M, np.int32)
+    _load().orc_mc_codes(N, M, clip, float(sigma), seed & 0xFFFFFFFFFFFFFFFF, s, i, _ptr(re), _ptr(im))
+    return re, im
+
+
+def mc_calibrate(N: int, M: int, sigma: float, n_sim: int, seed: int, est: int = EST_TILDE, clip: int = 7):
+    """Estimator values of n_sim simulated digitised blocks (App. B), own-block normalisation."""
+    v = np.empty(n_sim)
+    _load().orc_mc_calibrate(N, M, est, clip, float(sigma), n_sim, seed & 0xFFFFFFFFFFFFFFFF, _ptr(v))
+    return v

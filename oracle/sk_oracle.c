@@ -350,3 +350,76 @@ void orc_channel_stats(const double* V, int64_t F, int64_t B, int64_t M, double*
     count[f] = n;
   }
 }
+
+/* ------------------------------------------------------------------ App. B
+ * Monte-Carlo simulation of digitised data and the estimator (the paper's
+ * way of setting thresholds). SplitMix64 (Steele, Lea and Flood 2014): key =
+ * output function of the seed; draw n = output function of key + (n+1) *
+ * 0x9E3779B97F4A7C15. Sample j of input i of estimate s uses draw
+ * (s N + i) M + j; high 32 bits -> real part, low 32 bits -> imaginary part,
+ * each = -clip + #{k : thr[k] <= u}, thr[k] = floor(2^32 Phi((k - clip + 1/2)/sigma)).
+ * Each input is normalised by its own block mean (L = 1). */
+static uint64_t orc_splitmix_out(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+void orc_mc_thresholds(double sigma, int clip, uint32_t* thr) {
+  for (int k = 0; k < 2 * clip; ++k) {
+    double s = floor(orc_phi(((double)(k - clip) + 0.5) / sigma) * 4294967296.0);
+    if (s < 0) s = 0;
+    if (s > 4294967295.0) s = 4294967295.0;
+    thr[k] = (uint32_t)s;
+  }
+}
+
+/* Codes of input i, estimate s (for tests of the generator): re, im [M]. */
+void orc_mc_codes(int64_t N, int64_t M, int clip, double sigma, uint64_t seed, int64_t s, int64_t i,
+                  int32_t* re, int32_t* im) {
+  uint32_t thr[16];
+  orc_mc_thresholds(sigma, clip, thr);
+  uint64_t key = orc_splitmix_out(seed);
+  for (int64_t j = 0; j < M; ++j) {
+    uint64_t n = ((uint64_t)s * N + i) * (uint64_t)M + j;
+    uint64_t r = orc_splitmix_out(key + (n + 1) * 0x9E3779B97F4A7C15ULL);
+    uint32_t ur = (uint32_t)(r >> 32), ui = (uint32_t)r;
+    int a = -clip, c = -clip;
+    for (int k = 0; k < 2 * clip; ++k) { a += (thr[k] <= ur); c += (thr[k] <= ui); }
+    re[j] = a;
+    im[j] = c;
+  }
+}
+
+void orc_mc_calibrate(int64_t N, int64_t M, int est, int clip, double sigma, int64_t n_sim, uint64_t seed,
+                      double* values) {
+  int32_t* re = (int32_t*)malloc(sizeof(int32_t) * (size_t)M);
+  int32_t* im = (int32_t*)malloc(sizeof(int32_t) * (size_t)M);
+  for (int64_t s = 0; s < n_sim; ++s) {
+    double Bq = 0.0;
+    int64_t n = 0;
+    for (int64_t i = 0; i < N; ++i) {
+      orc_mc_codes(N, M, clip, sigma, seed, s, i, re, im);
+      int64_t s1 = 0, s2 = 0;
+      for (int64_t j = 0; j < M; ++j) {
+        int64_t p = (int64_t)re[j] * re[j] + (int64_t)im[j] * im[j];
+        s1 += p;
+        s2 += p * p;
+      }
+      if (s1 > 0) {
+        Bq += (double)s2 / ((double)s1 * (double)s1);
+        n += 1;
+      }
+    }
+    double Md = (double)M, Kd = (double)(n * M), V = NAN;
+    if (n > 0 && n * M >= 2) {
+      if (est == ORC_EST_TILDE)
+        V = (Md + 1.0) / (Md - 1.0) * (Md * Bq / (double)n - 1.0);
+      else
+        V = (Kd + 1.0) / (Kd - 1.0) * (Kd * Bq / ((double)n * (double)n) - 1.0);
+    }
+    values[s] = V;
+  }
+  free(re);
+  free(im);
+}

@@ -47,6 +47,12 @@ class Outputs(ctypes.Structure):
                 ("n_eff", ctypes.c_void_p), ("sk_i", ctypes.c_void_p), ("significance", ctypes.c_void_p)]
 
 
+class McDesc(ctypes.Structure):
+    _fields_ = [("n_inputs", ctypes.c_int32), ("block_len", ctypes.c_int32), ("estimator", ctypes.c_int32),
+                ("clip", ctypes.c_int32), ("sigma", ctypes.c_double), ("n_sim", ctypes.c_int64),
+                ("seed", ctypes.c_uint64)]
+
+
 class ServerDesc(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_inflight", ctypes.c_int32),
                 ("n_streams", ctypes.c_int32), ("queue_capacity", ctypes.c_int32)]
@@ -107,6 +113,8 @@ def load_library():
     lib.sk_server_drain.argtypes = [VP]
     lib.sk_server_get_stats.argtypes = [VP, ctypes.POINTER(ServerStats)]
     lib.sk_server_destroy.argtypes = [VP]
+    lib.sk_calibrate_mc.argtypes = [ctypes.POINTER(McDesc), VP, VP, VP]
+    lib.sk_calibrate_mc.restype = ctypes.c_int
     lib.sk_channel_stats.argtypes = [VP, I32, I64, I32, VP, VP, VP, VP, VP]
     lib.sk_channel_stats.restype = ctypes.c_int
     for name in ("sk_server_create", "sk_server_add_array", "sk_stream_submit", "sk_stream_poll",
@@ -146,6 +154,18 @@ def digitised_expectation(sigma: Sequence[float], block_len: int, clip: int = 7)
     _check(load_library().sk_digitised_expectation(s.ctypes.data, len(s), int(block_len), int(clip),
                                                    ctypes.byref(d), ctypes.byref(sv)))
     return d.value, sv.value
+
+
+def calibrate_mc(n_inputs: int, block_len: int, sigma: float, n_sim: int, seed: int, estimator: int = EST_TILDE,
+                 clip: int = 7, device="cuda:0", return_values: bool = False):
+    """App. B Monte-Carlo on the GPU: moments (mean, var, skew, excess kurtosis) of the
+    estimator over n_sim simulated digitised blocks; optionally every value."""
+    import numpy as np
+    d = McDesc(n_inputs, block_len, estimator, clip, float(sigma), int(n_sim), int(seed) & 0xFFFFFFFFFFFFFFFF)
+    m = np.empty(4)
+    vals = torch.empty(int(n_sim), dtype=torch.float64, device=device) if return_values else None
+    _check(load_library().sk_calibrate_mc(ctypes.byref(d), m.ctypes.data, _ptr(vals), _stream_handle(None)))
+    return (m, vals) if return_values else m
 
 
 def channel_stats(v: torch.Tensor, block_len: int, stream: Optional[torch.cuda.Stream] = None):
