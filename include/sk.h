@@ -126,6 +126,18 @@ int sk_compute(sk_plan_t plan, const uint8_t* d_packed, const uint8_t* d_mask,
 int sk_flags(sk_plan_t plan, const float* d_v, const int32_t* d_n_eff, uint8_t* d_flags,
              int64_t n, void* stream);
 
+/* Flag thresholds from a false-alarm probability instead of E -+ k sigma
+ * (Sec. 3.2: for small nN the skewness of the estimator makes a symmetric
+ * interval inaccurate). For each N_eff the thresholds are the p and 1 - p
+ * quantiles of a Pearson type III law with mean E (as for the symmetric
+ * cut), standard deviation sigma (sqrt(4/K) or sigma_override) and skewness
+ * 10 / sqrt(K) (Sec. 2.1), K = N_eff M. fap in (0, 0.5); 0 restores the
+ * symmetric cut. Applies to sk_compute and sk_flags of this plan. */
+int sk_plan_set_false_alarm(sk_plan_t plan, double fap);
+
+/* The (lo, hi) thresholds the plan applies for a given N_eff (host). */
+int sk_plan_get_thresholds(sk_plan_t plan, int32_t n_eff, double* lo, double* hi);
+
 /* Forget the normaliser history (the next call starts a fresh warm-up). */
 int sk_state_reset(sk_plan_t plan);
 

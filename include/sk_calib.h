@@ -45,6 +45,11 @@ typedef struct {
  * Synchronises `stream`. */
 int sk_calibrate_mc(const sk_mc_desc* desc, double* moments, double* d_values, void* stream);
 
+/* Quantile at lower-tail probability p of the Pearson type III law with the
+ * given mean, standard deviation and skewness (>= 0; 0 is the normal law):
+ * the model behind sk_plan_set_false_alarm (host, FP64). */
+int sk_pearson3_quantile(double mean, double sd, double skew, double p, double* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -73,6 +73,9 @@ def _load():
         lib.orc_quantised_power_moments.argtypes = [F64, I32, VP]
         lib.orc_mc_codes.argtypes = [I64, I64, I32, F64, ctypes.c_uint64, I64, I64, VP, VP]
         lib.orc_mc_calibrate.argtypes = [I64, I64, I32, I32, F64, I64, ctypes.c_uint64, VP]
+        lib.orc_pearson3_quantile.argtypes = [F64, F64, F64, F64]
+        lib.orc_pearson3_quantile.restype = ctypes.c_double
+        lib.orc_flags_fap.argtypes = [VP, VP, I64, I64, I64, I32, F64, F64, F64, VP, VP, VP]
         lib.orc_channel_stats.argtypes = [VP, I64, I64, I64, VP, VP, VP, VP]
         lib.orc_significance.argtypes = [VP, VP, I64, I64, I64, I32, F64, F64, VP]
         _lib = lib
@@ -254,3 +257,19 @@ def mc_calibrate(N: int, M: int, sigma: float, n_sim: int, seed: int, est: int =
     v = np.empty(n_sim)
     _load().orc_mc_calibrate(N, M, est, clip, float(sigma), n_sim, seed & 0xFFFFFFFFFFFFFFFF, _ptr(v))
     return v
+
+
+def pearson3_quantile(mean: float, sd: float, skew: float, p: float) -> float:
+    return float(_load().orc_pearson3_quantile(mean, sd, skew, p))
+
+
+def flags_fap(V, n_eff, M: int, L: int, est: int = EST_HAT, fap: float = 1e-3, delta: float = 0.0,
+              sigma_override: float = 0.0):
+    """Flags with false-alarm thresholds; returns (flags, lo, hi)."""
+    V = np.ascontiguousarray(V, dtype=np.float64)
+    ne = np.ascontiguousarray(n_eff, dtype=np.int32)
+    fl = np.empty(V.shape, np.uint8)
+    lo = np.empty(V.shape)
+    hi = np.empty(V.shape)
+    _load().orc_flags_fap(_ptr(V), _ptr(ne), V.size, M, L, est, fap, delta, sigma_override, _ptr(lo), _ptr(hi), _ptr(fl))
+    return fl, lo, hi

@@ -423,3 +423,94 @@ void orc_mc_calibrate(int64_t N, int64_t M, int est, int clip, double sigma, int
   free(re);
   free(im);
 }
+
+/* ------------------------------------------------------------------ Sec. 3.2
+ * False-alarm thresholds for small K: quantiles of a Pearson type III law
+ * with mean E, standard deviation s and skewness g = 10 / sqrt(K) (Sec. 2.1,
+ * divided by sqrt(N) for the average of N receivers, Eq. final). The gamma
+ * CDF is integrated numerically (composite Simpson); for shape a < 1 the
+ * substitution u = t^a removes the singularity at 0. */
+static double orc_gamma_cdf(double a, double x) {
+  if (x <= 0.0) return 0.0;
+  const int n = 40000;
+  double lo, hi, s = 0.0;
+  if (a < 1.0) {
+    /* int_0^x t^(a-1) e^-t dt = (1/a) int_0^(x^a) exp(-u^(1/a)) du */
+    hi = pow(x, a);
+    double h = hi / n;
+    for (int k = 0; k <= n; ++k) {
+      double u = k * h;
+      double f = exp(-pow(u, 1.0 / a));
+      s += f * ((k == 0 || k == n) ? 1.0 : (k % 2 ? 4.0 : 2.0));
+    }
+    return s * h / 3.0 / a / exp(lgamma(a));
+  }
+  lo = a - 60.0 * sqrt(a) - 60.0;
+  if (lo < 0.0) lo = 0.0;
+  if (x <= lo) return 0.0;
+  hi = x;
+  double h = (hi - lo) / n;
+  for (int k = 0; k <= n; ++k) {
+    double t = lo + k * h;
+    double f = t > 0.0 ? exp((a - 1.0) * log(t) - t - lgamma(a)) : 0.0;
+    s += f * ((k == 0 || k == n) ? 1.0 : (k % 2 ? 4.0 : 2.0));
+  }
+  return s * h / 3.0;
+}
+
+double orc_pearson3_quantile(double mean, double sd, double skew, double p) {
+  if (skew < 1e-6) {
+    double lo = -40.0, hi = 40.0;
+    for (int it = 0; it < 200; ++it) {
+      double mid = 0.5 * (lo + hi);
+      if (0.5 * erfc(-mid / sqrt(2.0)) < p) lo = mid; else hi = mid;
+    }
+    return mean + sd * 0.5 * (lo + hi);
+  }
+  double a = 4.0 / (skew * skew);
+  double lo = 0.0, hi = a + 20.0 * sqrt(a) + 20.0;
+  while (orc_gamma_cdf(a, hi) < p) hi *= 2.0;
+  for (int it = 0; it < 64; ++it) {
+    double mid = 0.5 * (lo + hi);
+    if (orc_gamma_cdf(a, mid) < p) lo = mid; else hi = mid;
+  }
+  return mean - 2.0 * sd / skew + sd * skew / 2.0 * 0.5 * (lo + hi);
+}
+
+/* Flags with false-alarm thresholds (fap per tail); the thresholds depend
+ * only on N_eff, so they are computed once per distinct value. */
+void orc_flags_fap(const double* V, const int32_t* n_eff, int64_t n, int64_t M, int64_t L, int est,
+                   double fap, double delta, double sigma_override, double* lo_out, double* hi_out,
+                   uint8_t* flags) {
+  int32_t nmax = 0;
+  for (int64_t j = 0; j < n; ++j)
+    if (n_eff[j] > nmax) nmax = n_eff[j];
+  double* tlo = (double*)malloc(sizeof(double) * ((size_t)nmax + 1));
+  double* thi = (double*)malloc(sizeof(double) * ((size_t)nmax + 1));
+  char* have = (char*)calloc((size_t)nmax + 1, 1);
+  for (int64_t j = 0; j < n; ++j) {
+    int64_t K = (int64_t)n_eff[j] * M;
+    if (K < 2 || isnan(V[j])) {
+      flags[j] = ORC_FLAG_INVALID;
+      if (lo_out) lo_out[j] = NAN;
+      if (hi_out) hi_out[j] = NAN;
+      continue;
+    }
+    int32_t ne = n_eff[j];
+    if (!have[ne]) {
+      double E, s;
+      orc_expectation(K, M, L, est, delta, sigma_override, &E, &s);
+      double g = 10.0 / sqrt((double)K);
+      tlo[ne] = orc_pearson3_quantile(E, s, g, fap);
+      thi[ne] = orc_pearson3_quantile(E, s, g, 1.0 - fap);
+      have[ne] = 1;
+    }
+    double lo = tlo[ne], hi = thi[ne];
+    if (lo_out) lo_out[j] = lo;
+    if (hi_out) hi_out[j] = hi;
+    flags[j] = (uint8_t)((V[j] < lo ? ORC_FLAG_LOW : 0) | (V[j] > hi ? ORC_FLAG_HIGH : 0));
+  }
+  free(tlo);
+  free(thi);
+  free(have);
+}

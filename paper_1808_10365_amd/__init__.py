@@ -113,6 +113,12 @@ def load_library():
     lib.sk_server_drain.argtypes = [VP]
     lib.sk_server_get_stats.argtypes = [VP, ctypes.POINTER(ServerStats)]
     lib.sk_server_destroy.argtypes = [VP]
+    lib.sk_pearson3_quantile.argtypes = [F64, F64, F64, F64, ctypes.POINTER(F64)]
+    lib.sk_pearson3_quantile.restype = ctypes.c_int
+    lib.sk_plan_set_false_alarm.argtypes = [VP, F64]
+    lib.sk_plan_set_false_alarm.restype = ctypes.c_int
+    lib.sk_plan_get_thresholds.argtypes = [VP, I32, ctypes.POINTER(F64), ctypes.POINTER(F64)]
+    lib.sk_plan_get_thresholds.restype = ctypes.c_int
     lib.sk_calibrate_mc.argtypes = [ctypes.POINTER(McDesc), VP, VP, VP]
     lib.sk_calibrate_mc.restype = ctypes.c_int
     lib.sk_channel_stats.argtypes = [VP, I32, I64, I32, VP, VP, VP, VP, VP]
@@ -154,6 +160,12 @@ def digitised_expectation(sigma: Sequence[float], block_len: int, clip: int = 7)
     _check(load_library().sk_digitised_expectation(s.ctypes.data, len(s), int(block_len), int(clip),
                                                    ctypes.byref(d), ctypes.byref(sv)))
     return d.value, sv.value
+
+
+def pearson3_quantile(mean: float, sd: float, skew: float, p: float) -> float:
+    out = ctypes.c_double()
+    _check(load_library().sk_pearson3_quantile(float(mean), float(sd), float(skew), float(p), ctypes.byref(out)))
+    return out.value
 
 
 def calibrate_mc(n_inputs: int, block_len: int, sigma: float, n_sim: int, seed: int, estimator: int = EST_TILDE,
@@ -234,6 +246,15 @@ class Plan:
 
     def set_pass_a_tile(self, lanes_per_row: int):
         _check(self._lib.sk_plan_set_pass_a_tile(self.handle, int(lanes_per_row)))
+
+    def set_false_alarm(self, fap: float):
+        """Flag at the fap and 1 - fap quantiles of a Pearson III law (0: symmetric k sigma)."""
+        _check(self._lib.sk_plan_set_false_alarm(self.handle, float(fap)))
+
+    def thresholds(self, n_eff: int):
+        lo, hi = ctypes.c_double(), ctypes.c_double()
+        _check(self._lib.sk_plan_get_thresholds(self.handle, int(n_eff), ctypes.byref(lo), ctypes.byref(hi)))
+        return lo.value, hi.value
 
     def set_pass_a_variant(self, variant: int, grid: int = 0):
         """Row batching variant of pass A (0..3) and workgroup count (0: one per task)."""

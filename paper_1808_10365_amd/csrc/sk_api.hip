@@ -55,6 +55,8 @@ struct sk_plan_s {
   int pass_a_variant;      // row batching variant of pass A
   int pass_a_grid;         // 0 = one workgroup per task
   std::vector<hipEvent_t> prof;   // 3 events per recorded call
+  double* thresholds;             // [N + 1][2] false-alarm thresholds by N_eff, or null
+  double fap;
   int32_t prof_max, prof_n;
 };
 
@@ -97,6 +99,7 @@ static void free_profile(sk_plan_s* p) {
 
 static void free_plan_memory(sk_plan_s* p) {
   free_profile(p);
+  if (p->thresholds) (void)hipFree(p->thresholds);
   if (p->s1_s2_owned) {
     if (p->s1) (void)hipFree(p->s1);
     if (p->s2) (void)hipFree(p->s2);
@@ -311,6 +314,7 @@ int sk_compute(sk_plan_t p, const uint8_t* d_packed, const uint8_t* d_mask, cons
   a.n_eff = outs->n_eff;
   a.sk_i = outs->sk_i;
   a.significance = outs->significance;
+  a.thresholds = p->thresholds;
   a.n_inputs = (int32_t)N;
   a.n_channels = (int32_t)F;
   a.n_blocks = (int32_t)B;
@@ -351,6 +355,8 @@ int sk_flags(sk_plan_t p, const float* d_v, const int32_t* d_n_eff, uint8_t* d_f
   clear_error();
   if (!p || (n > 0 && (!d_v || !d_n_eff || !d_flags)) || n < 0) { set_error("bad arguments"); return SK_ERR_INVALID_ARG; }
   FlagArgs a;
+  a.thresholds = p->thresholds;
+  a.n_max = p->d.n_inputs;
   a.v = d_v;
   a.n_eff = d_n_eff;
   a.flags = d_flags;
@@ -362,6 +368,58 @@ int sk_flags(sk_plan_t p, const float* d_v, const int32_t* d_n_eff, uint8_t* d_f
   a.expect_offset = p->d.expect_offset;
   a.sigma_override = p->d.sigma_override;
   return launch_flags(a, (hipStream_t)stream);
+}
+
+int sk_plan_set_false_alarm(sk_plan_t p, double fap) {
+  clear_error();
+  if (!p || !(fap >= 0.0) || fap >= 0.5) { set_error("false-alarm probability must be in [0, 0.5)"); return SK_ERR_INVALID_ARG; }
+  if (fap == 0.0) {
+    if (p->thresholds) (void)hipFree(p->thresholds);
+    p->thresholds = nullptr;
+    p->fap = 0.0;
+    return SK_OK;
+  }
+  const sk_plan_desc& d = p->d;
+  std::vector<double> t(2 * ((size_t)d.n_inputs + 1));
+  for (int n = 0; n <= d.n_inputs; ++n) {
+    const double K = (double)n * d.block_len, Md = d.block_len;
+    if (n == 0 || K < 2) { t[2 * n] = -INFINITY; t[2 * n + 1] = INFINITY; continue; }
+    double e0 = 1.0;
+    if (d.estimator == SK_EST_HAT && d.norm_window_blocks == 1) e0 = ((K + 1.0) * (Md - 1.0)) / ((K - 1.0) * (Md + 1.0));
+    const double E = e0 + d.expect_offset;
+    const double s = d.sigma_override > 0.0 ? d.sigma_override : sqrt(4.0 / K);
+    const double g = 10.0 / sqrt(K);
+    t[2 * n] = pearson3_quantile(E, s, g, fap);
+    t[2 * n + 1] = pearson3_quantile(E, s, g, 1.0 - fap);
+  }
+  if (!p->thresholds) SK_HIP_TRY(hipMalloc((void**)&p->thresholds, sizeof(double) * t.size()));
+  SK_HIP_TRY(hipMemcpy(p->thresholds, t.data(), sizeof(double) * t.size(), hipMemcpyHostToDevice));
+  p->fap = fap;
+  return SK_OK;
+}
+
+int sk_plan_get_thresholds(sk_plan_t p, int32_t n_eff, double* lo, double* hi) {
+  if (!p || !lo || !hi || n_eff < 0 || n_eff > p->d.n_inputs) { set_error("bad arguments"); return SK_ERR_INVALID_ARG; }
+  const sk_plan_desc& d = p->d;
+  const double K = (double)n_eff * d.block_len, Md = d.block_len;
+  if (n_eff == 0 || K < 2) { *lo = -INFINITY; *hi = INFINITY; return SK_OK; }
+  if (p->fap > 0.0) {
+    const double g = 10.0 / sqrt(K);
+    double e0 = 1.0;
+    if (d.estimator == SK_EST_HAT && d.norm_window_blocks == 1) e0 = ((K + 1.0) * (Md - 1.0)) / ((K - 1.0) * (Md + 1.0));
+    const double E = e0 + d.expect_offset;
+    const double s = d.sigma_override > 0.0 ? d.sigma_override : sqrt(4.0 / K);
+    *lo = pearson3_quantile(E, s, g, p->fap);
+    *hi = pearson3_quantile(E, s, g, 1.0 - p->fap);
+    return SK_OK;
+  }
+  double e0 = 1.0;
+  if (d.estimator == SK_EST_HAT && d.norm_window_blocks == 1) e0 = ((K + 1.0) * (Md - 1.0)) / ((K - 1.0) * (Md + 1.0));
+  const double E = e0 + d.expect_offset;
+  const double s = d.sigma_override > 0.0 ? d.sigma_override : sqrt(4.0 / K);
+  *lo = E - d.k_sigma * s;
+  *hi = E + d.k_sigma * s;
+  return SK_OK;
 }
 
 int sk_state_reset(sk_plan_t p) {

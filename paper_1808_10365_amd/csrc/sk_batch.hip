@@ -71,6 +71,7 @@ __device__ __forceinline__ PassBArgs make_args(const BatchProb& P, const BatchSt
   a.n_eff = P.n_eff;
   a.sk_i = P.sk_i;
   a.significance = P.significance;
+  a.thresholds = nullptr;
   a.n_inputs = P.a.n_inputs;
   a.n_channels = (int32_t)(P.a.row_bytes / P.a.n_inputs);
   a.n_blocks = P.a.n_blocks;

@@ -83,6 +83,7 @@ struct PassBArgs {
   int32_t* n_eff;
   float* sk_i;            // [F][B][N] or null
   float* significance;    // [F][B] or null
+  const double* thresholds;  // [N + 1][2] (lo, hi) by N_eff, or null: E -+ k sigma
   int32_t n_inputs, n_channels, n_blocks, block_len, window, hist_len, hist_cap, hist_next_len;
   int32_t chunk, n_chunks, n_groups, vec, estimator;
   double k_sigma, expect_offset, sigma_override;
@@ -91,11 +92,15 @@ struct PassBArgs {
 int pass_b_vec(int32_t n_inputs);
 int launch_pass_b(const PassBArgs& a, hipStream_t s);
 
+double pearson3_quantile(double mean, double sd, double skew, double p);
+
 struct FlagArgs {
+  const double* thresholds;
   const float* v;
   const int32_t* n_eff;
   uint8_t* flags;
   int64_t n;
+  int32_t n_max;          // N of the plan: n_eff above it has no threshold entry
   int32_t block_len, window, estimator;
   double k_sigma, expect_offset, sigma_override;
 };

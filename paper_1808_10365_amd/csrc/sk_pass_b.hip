@@ -75,7 +75,7 @@ __global__ __launch_bounds__(256) void flags_kernel(FlagArgs a) {
   const double V = (double)a.v[j];
   const int64_t K = (int64_t)a.n_eff[j] * a.block_len;
   uint8_t fl;
-  if (K < 2 || isnan(V)) {
+  if (K < 2 || isnan(V) || (a.thresholds && a.n_eff[j] > a.n_max)) {
     fl = SK_FLAG_INVALID;
   } else {
     const double Kd = (double)K, Md = (double)a.block_len;
@@ -83,7 +83,11 @@ __global__ __launch_bounds__(256) void flags_kernel(FlagArgs a) {
     if (a.estimator == SK_EST_HAT && a.window == 1) e0 = ((Kd + 1.0) * (Md - 1.0)) / ((Kd - 1.0) * (Md + 1.0));
     const double E = e0 + a.expect_offset;
     const double s = a.sigma_override > 0.0 ? a.sigma_override : sqrt(4.0 / Kd);
-    const double lo = E - a.k_sigma * s, hi = E + a.k_sigma * s;
+    double lo = E - a.k_sigma * s, hi = E + a.k_sigma * s;
+    if (a.thresholds) {
+      lo = a.thresholds[2 * a.n_eff[j]];
+      hi = a.thresholds[2 * a.n_eff[j] + 1];
+    }
     fl = (V < lo ? SK_FLAG_LOW : 0) | (V > hi ? SK_FLAG_HIGH : 0);
   }
   a.flags[j] = fl;

@@ -276,7 +276,11 @@ __device__ __forceinline__ void finish(const PassBArgs& a, int f, int b, double 
     if (a.estimator == SK_EST_HAT && a.window == 1) e0 = ((Kd + 1.0) * (Md - 1.0)) / ((Kd - 1.0) * (Md + 1.0));
     const double E = e0 + a.expect_offset;
     const double s = a.sigma_override > 0.0 ? a.sigma_override : sqrt(4.0 / Kd);
-    const double lo = E - a.k_sigma * s, hi = E + a.k_sigma * s;
+    double lo = E - a.k_sigma * s, hi = E + a.k_sigma * s;
+    if (a.thresholds) {
+      lo = a.thresholds[2 * n];
+      hi = a.thresholds[2 * n + 1];
+    }
     fl = (V < lo ? SK_FLAG_LOW : 0) | (V > hi ? SK_FLAG_HIGH : 0);
     sig = (V - E) / s;
   }

@@ -281,3 +281,33 @@ def test_pathfinder_full():
 def test_chime_full(M):
     w = synth.chime(seed=3, block_len=M)
     _workload_parity(w, w.norm_window)
+
+
+@pytest.mark.parametrize("L,est", [(1, 1), (1, 0), (4, 0)])
+def test_false_alarm_thresholds(L, est):
+    # Small K (N = 3 inputs, M = 32): thresholds from the false-alarm
+    # probability, checked against the oracle's independent quantiles.
+    rng = np.random.default_rng(10 + L)
+    T, F, N, M = 32 * 200, 2, 3, 32
+    x = synth.generate(synth.Workload("f", N, F, T, M, 12, np.full(N, 2.0), []), nthreads=2)
+    x[:, 1, 2] = 0x88                                     # one dead input: N_eff = 2 in channel 1
+    plan = sk.Plan(N, F, T, M, norm_window=L, estimator=est, k_sigma=5.0)
+    plan.set_false_alarm(0.005)
+    for n in range(N + 1):
+        lo, hi = plan.thresholds(n)
+        if n == 0:
+            continue
+        fl, olo, ohi = oracle.flags_fap(np.array([1.0]), np.array([n], np.int32), M, L, est, fap=0.005)
+        assert abs(lo - olo[0]) < 1e-7 and abs(hi - ohi[0]) < 1e-7
+    out = plan.compute(torch.from_numpy(x).to(DEV))
+    torch.cuda.synchronize()
+    ref = oracle.sk(x, M, L, est)
+    v = out.v.cpu().numpy().astype(np.float64)
+    assert np.allclose(v, ref.V, rtol=0, atol=1e-6, equal_nan=True)
+    f0, lo0, hi0 = oracle.flags_fap(ref.V, ref.n_eff, M, L, est, fap=0.005)
+    clear = ~(np.isclose(ref.V, lo0, rtol=0, atol=1e-6) | np.isclose(ref.V, hi0, rtol=0, atol=1e-6))
+    g = out.flags.cpu().numpy()
+    assert np.array_equal(g[clear], f0[clear])
+    assert (g != 0).mean() < 0.1
+    fl2 = plan.flags(out.v, out.n_eff).cpu().numpy()
+    assert np.array_equal(fl2[clear], f0[clear])
