@@ -26,7 +26,9 @@ int sk_profile_enable(sk_plan_t plan, int32_t max_records);
  * new recording. */
 int sk_profile_read(sk_plan_t plan, float* ms_pass_a, float* ms_pass_b, int32_t cap, int32_t* n);
 
-/* Force pass A's lanes per row (power of two, 1..256; 0 = library choice). */
+/* Force pass A's lanes per row (power of two, 1..1024; 0 = library choice).
+ * Up to 256 a workgroup has 256 lanes split into 256 / lanes row phases;
+ * 512 and 1024 use workgroups of that many lanes with one row phase. */
 int sk_plan_set_pass_a_tile(sk_plan_t plan, int32_t lanes_per_row);
 
 /* Pass A's row batching variant (0: 8 rows per batch; 1: 8 rows with the

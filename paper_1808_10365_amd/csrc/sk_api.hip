@@ -201,7 +201,7 @@ int sk_plan_device_bytes(sk_plan_t p, size_t* bytes) {
 
 // Internal: force pass A lanes-per-row (autotuner and tests); 0 = heuristic.
 int sk_plan_set_pass_a_tile(sk_plan_t p, int32_t lpr) {
-  if (!p || (lpr != 0 && (lpr < 1 || lpr > 256 || (lpr & (lpr - 1))))) { set_error("bad tile"); return SK_ERR_INVALID_ARG; }
+  if (!p || (lpr != 0 && (lpr < 1 || lpr > 1024 || (lpr & (lpr - 1))))) { set_error("bad tile"); return SK_ERR_INVALID_ARG; }
   p->pass_a_lpr = lpr;
   return SK_OK;
 }

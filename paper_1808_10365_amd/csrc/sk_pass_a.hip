@@ -17,15 +17,21 @@
 
 namespace sk {
 
+// Workgroup size: 256 lanes, or LPR lanes (512, 1024) when a workgroup spans
+// a whole wide row with one row phase (one contiguous slab per block).
+template <int LPR>
+constexpr int wg_size() { return LPR > 256 ? LPR : 256; }
+
 template <int VEC, int LPR, int U, bool PF>
-__global__ __launch_bounds__(256) void pass_a_kernel(PassATask t) {
-  constexpr int RP = 256 / LPR;         // row phases per workgroup
+__global__ __launch_bounds__(wg_size<LPR>()) void pass_a_kernel(PassATask t) {
+  constexpr int WG = wg_size<LPR>();
+  constexpr int RP = WG / LPR;          // row phases per workgroup
   constexpr int W = 2 * VEC + 1;        // LDS stride of one lane's partials (odd: no bank conflicts)
   __shared__ uint16_t lut[256];
   extern __shared__ uint32_t red[];     // [RP * LPR][W] when RP > 1
 
   const int tid = threadIdx.x;
-  lut[tid] = (uint16_t)code_power((uint32_t)tid);
+  for (int k = tid; k < 256; k += WG) lut[k] = (uint16_t)code_power((uint32_t)k);
   __syncthreads();
 
   const int lc = tid % LPR;
@@ -73,7 +79,7 @@ __global__ __launch_bounds__(256) void pass_a_kernel(PassATask t) {
         mine[VEC + k] = s2[k];
       }
       __syncthreads();
-      for (int o = tid; o < LPR * 2 * VEC; o += 256) {
+      for (int o = tid; o < LPR * 2 * VEC; o += WG) {
         const int l = o / (2 * VEC), k = o % (2 * VEC);
         uint32_t s = 0;
 #pragma unroll 8
@@ -93,9 +99,10 @@ __global__ __launch_bounds__(256) void pass_a_kernel(PassATask t) {
 
 template <int VEC, int LPR, int U, bool PF>
 static int launch_one(const PassATask& t, int grid, hipStream_t s) {
-  constexpr int RP = 256 / LPR;
-  const size_t lds = RP > 1 ? sizeof(uint32_t) * 256 * (2 * VEC + 1) : 0;
-  pass_a_kernel<VEC, LPR, U, PF><<<dim3(grid), dim3(256), lds, s>>>(t);
+  constexpr int WG = wg_size<LPR>();
+  constexpr int RP = WG / LPR;
+  const size_t lds = RP > 1 ? sizeof(uint32_t) * WG * (2 * VEC + 1) : 0;
+  pass_a_kernel<VEC, LPR, U, PF><<<dim3(grid), dim3(WG), lds, s>>>(t);
   SK_HIP_TRY(hipGetLastError());
   return SK_OK;
 }
@@ -112,6 +119,8 @@ static int launch_lpr(const PassATask& t, int lpr, int grid, hipStream_t s) {
     case 64: return launch_one<VEC, 64, U, PF>(t, grid, s);
     case 128: return launch_one<VEC, 128, U, PF>(t, grid, s);
     case 256: return launch_one<VEC, 256, U, PF>(t, grid, s);
+    case 512: return launch_one<VEC, 512, U, PF>(t, grid, s);
+    case 1024: return launch_one<VEC, 1024, U, PF>(t, grid, s);
   }
   set_error("pass A: unsupported lanes-per-row %d", lpr);
   return SK_ERR_INVALID_ARG;

@@ -89,7 +89,7 @@ def test_ragged_random_bytes(shape, L):
     both(x, M, L, what=f"ragged {shape}")
 
 
-@pytest.mark.parametrize("lpr", [1, 2, 4, 8, 16, 32, 64, 128, 256])
+@pytest.mark.parametrize("lpr", [1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1024])
 @pytest.mark.parametrize("variant", [0, 1, 2, 3])
 def test_every_pass_a_tile(lpr, variant):
     # M = 48 and M = 100 leave partial batches and odd row counts for every
