@@ -431,28 +431,25 @@ void orc_mc_calibrate(int64_t N, int64_t M, int est, int clip, double sigma, int
  * CDF is integrated numerically (composite Simpson); for shape a < 1 the
  * substitution u = t^a removes the singularity at 0. */
 static double orc_gamma_cdf(double a, double x) {
+  /* P(a, x) = int_0^x t^(a-1) e^-t dt / Gamma(a). With t = v^m the integrand
+   * becomes m v^(m a - 1) exp(-v^m); m = ceil(6 / a) makes it smooth at 0, so
+   * composite Simpson converges at its full order. For large a the mass sits
+   * within a few sqrt(a) of a, and the integral starts below it. */
   if (x <= 0.0) return 0.0;
-  const int n = 40000;
-  double lo, hi, s = 0.0;
-  if (a < 1.0) {
-    /* int_0^x t^(a-1) e^-t dt = (1/a) int_0^(x^a) exp(-u^(1/a)) du */
-    hi = pow(x, a);
-    double h = hi / n;
-    for (int k = 0; k <= n; ++k) {
-      double u = k * h;
-      double f = exp(-pow(u, 1.0 / a));
-      s += f * ((k == 0 || k == n) ? 1.0 : (k % 2 ? 4.0 : 2.0));
-    }
-    return s * h / 3.0 / a / exp(lgamma(a));
+  int m = (int)ceil(6.0 / a);
+  if (m < 1) m = 1;
+  double tlo = 0.0;
+  if (m == 1) {
+    tlo = a - 60.0 * sqrt(a) - 60.0;
+    if (tlo < 0.0) tlo = 0.0;
   }
-  lo = a - 60.0 * sqrt(a) - 60.0;
-  if (lo < 0.0) lo = 0.0;
-  if (x <= lo) return 0.0;
-  hi = x;
-  double h = (hi - lo) / n;
+  if (x <= tlo) return 0.0;
+  const int n = 40000;
+  double vlo = pow(tlo, 1.0 / m), vhi = pow(x, 1.0 / m);
+  double h = (vhi - vlo) / n, s = 0.0;
   for (int k = 0; k <= n; ++k) {
-    double t = lo + k * h;
-    double f = t > 0.0 ? exp((a - 1.0) * log(t) - t - lgamma(a)) : 0.0;
+    double v = vlo + k * h;
+    double f = v > 0.0 ? (double)m * exp(((double)m * a - 1.0) * log(v) - pow(v, (double)m) - lgamma(a)) : 0.0;
     s += f * ((k == 0 || k == n) ? 1.0 : (k % 2 ? 4.0 : 2.0));
   }
   return s * h / 3.0;
