@@ -54,6 +54,10 @@ int sk_batch_state_reset(sk_batch_t batch, void* stream);
  * workgroup count of pass A. */
 int sk_batch_get_tiles(sk_batch_t batch, int32_t j, int32_t* lanes_per_row, int32_t* pass_a_grid);
 
+/* History length (blocks) problem j's normaliser holds on the device now.
+ * Synchronises the device. */
+int sk_batch_get_state(sk_batch_t batch, int32_t j, int32_t* hist_len);
+
 int sk_batch_destroy(sk_batch_t batch);
 
 #ifdef __cplusplus

@@ -105,6 +105,7 @@ def load_library():
     lib.sk_batch_state_reset.argtypes = [VP, VP]
     lib.sk_batch_get_tiles.argtypes = [VP, I32, ctypes.POINTER(I32), ctypes.POINTER(I32)]
     lib.sk_batch_destroy.argtypes = [VP]
+    lib.sk_batch_get_state.argtypes = [VP, I32, ctypes.POINTER(I32)]
     lib.sk_server_now.restype = ctypes.c_double
     lib.sk_server_create.argtypes = [ctypes.POINTER(ServerDesc), ctypes.POINTER(VP)]
     lib.sk_server_add_array.argtypes = [VP, ctypes.POINTER(PlanDesc), ctypes.POINTER(I32)]
@@ -126,7 +127,7 @@ def load_library():
     for name in ("sk_server_create", "sk_server_add_array", "sk_stream_submit", "sk_stream_poll",
                  "sk_server_drain", "sk_server_get_stats", "sk_server_destroy"):
         getattr(lib, name).restype = ctypes.c_int
-    for name in ("sk_batch_create", "sk_batch_compute", "sk_batch_state_reset", "sk_batch_get_tiles", "sk_batch_destroy"):
+    for name in ("sk_batch_create", "sk_batch_compute", "sk_batch_state_reset", "sk_batch_get_tiles", "sk_batch_destroy", "sk_batch_get_state"):
         getattr(lib, name).restype = ctypes.c_int
     for name in ("sk_plan_create", "sk_plan_destroy", "sk_plan_device_bytes", "sk_compute", "sk_flags",
                  "sk_state_reset", "sk_state_size", "sk_state_export", "sk_state_import",
@@ -365,6 +366,11 @@ class Batch:
 
     def reset(self, stream: Optional[torch.cuda.Stream] = None):
         _check(self._lib.sk_batch_state_reset(self.handle, _stream_handle(stream)))
+
+    def hist_len(self, j: int) -> int:
+        h = ctypes.c_int32()
+        _check(self._lib.sk_batch_get_state(self.handle, j, ctypes.byref(h)))
+        return h.value
 
     def tiles(self, j: int):
         lpr, grid = ctypes.c_int32(), ctypes.c_int32()

@@ -640,6 +640,19 @@ int sk_batch_get_tiles(sk_batch_t b, int32_t j, int32_t* lpr, int32_t* grid) {
   return SK_OK;
 }
 
+int sk_batch_get_state(sk_batch_t b, int32_t j, int32_t* hist_len) {
+  clear_error();
+  if (!b || j < 0 || j >= b->n || !hist_len) { set_error("bad arguments"); return SK_ERR_INVALID_ARG; }
+  SK_HIP_TRY(hipDeviceSynchronize());
+  for (int q = 0; q < b->n; ++q) {
+    if (b->order[q] != j) continue;
+    BatchState st;
+    SK_HIP_TRY(hipMemcpy(&st, b->d_state + q, sizeof st, hipMemcpyDeviceToHost));
+    *hist_len = st.hist_len;
+  }
+  return SK_OK;
+}
+
 int sk_batch_destroy(sk_batch_t b) {
   clear_error();
   if (!b) return SK_OK;

@@ -33,7 +33,26 @@ def _problems(seed, n, max_t=1 << 12):
     return out
 
 
-@pytest.mark.parametrize("graph,autotune", [(True, True), (False, False), (True, False)])
+@pytest.mark.parametrize("graph,autotune", [(False, False), (True, False), (False, True), (True, True)])
+def test_batch_state_advances_once_per_call(graph, autotune, tmp_path):
+    probs = _problems(11, 9)
+    xs = [torch.from_numpy(np.ascontiguousarray(synth.generate(w, nthreads=2)[:kw["n_samples"]])).to(DEV)
+          for w, kw in probs]
+    batch = sk.Batch([kw for _, kw in probs], xs, autotune=autotune, use_graph=graph,
+                     tune_cache=str(tmp_path / "tune.json"))
+    h0 = [batch.hist_len(j) for j in range(len(probs))]
+    print("history after create:", h0, flush=True)
+    assert h0 == [0] * len(probs)
+    for call in (1, 2):
+        batch.compute()
+        torch.cuda.synchronize()
+        h = [batch.hist_len(j) for j in range(len(probs))]
+        expect = [min(max(kw["norm_window"] - 1, 0), call * (kw["n_samples"] // kw["block_len"])) for _, kw in probs]
+        print(f"history after call {call}:", h, "expected", expect, flush=True)
+        assert h == expect
+
+
+@pytest.mark.parametrize("graph,autotune", [(False, False), (True, False), (True, True)])
 def test_batch_two_calls_match_oracle_and_plans(graph, autotune, tmp_path):
     probs = _problems(11, 9)
     xs = [synth.generate(w, nthreads=2) for w, _ in probs]
@@ -47,8 +66,8 @@ def test_batch_two_calls_match_oracle_and_plans(graph, autotune, tmp_path):
         outs = batch.compute(inputs)
         torch.cuda.synchronize()
         res_batch.append([{k: getattr(o, k).cpu().numpy().copy() for k in sk.ALL_OUTPUTS} for o in outs])
-        res_plan.append([{k: getattr(p.compute(x, want=sk.ALL_OUTPUTS), k).cpu().numpy() for k in sk.ALL_OUTPUTS}
-                         for p, x in zip(plans, inputs)])
+        outs_plan = [p.compute(x, want=sk.ALL_OUTPUTS) for p, x in zip(plans, inputs)]   # one call per plan
+        res_plan.append([{k: getattr(o, k).cpu().numpy() for k in sk.ALL_OUTPUTS} for o in outs_plan])
         torch.cuda.synchronize()
     for j, (w, kw) in enumerate(probs):
         M, L, est = kw["block_len"], kw["norm_window"], kw["estimator"]
