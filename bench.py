@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--lpr", type=int, default=0, help="force pass A lanes per row")
     ap.add_argument("--variant", type=int, default=-1, help="force pass A row batching variant (0..3)")
     ap.add_argument("--grid", type=int, default=0, help="force pass A workgroup count (persistent loop)")
+    ap.add_argument("--chunk", type=int, default=0, help="force pass B chunk length (blocks)")
+    ap.add_argument("--bvec", type=int, default=0, help="force pass B inputs per lane (1 or 4)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
     ap.add_argument("--serving-frames", type=int, default=10000)
     ap.add_argument("--serving-loads", default="0.3,0.6,0.9",
@@ -215,6 +217,8 @@ def main():
         plan.set_pass_a_tile(args.lpr)
     if args.variant >= 0 or args.grid:
         plan.set_pass_a_variant(max(args.variant, 0), args.grid)
+    if args.chunk or args.bvec:
+        plan.set_pass_b_tile(args.chunk, args.bvec)
     # Inputs resident in HBM. Inputs smaller than the 256 MB last-level cache
     # rotate over enough copies that repeats cannot be served from it.
     nbuf = max(1, int(np.ceil(1.0e9 / x.nbytes))) if x.nbytes < 1 << 30 else 1

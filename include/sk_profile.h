@@ -37,6 +37,10 @@ int sk_plan_set_pass_a_tile(sk_plan_t plan, int32_t lanes_per_row);
  * fewer: workgroups loop over tasks). */
 int sk_plan_set_pass_a_variant(sk_plan_t plan, int32_t variant, int32_t grid);
 
+/* Pass B's chunk length (blocks per wavefront, power of two; 0 keeps the
+ * library's choice) and inputs per lane (1 or 4; 0 = library choice). */
+int sk_plan_set_pass_b_tile(sk_plan_t plan, int32_t chunk, int32_t inputs_per_lane);
+
 /* Pass A's lanes per row and workgroup count for the next call (after
  * sk_plan_set_pass_a_tile or the library's choice), for reporting. */
 int sk_plan_get_pass_a_tile(sk_plan_t plan, const uint8_t* d_packed, int32_t* vec_bytes,

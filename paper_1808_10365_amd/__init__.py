@@ -98,6 +98,8 @@ def load_library():
     lib.sk_plan_set_pass_a_tile.argtypes = [VP, I32]
     lib.sk_plan_get_pass_a_tile.argtypes = [VP, VP, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I64)]
     lib.sk_plan_set_pass_a_variant.argtypes = [VP, I32, I32]
+    lib.sk_plan_set_pass_b_tile.argtypes = [VP, I32, I32]
+    lib.sk_plan_set_pass_b_tile.restype = ctypes.c_int
     lib.sk_profile_enable.argtypes = [VP, I32]
     lib.sk_profile_read.argtypes = [VP, VP, VP, I32, ctypes.POINTER(I32)]
     lib.sk_batch_create.argtypes = [ctypes.POINTER(PlanDesc), I32, ctypes.POINTER(BatchOpts), VP, ctypes.POINTER(Outputs), ctypes.POINTER(VP)]
@@ -247,6 +249,9 @@ class Plan:
 
     def set_pass_a_tile(self, lanes_per_row: int):
         _check(self._lib.sk_plan_set_pass_a_tile(self.handle, int(lanes_per_row)))
+
+    def set_pass_b_tile(self, chunk: int = 0, inputs_per_lane: int = 0):
+        _check(self._lib.sk_plan_set_pass_b_tile(self.handle, int(chunk), int(inputs_per_lane)))
 
     def set_false_alarm(self, fap: float):
         """Flag at the fap and 1 - fap quantiles of a Pearson III law (0: symmetric k sigma)."""

@@ -54,6 +54,7 @@ struct sk_plan_s {
   int pass_a_lpr;          // 0 = heuristic
   int pass_a_variant;      // row batching variant of pass A
   int pass_a_grid;         // 0 = one workgroup per task
+  int pass_b_vec;          // 0 = library choice, else 1 or 4 inputs per lane
   std::vector<hipEvent_t> prof;   // 3 events per recorded call
   double* thresholds;             // [N + 1][2] false-alarm thresholds by N_eff, or null
   double fap;
@@ -231,6 +232,29 @@ int sk_plan_set_pass_a_variant(sk_plan_t p, int32_t variant, int32_t grid) {
   return SK_OK;
 }
 
+int sk_plan_set_pass_b_tile(sk_plan_t p, int32_t chunk, int32_t vec) {
+  clear_error();
+  if (!p || chunk < 0 || chunk > 1024 || (chunk & (chunk - 1)) || (vec != 0 && vec != 1 && vec != 4)) {
+    set_error("bad pass B tile");
+    return SK_ERR_INVALID_ARG;
+  }
+  if (chunk > 0 && chunk != p->chunk) {
+    const int64_t seq = p->hist_cap + p->n_blocks;
+    const int32_t n_max = (int32_t)((seq + chunk - 1) / chunk);
+    if (p->d.norm_window_blocks >= 2 && n_max > p->n_chunks_max) {
+      int32_t* cs = nullptr;
+      SK_HIP_TRY(hipDeviceSynchronize());
+      SK_HIP_TRY(hipMalloc((void**)&cs, (size_t)p->d.n_channels * n_max * p->d.n_inputs * sizeof(int32_t)));
+      if (p->chunk_sum) (void)hipFree(p->chunk_sum);
+      p->chunk_sum = cs;
+      p->n_chunks_max = n_max;
+    }
+    p->chunk = chunk;
+  }
+  p->pass_b_vec = vec;
+  return SK_OK;
+}
+
 int sk_plan_get_pass_a_tile(sk_plan_t p, const uint8_t* d_packed, int32_t* vec, int32_t* lpr, int64_t* wgs) {
   if (!p || !vec || !lpr || !wgs) { set_error("NULL argument"); return SK_ERR_INVALID_ARG; }
   PassATask t;
@@ -331,6 +355,7 @@ int sk_compute(sk_plan_t p, const uint8_t* d_packed, const uint8_t* d_mask, cons
   // Four inputs per lane need 16-byte aligned rows of the sums.
   a.vec = pass_b_vec((int32_t)N);
   if (((uintptr_t)s1 | (uintptr_t)s2 | (uintptr_t)outs->sk_i) % 16 != 0) a.vec = 1;
+  if (p->pass_b_vec == 1) a.vec = 1;
   a.n_groups = (int32_t)((N + 64 * a.vec - 1) / (64 * a.vec));
   a.estimator = d.estimator;
   a.k_sigma = d.k_sigma;

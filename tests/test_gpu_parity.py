@@ -311,3 +311,21 @@ def test_false_alarm_thresholds(L, est):
     assert (g != 0).mean() < 0.1
     fl2 = plan.flags(out.v, out.n_eff).cpu().numpy()
     assert np.array_equal(fl2[clear], f0[clear])
+
+
+@pytest.mark.parametrize("chunk,vec", [(1, 4), (2, 1), (8, 4), (64, 1), (128, 4)])
+def test_pass_b_tiles(chunk, vec):
+    # Every chunk length and lane width gives the oracle's results, across
+    # calls (history) and with a window longer than the chunk.
+    N, F, M, L = 96, 3, 32, 9
+    T = 32 * 20
+    x = synth.generate(synth.Workload("pb", N, F, 3 * T, M, 8, np.full(N, 2.2), []), nthreads=2)
+    ref = oracle.sk(x, M, L)
+    p = sk.Plan(N, F, T, M, norm_window=L)
+    p.set_pass_b_tile(chunk, vec)
+    vs = []
+    for k in range(3):
+        out = p.compute(torch.from_numpy(x[k * T:(k + 1) * T].copy()).to(DEV))
+        vs.append(out.v.cpu().numpy())
+    v = np.concatenate(vs, axis=1)
+    assert np.allclose(v, ref.V, rtol=0, atol=1e-6)
