@@ -38,7 +38,7 @@ def parse():
     ap.add_argument("--cpu-sample-blocks", type=int, default=0,
                     help="blocks per channel in the oracle's timed sample (0: pick ~10-30 s of work)")
     ap.add_argument("--lpr", type=int, default=0, help="force pass A lanes per row")
-    ap.add_argument("--variant", type=int, default=-1, help="force pass A row batching variant (0..3)")
+    ap.add_argument("--variant", type=int, default=-1, help="force pass A row batching variant (0..11; -1 = library choice)")
     ap.add_argument("--grid", type=int, default=0, help="force pass A workgroup count (persistent loop)")
     ap.add_argument("--chunk", type=int, default=0, help="force pass B chunk length (blocks)")
     ap.add_argument("--bvec", type=int, default=0, help="force pass B inputs per lane (1 or 4)")
@@ -216,7 +216,7 @@ def main():
     if args.lpr:
         plan.set_pass_a_tile(args.lpr)
     if args.variant >= 0 or args.grid:
-        plan.set_pass_a_variant(max(args.variant, 0), args.grid)
+        plan.set_pass_a_variant(args.variant, args.grid)
     if args.chunk or args.bvec:
         plan.set_pass_b_tile(args.chunk, args.bvec)
     # Inputs resident in HBM. Inputs smaller than the 256 MB last-level cache

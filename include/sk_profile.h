@@ -31,10 +31,18 @@ int sk_profile_read(sk_plan_t plan, float* ms_pass_a, float* ms_pass_b, int32_t 
  * 512 and 1024 use workgroups of that many lanes with one row phase. */
 int sk_plan_set_pass_a_tile(sk_plan_t plan, int32_t lanes_per_row);
 
-/* Pass A's row batching variant (0: 8 rows per batch; 1: 8 rows with the
- * next batch's loads issued before the current batch is reduced; 2: 4 rows
- * with that prefetch; 3: 16 rows) and workgroup count (0: one per task;
- * fewer: workgroups loop over tasks). */
+/* Pass A's row batching variant (-1: library choice; 0: 8 rows per batch;
+ * 1: 8 rows with the next batch's loads issued before the current batch is
+ * reduced; 2: 4 rows with that prefetch; 3: 16 rows; 4: two column groups of
+ * 16 inputs per lane, lanes_per_row apart, 4 rows per batch; 5: two groups,
+ * 8 rows; 6: four groups, 2 rows; 7: power table replicated per lane (64 KiB
+ * of LDS, free of bank conflicts), 8 rows; 8: replicated table, two groups,
+ * 4 rows; 9: replicated table, 8 rows with prefetch; 10: replicated table,
+ * 16 rows; 11: replicated table, 16 rows with prefetch) and workgroup count
+ * (0: one per task; fewer: workgroups loop over tasks). Variants 1..11 apply
+ * to the 16-byte path (N % 16 == 0, aligned input); the others use variant
+ * 0. Variants 7..11 use one row phase, so lanes per row below 256 are raised
+ * to 256 for them. */
 int sk_plan_set_pass_a_variant(sk_plan_t plan, int32_t variant, int32_t grid);
 
 /* Pass B's chunk length (blocks per wavefront, power of two; 0 keeps the

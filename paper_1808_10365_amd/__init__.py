@@ -263,7 +263,8 @@ class Plan:
         return lo.value, hi.value
 
     def set_pass_a_variant(self, variant: int, grid: int = 0):
-        """Row batching variant of pass A (0..3) and workgroup count (0: one per task)."""
+        """Row batching variant of pass A (-1: library choice, 0..11) and workgroup
+        count (0: one per task)."""
         _check(self._lib.sk_plan_set_pass_a_variant(self.handle, int(variant), int(grid)))
 
     def alloc_outputs(self, device, want: Sequence[str] = DEFAULT_OUTPUTS) -> Result:

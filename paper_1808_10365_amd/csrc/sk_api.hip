@@ -52,7 +52,7 @@ struct sk_plan_s {
   int32_t cur;             // index of the live history buffer
   size_t bytes;
   int pass_a_lpr;          // 0 = heuristic
-  int pass_a_variant;      // row batching variant of pass A
+  int pass_a_variant = -1; // row batching variant of pass A; -1 = heuristic
   int pass_a_grid;         // 0 = one workgroup per task
   int pass_b_vec;          // 0 = library choice, else 1 or 4 inputs per lane
   std::vector<hipEvent_t> prof;   // 3 events per recorded call
@@ -214,11 +214,13 @@ static PassAConfig plan_pass_a_config(const sk_plan_s* p, const uint8_t* d_packe
   t->n_inputs = (int32_t)N;
   t->block_len = p->d.block_len;
   t->n_blocks = (int32_t)B;
-  PassAConfig c = default_pass_a_config(vec, t->row_bytes, B);
+  PassAConfig c = default_pass_a_config(vec, t->row_bytes, B, p->pass_a_lpr == 0 && p->pass_a_variant < 0);
   if (p->pass_a_lpr) c.lpr = p->pass_a_lpr;
-  c.variant = p->pass_a_variant;
+  if (p->pass_a_variant >= 0) c.variant = p->pass_a_variant;
+  if (pass_a_lane_table(vec, c.variant) && c.lpr < 256) c.lpr = 256;
+  const int gpl = pass_a_groups_per_lane(vec, c.variant);
   t->col_groups = (int32_t)(t->row_bytes / vec);
-  t->chunks = (t->col_groups + c.lpr - 1) / c.lpr;
+  t->chunks = (t->col_groups + c.lpr * gpl - 1) / (c.lpr * gpl);
   t->n_tasks = B * t->chunks;
   c.grid = (int)(t->n_tasks < (1 << 30) ? t->n_tasks : (1 << 30));
   if (p->pass_a_grid > 0 && p->pass_a_grid < c.grid) c.grid = p->pass_a_grid;
@@ -226,7 +228,7 @@ static PassAConfig plan_pass_a_config(const sk_plan_s* p, const uint8_t* d_packe
 }
 
 int sk_plan_set_pass_a_variant(sk_plan_t p, int32_t variant, int32_t grid) {
-  if (!p || variant < 0 || variant > 3 || grid < 0) { set_error("bad variant"); return SK_ERR_INVALID_ARG; }
+  if (!p || variant < -1 || variant > 11 || grid < 0) { set_error("bad variant"); return SK_ERR_INVALID_ARG; }
   p->pass_a_variant = variant;
   p->pass_a_grid = grid;
   return SK_OK;

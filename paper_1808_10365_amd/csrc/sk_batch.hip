@@ -440,7 +440,7 @@ int sk_batch_create(const sk_plan_desc* descs, int32_t n, const sk_batch_opts* o
     P.a.block_len = d.block_len;
     P.a.n_blocks = (int32_t)B;
     P.a.col_groups = (int32_t)(F * N / 16);
-    PassAConfig c = default_pass_a_config(16, F * N, B);
+    PassAConfig c = default_pass_a_config(16, F * N, B, false);
     P.lpr = c.lpr;
     P.window = L;
     P.hist_cap = L >= 2 ? L - 1 : 0;

@@ -41,20 +41,27 @@ struct PassATask {
   int32_t block_len;    // M
   int32_t n_blocks;     // B
   int32_t col_groups;   // G / VEC
-  int32_t chunks;       // ceil(col_groups / LPR)
+  int32_t chunks;       // ceil(col_groups / (LPR * groups per lane))
   int64_t n_tasks;      // B * chunks
 };
 
 struct PassAConfig {
   int vec;     // 16, 4 or 1 bytes per lane per row
   int lpr;     // lanes per row: power of two, 1..256
-  int variant; // row batching variant (0..3, 16-byte path)
+  int variant; // row batching variant (0..8, 16-byte path; see pass_a_groups_per_lane)
   int grid;    // workgroups launched (<= tasks; grid-stride beyond)
 };
 
 int launch_pass_a(const PassATask& t, const PassAConfig& c, hipStream_t s);
 int pick_vec(const uint8_t* x, int32_t n_inputs);
-PassAConfig default_pass_a_config(int vec, int64_t row_bytes, int64_t n_blocks);
+// Column groups each lane owns in pass A for this vector width and variant.
+int pass_a_groups_per_lane(int vec, int variant);
+// Whether this variant uses the lane-replicated power table (needs >= 256
+// lanes per row: one row phase).
+bool pass_a_lane_table(int vec, int variant);
+// lane_table: the lane-replicated table variants may be chosen (single-plan
+// kernel only; the batched kernel has its own table).
+PassAConfig default_pass_a_config(int vec, int64_t row_bytes, int64_t n_blocks, bool lane_table);
 
 // ---------------------------------------------------------------- pass B
 // Normaliser window, array combine, estimator and flags (Eq. discreteMean,

@@ -10,6 +10,12 @@
 // the S2 accumulator and p0 + p1 (dot with (1,1)) to S1, so each sample costs
 // one byte extract, one LDS read and one dot-lane. Sums are exact in 32 bits:
 // p <= 128, so S2 <= M * 2^14 < 2^31 for M <= 131071.
+//
+// The shared 512-byte table makes the 64 lookups of a wavefront collide in
+// LDS banks whenever codes differ in the right bits; the lane-replicated
+// table (64 KiB, one 256-byte row per code with a dword slot per lane) is
+// conflict-free and its address is one v_perm_b32 of the code byte and the
+// lane's slot. Wide rows use it by default with one 256-lane row phase.
 #include <hip/hip_runtime.h>
 
 #include "sk_internal.h"
@@ -22,17 +28,55 @@ namespace sk {
 template <int LPR>
 constexpr int wg_size() { return LPR > 256 ? LPR : 256; }
 
-template <int VEC, int LPR, int U, bool PF>
+// Stores one lane's sums of column group g (VEC inputs) for block b.
+template <int VEC>
+__device__ __forceinline__ void store_group(const PassATask& t, int b, int g, const uint32_t* s1,
+                                            const uint32_t* s2) {
+  const int N = t.n_inputs;
+  const int B = t.n_blocks;
+  const int64_t col = (int64_t)g * VEC;
+  const int64_t f = col / N, i = col % N;
+  int32_t* d1 = t.s1 + (f * B + b) * N + i;
+  int32_t* d2 = t.s2 + (f * B + b) * N + i;
+  if constexpr (VEC >= 4) {
+#pragma unroll
+    for (int k = 0; k < VEC; k += 4) {
+      u32x4 a = {s1[k], s1[k + 1], s1[k + 2], s1[k + 3]};
+      u32x4 c = {s2[k], s2[k + 1], s2[k + 2], s2[k + 3]};
+      *reinterpret_cast<u32x4*>(d1 + k) = a;
+      *reinterpret_cast<u32x4*>(d2 + k) = c;
+    }
+  } else {
+    d1[0] = (int32_t)s1[0];
+    d2[0] = (int32_t)s2[0];
+  }
+}
+
+// One task is (block b, chunk ch) of LPR * GPL column groups. Lane lc of
+// row phase ph owns groups ch * LPR * GPL + j * LPR + lc (j < GPL), so for
+// every j a wavefront's loads of one row are 64 * VEC contiguous bytes.
+//
+// REP selects the lane-replicated 64 KiB power table (16-byte lanes and one
+// row phase only): bank-conflict free whatever the codes, at the price of
+// LDS that limits a CU to two workgroups.
+template <int VEC, int LPR, int U, bool PF, int GPL, bool REP>
 __global__ __launch_bounds__(wg_size<LPR>()) void pass_a_kernel(PassATask t) {
   constexpr int WG = wg_size<LPR>();
   constexpr int RP = WG / LPR;          // row phases per workgroup
   constexpr int W = 2 * VEC + 1;        // LDS stride of one lane's partials (odd: no bank conflicts)
-  __shared__ uint16_t lut[256];
+  static_assert(!REP || (VEC == 16 && RP == 1), "lane table: 16-byte lanes, one row phase");
+  __shared__ uint16_t lut16[REP ? 1 : 256];
+  __shared__ __attribute__((aligned(16))) uint32_t lut32[REP ? LANE_LUT_DWORDS : 1];
   extern __shared__ uint32_t red[];     // [RP * LPR][W] when RP > 1
 
   const int tid = threadIdx.x;
-  for (int k = tid; k < 256; k += WG) lut[k] = (uint16_t)code_power((uint32_t)k);
+  if constexpr (REP) {
+    fill_lane_lut<WG>(lut32, tid);
+  } else {
+    for (int k = tid; k < 256; k += WG) lut16[k] = (uint16_t)code_power((uint32_t)k);
+  }
   __syncthreads();
+  const LaneLut llut{reinterpret_cast<const uint8_t*>(lut32), (uint32_t)(tid & 63) * 4};
 
   const int lc = tid % LPR;
   const int ph = tid / LPR;
@@ -42,85 +86,109 @@ __global__ __launch_bounds__(wg_size<LPR>()) void pass_a_kernel(PassATask t) {
   for (int64_t task = blockIdx.x; task < t.n_tasks; task += gridDim.x) {
     const int b = (int)(task / t.chunks);
     const int ch = (int)(task % t.chunks);
-    const int g = ch * LPR + lc;
-    uint32_t s1[VEC], s2[VEC];
+    const int g0 = ch * LPR * GPL + lc;
+    uint32_t s1[GPL][VEC], s2[GPL][VEC];
 #pragma unroll
-    for (int k = 0; k < VEC; ++k) s1[k] = s2[k] = 0;
-
-    if (g < t.col_groups)
-      sum_rows<VEC, RP, U, PF>(t.x + (int64_t)b * M * G + (int64_t)g * VEC, G, M, ph, lut, s1, s2);
-
-    const int N = t.n_inputs;
-    const int B = t.n_blocks;
-    if constexpr (RP == 1) {
-      if (g < t.col_groups) {
-        const int64_t col = (int64_t)g * VEC;
-        const int64_t f = col / N, i = col % N;
-        int32_t* d1 = t.s1 + (f * B + b) * N + i;
-        int32_t* d2 = t.s2 + (f * B + b) * N + i;
-        if constexpr (VEC >= 4) {
+    for (int j = 0; j < GPL; ++j)
 #pragma unroll
-          for (int k = 0; k < VEC; k += 4) {
-            u32x4 a = {s1[k], s1[k + 1], s1[k + 2], s1[k + 3]};
-            u32x4 c = {s2[k], s2[k + 1], s2[k + 2], s2[k + 3]};
-            *reinterpret_cast<u32x4*>(d1 + k) = a;
-            *reinterpret_cast<u32x4*>(d2 + k) = c;
-          }
-        } else {
-          d1[0] = (int32_t)s1[0];
-          d2[0] = (int32_t)s2[0];
+      for (int k = 0; k < VEC; ++k) s1[j][k] = s2[j][k] = 0;
+
+    if (g0 < t.col_groups) {
+      const uint8_t* blk = t.x + (int64_t)b * M * G;
+      if constexpr (GPL == 1 && REP) {
+        sum_rows<VEC, RP, U, PF>(blk + (int64_t)g0 * VEC, G, M, ph, llut, s1[0], s2[0]);
+      } else if constexpr (GPL == 1) {
+        sum_rows<VEC, RP, U, PF>(blk + (int64_t)g0 * VEC, G, M, ph, lut16, s1[0], s2[0]);
+      } else {
+        // A group past the row's end walks group g0 again (in bounds); its
+        // sums are discarded below.
+        const uint8_t* base[GPL];
+#pragma unroll
+        for (int j = 0; j < GPL; ++j) {
+          const int g = g0 + j * LPR;
+          base[j] = blk + (int64_t)(g < t.col_groups ? g : g0) * VEC;
         }
+        if constexpr (REP)
+          sum_rows_multi<VEC, RP, U, GPL>(base, G, M, ph, llut, s1, s2);
+        else
+          sum_rows_multi<VEC, RP, U, GPL>(base, G, M, ph, lut16, s1, s2);
+      }
+    }
+
+    if constexpr (RP == 1) {
+#pragma unroll
+      for (int j = 0; j < GPL; ++j) {
+        const int g = g0 + j * LPR;
+        if (g < t.col_groups) store_group<VEC>(t, b, g, s1[j], s2[j]);
       }
     } else {
-      uint32_t* mine = red + (ph * LPR + lc) * W;
+      const int N = t.n_inputs;
+      const int B = t.n_blocks;
 #pragma unroll
-      for (int k = 0; k < VEC; ++k) {
-        mine[k] = s1[k];
-        mine[VEC + k] = s2[k];
-      }
-      __syncthreads();
-      for (int o = tid; o < LPR * 2 * VEC; o += WG) {
-        const int l = o / (2 * VEC), k = o % (2 * VEC);
-        uint32_t s = 0;
-#pragma unroll 8
-        for (int p = 0; p < RP; ++p) s += red[(p * LPR + l) * W + k];
-        const int gg = ch * LPR + l;
-        if (gg < t.col_groups) {
-          const int64_t col = (int64_t)gg * VEC + (k % VEC);
-          const int64_t f = col / N, i = col % N;
-          int32_t* dst = k < VEC ? t.s1 : t.s2;
-          dst[(f * B + b) * N + i] = (int32_t)s;
+      for (int j = 0; j < GPL; ++j) {
+        uint32_t* mine = red + (ph * LPR + lc) * W;
+#pragma unroll
+        for (int k = 0; k < VEC; ++k) {
+          mine[k] = s1[j][k];
+          mine[VEC + k] = s2[j][k];
         }
+        __syncthreads();
+        for (int o = tid; o < LPR * 2 * VEC; o += WG) {
+          const int l = o / (2 * VEC), k = o % (2 * VEC);
+          uint32_t s = 0;
+#pragma unroll 8
+          for (int q = 0; q < RP; ++q) s += red[(q * LPR + l) * W + k];
+          const int gg = ch * LPR * GPL + j * LPR + l;
+          if (gg < t.col_groups) {
+            const int64_t col = (int64_t)gg * VEC + (k % VEC);
+            const int64_t f = col / N, i = col % N;
+            int32_t* dst = k < VEC ? t.s1 : t.s2;
+            dst[(f * B + b) * N + i] = (int32_t)s;
+          }
+        }
+        __syncthreads();
       }
-      __syncthreads();
     }
   }
 }
 
-template <int VEC, int LPR, int U, bool PF>
+template <int VEC, int LPR, int U, bool PF, int GPL, bool REP = false>
 static int launch_one(const PassATask& t, int grid, hipStream_t s) {
   constexpr int WG = wg_size<LPR>();
   constexpr int RP = WG / LPR;
   const size_t lds = RP > 1 ? sizeof(uint32_t) * WG * (2 * VEC + 1) : 0;
-  pass_a_kernel<VEC, LPR, U, PF><<<dim3(grid), dim3(WG), lds, s>>>(t);
+  pass_a_kernel<VEC, LPR, U, PF, GPL, REP><<<dim3(grid), dim3(WG), lds, s>>>(t);
   SK_HIP_TRY(hipGetLastError());
   return SK_OK;
 }
 
-template <int VEC, int U, bool PF>
+// Lane-table variants: one row phase, so 256, 512 or 1024 lanes per row
+// (narrower tiles are widened to 256 by the planner).
+template <int U, int GPL, bool PF = false>
+static int launch_rep(const PassATask& t, int lpr, int grid, hipStream_t s) {
+  switch (lpr) {
+    case 256: return launch_one<16, 256, U, PF, GPL, true>(t, grid, s);
+    case 512: return launch_one<16, 512, U, PF, GPL, true>(t, grid, s);
+    case 1024: return launch_one<16, 1024, U, PF, GPL, true>(t, grid, s);
+  }
+  set_error("pass A: lane-table variant needs 256..1024 lanes per row, got %d", lpr);
+  return SK_ERR_INVALID_ARG;
+}
+
+template <int VEC, int U, bool PF, int GPL = 1>
 static int launch_lpr(const PassATask& t, int lpr, int grid, hipStream_t s) {
   switch (lpr) {
-    case 1: return launch_one<VEC, 1, U, PF>(t, grid, s);
-    case 2: return launch_one<VEC, 2, U, PF>(t, grid, s);
-    case 4: return launch_one<VEC, 4, U, PF>(t, grid, s);
-    case 8: return launch_one<VEC, 8, U, PF>(t, grid, s);
-    case 16: return launch_one<VEC, 16, U, PF>(t, grid, s);
-    case 32: return launch_one<VEC, 32, U, PF>(t, grid, s);
-    case 64: return launch_one<VEC, 64, U, PF>(t, grid, s);
-    case 128: return launch_one<VEC, 128, U, PF>(t, grid, s);
-    case 256: return launch_one<VEC, 256, U, PF>(t, grid, s);
-    case 512: return launch_one<VEC, 512, U, PF>(t, grid, s);
-    case 1024: return launch_one<VEC, 1024, U, PF>(t, grid, s);
+    case 1: return launch_one<VEC, 1, U, PF, GPL>(t, grid, s);
+    case 2: return launch_one<VEC, 2, U, PF, GPL>(t, grid, s);
+    case 4: return launch_one<VEC, 4, U, PF, GPL>(t, grid, s);
+    case 8: return launch_one<VEC, 8, U, PF, GPL>(t, grid, s);
+    case 16: return launch_one<VEC, 16, U, PF, GPL>(t, grid, s);
+    case 32: return launch_one<VEC, 32, U, PF, GPL>(t, grid, s);
+    case 64: return launch_one<VEC, 64, U, PF, GPL>(t, grid, s);
+    case 128: return launch_one<VEC, 128, U, PF, GPL>(t, grid, s);
+    case 256: return launch_one<VEC, 256, U, PF, GPL>(t, grid, s);
+    case 512: return launch_one<VEC, 512, U, PF, GPL>(t, grid, s);
+    case 1024: return launch_one<VEC, 1024, U, PF, GPL>(t, grid, s);
   }
   set_error("pass A: unsupported lanes-per-row %d", lpr);
   return SK_ERR_INVALID_ARG;
@@ -129,6 +197,25 @@ static int launch_lpr(const PassATask& t, int lpr, int grid, hipStream_t s) {
 // Row batching variants (the 16-byte path only; others use variant 0):
 //   0: 8 rows per batch            1: 8 rows, next batch prefetched
 //   2: 4 rows, prefetched          3: 16 rows per batch
+//   4: 2 column groups per lane, 4 rows per batch
+//   5: 2 column groups per lane, 8 rows per batch
+//   6: 4 column groups per lane, 2 rows per batch
+//   7: lane-replicated power table, 8 rows per batch
+//   8: lane-replicated power table, 2 column groups per lane, 4 rows
+//   9: lane-replicated power table, 8 rows, next batch prefetched
+//  10: lane-replicated power table, 16 rows per batch
+//  11: lane-replicated power table, 16 rows, next batch prefetched
+int pass_a_groups_per_lane(int vec, int variant) {
+  if (vec != 16) return 1;
+  switch (variant) {
+    case 4: case 5: case 8: return 2;
+    case 6: return 4;
+    default: return 1;
+  }
+}
+
+bool pass_a_lane_table(int vec, int variant) { return vec == 16 && variant >= 7 && variant <= 11; }
+
 template <int VEC>
 static int launch_vec(const PassATask& t, int lpr, int variant, int grid, hipStream_t s) {
   if constexpr (VEC == 16) {
@@ -136,6 +223,14 @@ static int launch_vec(const PassATask& t, int lpr, int variant, int grid, hipStr
       case 1: return launch_lpr<VEC, 8, true>(t, lpr, grid, s);
       case 2: return launch_lpr<VEC, 4, true>(t, lpr, grid, s);
       case 3: return launch_lpr<VEC, 16, false>(t, lpr, grid, s);
+      case 4: return launch_lpr<VEC, 4, false, 2>(t, lpr, grid, s);
+      case 5: return launch_lpr<VEC, 8, false, 2>(t, lpr, grid, s);
+      case 6: return launch_lpr<VEC, 2, false, 4>(t, lpr, grid, s);
+      case 7: return launch_rep<8, 1>(t, lpr, grid, s);
+      case 8: return launch_rep<4, 2>(t, lpr, grid, s);
+      case 9: return launch_rep<8, 1, true>(t, lpr, grid, s);
+      case 10: return launch_rep<16, 1>(t, lpr, grid, s);
+      case 11: return launch_rep<16, 1, true>(t, lpr, grid, s);
       default: break;
     }
   }
@@ -149,8 +244,21 @@ int pick_vec(const uint8_t* x, int32_t n_inputs) {
   return 1;
 }
 
-PassAConfig default_pass_a_config(int vec, int64_t row_bytes, int64_t n_blocks) {
+PassAConfig default_pass_a_config(int vec, int64_t row_bytes, int64_t n_blocks, bool lane_table) {
   const int64_t cg = row_bytes / vec;
+  // Wide rows (>= 256 groups of 16 inputs) with at least one task per CU:
+  // one row phase of 256 lanes and the lane-replicated table (no bank
+  // conflicts on the power lookups), the fastest tile measured on MI355X
+  // for rows of 8 KiB at block lengths 256 and 1024.
+  if (lane_table && vec == 16 && cg >= 256 && n_blocks * ((cg + 255) / 256) >= 256) {
+    const int64_t tasks = n_blocks * ((cg + 255) / 256);
+    PassAConfig c;
+    c.vec = vec;
+    c.lpr = 256;
+    c.variant = 7;
+    c.grid = (int)(tasks < (1 << 30) ? tasks : (1 << 30));
+    return c;
+  }
   int lpr = 1;
   while (lpr < 256 && lpr < cg) lpr *= 2;
   // Keep at least ~2048 workgroups in flight when the rows are wide: trade

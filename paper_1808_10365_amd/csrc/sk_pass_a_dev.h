@@ -17,18 +17,24 @@ __device__ __forceinline__ uint32_t code_power(uint32_t c) {
   return (uint32_t)(re * re + im * im);
 }
 
+#define SK_GLOBAL __attribute__((address_space(1)))
+
+// Input rows always live in device (global) memory. Loading through a
+// global-address-space pointer keeps the loads global_load_* even where the
+// compiler cannot infer the address space (flat loads would also count
+// against the LDS wait counter and serialise the table reads behind them).
 template <int VEC>
 struct Row {
   static constexpr int DW = VEC >= 4 ? VEC / 4 : 1;
   uint32_t w[DW];
   __device__ __forceinline__ void load(const uint8_t* p) {
     if constexpr (VEC == 16) {
-      const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p));
+      const u32x4 v = __builtin_nontemporal_load((const SK_GLOBAL u32x4*)p);
       w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
     } else if constexpr (VEC == 4) {
-      w[0] = __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(p));
+      w[0] = __builtin_nontemporal_load((const SK_GLOBAL uint32_t*)p);
     } else {
-      w[0] = *p;
+      w[0] = *(const SK_GLOBAL uint8_t*)p;
     }
   }
   __device__ __forceinline__ uint32_t byte(int k) const {
@@ -60,12 +66,61 @@ __device__ __forceinline__ void accumulate_one(const Row<VEC>& r0, const uint16_
   }
 }
 
+// Power table replicated per lane: the entry of code c for lane l is the
+// low 16 bits of the dword at byte (c << 8) | (l % 64) * 4, 64 KiB in all.
+// The 64 lanes of a wavefront always read 64 distinct consecutive dwords
+// (no bank conflicts whatever the codes), and one v_perm_b32 forms the
+// address: byte 1 = the code byte, byte 0 = the lane's offset.
+struct LaneLut {
+  const uint8_t* base;
+  uint32_t laneoff;
+  __device__ __forceinline__ uint32_t at(uint32_t w, int k) const {
+    const uint32_t sel = 0x0C0C0000u | ((uint32_t)(4 + k) << 8);
+    return *reinterpret_cast<const uint16_t*>(base + __builtin_amdgcn_perm(w, laneoff, sel));
+  }
+};
+constexpr int LANE_LUT_DWORDS = 256 * 64;
+
+// Fill a lane-replicated table with WG lanes (16-byte stores).
+template <int WG>
+__device__ __forceinline__ void fill_lane_lut(uint32_t* t, int tid) {
+  for (int k = tid; k < LANE_LUT_DWORDS / 4; k += WG) {
+    const uint32_t p = code_power((uint32_t)(k >> 4));
+    reinterpret_cast<u32x4*>(t)[k] = u32x4{p, p, p, p};
+  }
+}
+
+template <int VEC>
+__device__ __forceinline__ void accumulate_pair(const Row<VEC>& r0, const Row<VEC>& r1,
+                                                const LaneLut& lut, uint32_t* s1, uint32_t* s2) {
+  static_assert(VEC >= 4, "the lane table reads bytes of whole dwords");
+  const u16x2 ones = {1, 1};
+#pragma unroll
+  for (int k = 0; k < VEC; ++k) {
+    const uint32_t pp = lut.at(r0.w[k >> 2], k & 3) | (lut.at(r1.w[k >> 2], k & 3) << 16);
+    const u16x2 P = __builtin_bit_cast(u16x2, pp);
+    s2[k] = __builtin_amdgcn_udot2(P, P, s2[k], false);
+    s1[k] = __builtin_amdgcn_udot2(P, ones, s1[k], false);
+  }
+}
+
+template <int VEC>
+__device__ __forceinline__ void accumulate_one(const Row<VEC>& r0, const LaneLut& lut,
+                                               uint32_t* s1, uint32_t* s2) {
+#pragma unroll
+  for (int k = 0; k < VEC; ++k) {
+    const uint32_t p = lut.at(r0.w[k >> 2], k & 3);
+    s1[k] += p;
+    s2[k] += p * p;
+  }
+}
+
 // Rows of this lane in batches of U: r = ph, ph + RP, ... (< M). With PF the
 // loads of the next batch are issued before the current batch is reduced, so
 // each wavefront keeps a batch of rows in flight while it computes.
-template <int VEC, int RP, int U, bool PF>
+template <int VEC, int RP, int U, bool PF, typename Lut>
 __device__ __forceinline__ void sum_rows(const uint8_t* base, int64_t G, int M, int ph,
-                                         const uint16_t* lut, uint32_t* s1, uint32_t* s2) {
+                                         const Lut& lut, uint32_t* s1, uint32_t* s2) {
   const int nrow = ph < M ? (M - ph + RP - 1) / RP : 0;
   const int nb = nrow / U;
   int r = ph;
@@ -106,6 +161,54 @@ __device__ __forceinline__ void sum_rows(const uint8_t* base, int64_t G, int M, 
     Row<VEC> q0;
     q0.load(base + (int64_t)r * G);
     accumulate_one<VEC>(q0, lut, s1, s2);
+  }
+}
+
+// Several column groups per lane: group j starts at base[j] (the same row
+// layout). Each batch issues the loads of U rows of every group before any
+// of them is reduced, so a lane keeps GPL * U rows in flight.
+template <int VEC, int RP, int U, int GPL, typename Lut>
+__device__ __forceinline__ void sum_rows_multi(const uint8_t* const* base, int64_t G, int M, int ph,
+                                               const Lut& lut, uint32_t (*s1)[VEC], uint32_t (*s2)[VEC]) {
+  static_assert(U % 2 == 0, "rows are reduced in pairs");
+  const int nrow = ph < M ? (M - ph + RP - 1) / RP : 0;
+  const int nb = nrow / U;
+  const int64_t step = (int64_t)RP * G;
+  const uint8_t* p[GPL];
+#pragma unroll
+  for (int j = 0; j < GPL; ++j) p[j] = base[j] + (int64_t)ph * G;
+  int r = ph;
+  for (int bt = 0; bt < nb; ++bt) {
+    Row<VEC> q[GPL][U];
+#pragma unroll
+    for (int j = 0; j < GPL; ++j)
+#pragma unroll
+      for (int u = 0; u < U; ++u) q[j][u].load(p[j] + u * step);
+#pragma unroll
+    for (int j = 0; j < GPL; ++j) {
+#pragma unroll
+      for (int u = 0; u < U / 2; ++u) accumulate_pair<VEC>(q[j][2 * u], q[j][2 * u + 1], lut, s1[j], s2[j]);
+      p[j] += U * step;
+    }
+    r += U * RP;
+  }
+  for (; r + RP < M; r += 2 * RP) {
+#pragma unroll
+    for (int j = 0; j < GPL; ++j) {
+      Row<VEC> q0, q1;
+      q0.load(p[j]);
+      q1.load(p[j] + step);
+      accumulate_pair<VEC>(q0, q1, lut, s1[j], s2[j]);
+      p[j] += 2 * step;
+    }
+  }
+  if (r < M) {
+#pragma unroll
+    for (int j = 0; j < GPL; ++j) {
+      Row<VEC> q0;
+      q0.load(p[j]);
+      accumulate_one<VEC>(q0, lut, s1[j], s2[j]);
+    }
   }
 }
 

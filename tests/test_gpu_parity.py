@@ -26,14 +26,14 @@ def _say(msg):
     sys.stdout.flush()
 
 
-def run_gpu(x, M, L=1, est=0, k=5.0, delta=0.0, sigma_override=0.0, mask=None, lpr=0, variant=0, grid=0):
+def run_gpu(x, M, L=1, est=0, k=5.0, delta=0.0, sigma_override=0.0, mask=None, lpr=0, variant=None, grid=0):
     T, F, N = x.shape
     plan = sk.Plan(N, F, T, M, norm_window=L, estimator=est, k_sigma=k, expect_offset=delta,
                    sigma_override=sigma_override)
     if lpr:
         plan.set_pass_a_tile(lpr)
-    if variant or grid:
-        plan.set_pass_a_variant(variant, grid)
+    if variant is not None or grid:
+        plan.set_pass_a_variant(-1 if variant is None else variant, grid)
     xd = torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
     md = None if mask is None else torch.from_numpy(np.ascontiguousarray(mask)).to(DEV)
     out = plan.compute(xd, mask=md, want=sk.ALL_OUTPUTS)
@@ -90,12 +90,15 @@ def test_ragged_random_bytes(shape, L):
 
 
 @pytest.mark.parametrize("lpr", [1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1024])
-@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+@pytest.mark.parametrize("variant", list(range(12)))
 def test_every_pass_a_tile(lpr, variant):
     # M = 48 and M = 100 leave partial batches and odd row counts for every
-    # row-phase count.
+    # row-phase count; rows of 96 and 32 column groups leave the second and
+    # later groups of a lane (variants 4..6, 8) partly past the row's end, and
+    # the 512-group row fills them exactly at 256 lanes per row. Variants
+    # 7..11 (lane-replicated table) widen tiles below 256 lanes to 256.
     rng = np.random.default_rng(lpr + 7 * variant)
-    for T, F, N, M in ((96, 3, 512, 48), (200, 2, 256, 100)):
+    for T, F, N, M in ((96, 3, 512, 48), (200, 2, 256, 100), (64, 4, 2048, 32)):
         x = rng.integers(0, 256, size=(T, F, N), dtype=np.uint8)
         both(x, M, 2, what=f"tile lpr={lpr} variant={variant}", lpr=lpr, variant=variant)
 
@@ -106,8 +109,8 @@ def test_pass_a_persistent_grid(grid):
     rng = np.random.default_rng(grid)
     T, F, N, M = 512, 2, 1024, 64
     x = rng.integers(0, 256, size=(T, F, N), dtype=np.uint8)
-    for variant in (0, 1):
-        both(x, M, 3, what=f"grid={grid}", lpr=64, variant=variant, grid=grid)
+    for variant in (0, 1, 4, 6, 7, 8):
+        both(x, M, 3, what=f"grid={grid} variant={variant}", lpr=64, variant=variant, grid=grid)
 
 
 def test_unaligned_input_pointer():
