@@ -140,8 +140,21 @@ __device__ __forceinline__ float per_input_sk(int32_t s1, int32_t s2, int32_t bl
   return (float)((Md + 1.0) / (Md - 1.0) * (Md * (double)s2 / (x * x) - 1.0));
 }
 
-template <int V>
-__device__ __forceinline__ void partial_body(const PassBArgs& a, int c, int f, int z) {
+// 1/p for p >= 1: the hardware reciprocal estimate refined by two Newton
+// steps (each squares the relative error), within a few ulps of the
+// correctly rounded quotient. S1/P and S2/P^2 then cost multiplies.
+__device__ __forceinline__ double recip_pos(double p) {
+  double r = __builtin_amdgcn_rcp(p);
+  double e = __builtin_fma(-p, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-p, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+
+// RI: integer type of the per-wavefront R1/R2 sums: int32_t when a
+// wavefront's sums provably fit (64 V M 2^14 < 2^31), else int64_t.
+template <int V, typename RI>
+__device__ __forceinline__ void partial_body_t(const PassBArgs& a, int c, int f, int z) {
   constexpr int U = 4;                                         // blocks loaded together
   const int lane = threadIdx.x & 63;
   const int g = z * 4 + (threadIdx.x >> 6);                   // input group of 64*V
@@ -187,7 +200,7 @@ __device__ __forceinline__ void partial_body(const PassBArgs& a, int c, int f, i
       const int64_t e = eb + u;
       if (e >= e1) break;
       double pa = 0.0, pq = 0.0;
-      int64_t r1 = 0, r2 = 0;
+      RI r1 = 0, r2 = 0;
       int32_t n = 0;
       if (active) {
         if (L >= 2) {
@@ -214,9 +227,9 @@ __device__ __forceinline__ void partial_body(const PassBArgs& a, int c, int f, i
             r1 += x1[u].v[k];
             r2 += x2[u].v[k];
             if (L >= 1) {
-              const double pd = (double)P[k];
-              pa += (double)x1[u].v[k] / pd;
-              pq += (double)x2[u].v[k] / (pd * pd);
+              const double rp = recip_pos((double)P[k]);
+              pa += (double)x1[u].v[k] * rp;
+              pq += (double)x2[u].v[k] * rp * rp;
             }
           }
         }
@@ -230,12 +243,21 @@ __device__ __forceinline__ void partial_body(const PassBArgs& a, int c, int f, i
         const int64_t o = ((int64_t)f * a.n_groups + g) * a.n_blocks + (e - H);
         a.part_a[o] = pa;
         a.part_q[o] = pq;
-        a.part_r1[o] = r1;
-        a.part_r2[o] = r2;
+        a.part_r1[o] = (int64_t)r1;
+        a.part_r2[o] = (int64_t)r2;
         a.part_n[o] = n;
       }
     }
   }
+}
+
+template <int V>
+__device__ __forceinline__ void partial_body(const PassBArgs& a, int c, int f, int z) {
+  // S2 of one input is at most M * 128^2 = M * 2^14 (Eq. singlesums).
+  if ((int64_t)64 * V * a.block_len * 16384 < ((int64_t)1 << 31))
+    partial_body_t<V, int32_t>(a, c, f, z);
+  else
+    partial_body_t<V, int64_t>(a, c, f, z);
 }
 
 // Estimator and flags from the combined sums (Eq. avgSK, final; Sec. 3.2).
