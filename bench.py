@@ -46,6 +46,11 @@ def parse():
     ap.add_argument("--serving-frames", type=int, default=10000)
     ap.add_argument("--serving-loads", default="0.3,0.6,0.9",
                     help="offered loads as fractions of the measured saturated frame rate")
+    ap.add_argument("--no-ceiling", action="store_true", help="skip the read-only stream ceiling")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched (32 problems) measurement")
+    ap.add_argument("--batched-steps", type=int, default=10)
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="threads for the split oracle run (0: the CPUs this process may use, at most 16)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after timing, run one device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -86,8 +91,64 @@ def traffic_from_profile(wname, launches_bytes):
     return d.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(x, w, L, delta, sig, sample_blocks):
-    """The oracle as it stands, single-threaded, on the first blocks of every channel."""
+def host_info():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return {"nproc": os.cpu_count(), "usable_cpus": usable, "cpu_model": model}
+
+
+def split_oracle_tasks(T, F, M, L, n_tasks):
+    """(channel, first block, last block + 1, first block of the halo) for a
+    split of every channel's blocks into ranges. A range starting at block
+    b0 > 0 re-reads the L - 1 blocks before it (its normaliser window), and
+    those blocks' outputs are dropped, so the stitched results equal one
+    whole-stream run."""
+    B = T // M
+    per_f = max(1, min(B, n_tasks // F if n_tasks >= F else 1))
+    bounds = [B * k // per_f for k in range(per_f + 1)]
+    tasks = []
+    for f in range(F):
+        for b0, b1 in zip(bounds[:-1], bounds[1:]):
+            if b1 > b0:
+                tasks.append((f, b0, b1, max(0, b0 - max(L - 1, 0))))
+    return tasks
+
+
+def run_split_oracle(x, M, L, delta, sig, tasks, threads):
+    """The oracle on every task's slice in a thread pool (the oracle is C
+    called through ctypes, which releases the GIL). Returns the wall time and
+    the per-task results (V, flags) for the blocks each task owns."""
+    import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
+    import oracle
+    slices = [np.ascontiguousarray(x[h * M:b1 * M, f:f + 1, :]) for f, b0, b1, h in tasks]
+
+    def one(j):
+        f, b0, b1, h = tasks[j]
+        r = oracle.sk(slices[j], M, L, 0, 5.0, delta, sig)
+        return r.V[0, b0 - h:], r.flags[0, b0 - h:]
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        out = list(ex.map(one, range(len(tasks))))
+    return time.perf_counter() - t0, out
+
+
+def cpu_baseline(x, w, L, delta, sig, sample_blocks, threads):
+    """The oracle as it stands, on the first blocks of every channel: once on
+    one thread, and split over (channel, block range) tasks on `threads`
+    threads (the reported value)."""
     import numpy as np
     import oracle
     M = w.block_len
@@ -99,11 +160,87 @@ def cpu_baseline(x, w, L, delta, sig, sample_blocks):
     xs = np.ascontiguousarray(x[:T])
     t0 = time.perf_counter()
     oracle.sk(xs, M, L, 0, 5.0, delta, sig)
-    dt = time.perf_counter() - t0
+    dt1 = time.perf_counter() - t0
     nbytes = xs.nbytes
-    return {"value": nbytes / dt / 1e9, "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {sample_blocks} blocks of every channel ({nbytes} bytes, T={T}), "
-                      f"whole path single-threaded, {dt:.1f} s"}
+    info = host_info()
+    if threads <= 0:
+        threads = max(1, min(16, info["usable_cpus"]))
+    tasks = split_oracle_tasks(T, w.n_channels, M, L, threads)
+    dtn, _ = run_split_oracle(xs, M, L, delta, sig, tasks, threads)
+    halo = sum(b0 - h for _, b0, _, h in tasks)
+    return {"value": nbytes / dtn / 1e9, "unit": "GB/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {sample_blocks} blocks of every channel ({nbytes} bytes, T={T}), whole path; "
+                      f"{len(tasks)} (channel, block range) tasks on {threads} threads, {dtn:.2f} s, "
+                      f"{halo} halo blocks re-read for the normaliser window",
+            "single_thread": {"value": nbytes / dt1 / 1e9, "seconds": round(dt1, 2)},
+            "host": info}
+
+
+def read_ceiling(xd, dev, reps=10):
+    """Best rate of the library's read-only stream probe over a few grid sizes."""
+    import torch
+    import paper_1808_10365_amd as sk
+    best = None
+    sink = torch.empty(8192 * 256, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+    for wgs in (1024, 2048, 4096, 8192):
+        sk.read_probe(xd, wgs, sink)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            sk.read_probe(xd, wgs, sink)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        gbs = xd.numel() / (e0.elapsed_time(e1) / reps * 1e-3) / 1e9
+        if best is None or gbs > best["GBps"]:
+            best = {"GBps": round(gbs, 1), "workgroups": wgs}
+    return best
+
+
+def batched_bench(args, dev):
+    """The batched persistent form on the 32-problem draw (seed 4): every
+    problem's input resident in HBM, one graph launch per call."""
+    import tempfile
+    import numpy as np
+    import torch
+    import paper_1808_10365_amd as sk
+    import synth
+    ws = synth.batched(seed=4)
+    xs, plans = [], []
+    t0 = time.perf_counter()
+    for w in ws:
+        x = synth.generate(w)
+        xs.append(torch.from_numpy(x).to(dev))
+        del x
+        plans.append(dict(n_inputs=w.n_inputs, n_channels=w.n_channels, n_samples=w.n_samples,
+                          block_len=w.block_len, norm_window=w.norm_window, k_sigma=5.0))
+    total = sum(w.nbytes for w in ws)
+    print(f"# batched: {len(ws)} problems, {total / 1e9:.2f} GB generated in {time.perf_counter() - t0:.1f} s",
+          file=sys.stderr, flush=True)
+    with tempfile.TemporaryDirectory() as td:
+        batch = sk.Batch(plans, xs, autotune=True, use_graph=True, tune_cache=os.path.join(td, "tune.json"))
+        for _ in range(3):
+            batch.compute()
+        torch.cuda.synchronize()
+        stream = torch.cuda.current_stream()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.batched_steps):
+            batch.compute()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.batched_steps
+        batch.close()
+    del xs
+    torch.cuda.empty_cache()
+    gbs = total / (ms * 1e-3) / 1e9
+    return {"problems": len(ws), "input_bytes": total, "ms_per_call": round(ms, 4), "GBps": round(gbs, 1),
+            "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+            "shapes": "N in {64,256,1024,2048}, M in {64,256,1024}, F in {1,4,8}, T = M * U{1..2^17/M}, "
+                      "L = 2^16/M; one graph launch per call"}
 
 
 def serving_bench(args, dev):
@@ -317,14 +454,23 @@ def main():
                      "algorithmic_bytes_per_launch": pass_a_bytes},
         "flagged_fraction": round(flagged, 5),
     }
+    if not args.no_ceiling and x.nbytes % 16 == 0:
+        print("# read-only stream ceiling", file=sys.stderr, flush=True)
+        c = read_ceiling(xd[0], dev)
+        c["pass_a_frac_of_ceiling"] = round(achieved / c["GBps"], 4)
+        c["note"] = "library read-only probe (16-byte nontemporal loads, contiguous slab per workgroup)"
+        res["read_ceiling"] = c
+    del xd
+    torch.cuda.empty_cache()
     if not args.no_serving:
         print("# serving: Poisson arrivals from two arrays", file=sys.stderr, flush=True)
-        del xd
-        torch.cuda.empty_cache()
         res["serving"] = serving_bench(args, dev)
+    if not args.no_batched:
+        print("# batched: 32 problems, one graph launch per call", file=sys.stderr, flush=True)
+        res["batched"] = batched_bench(args, dev)
     if not args.no_cpu_baseline:
         print("# timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
-        res["cpu_baseline"] = cpu_baseline(x, w, L, delta, sig, args.cpu_sample_blocks)
+        res["cpu_baseline"] = cpu_baseline(x, w, L, delta, sig, args.cpu_sample_blocks, args.cpu_threads)
     else:
         res["cpu_baseline"] = None
     print(json.dumps(res), flush=True)

@@ -54,6 +54,15 @@ int sk_plan_set_pass_b_tile(sk_plan_t plan, int32_t chunk, int32_t inputs_per_la
 int sk_plan_get_pass_a_tile(sk_plan_t plan, const uint8_t* d_packed, int32_t* vec_bytes,
                             int32_t* lanes_per_row, int64_t* workgroups);
 
+/* Read-only stream probe, the practical HBM read ceiling for streaming
+ * kernels such as pass A: reads the `bytes` bytes at device pointer d_x once
+ * (16-byte nontemporal loads, one contiguous slab per workgroup of 256
+ * lanes) and writes one XOR word per lane to d_sink, which must hold
+ * workgroups * 256 uint32 words. Needs a 16-byte aligned d_x and
+ * bytes % 16 == 0, else SK_ERR_INVALID_ARG. Asynchronous on `stream`; the
+ * caller times it. The sink's contents carry no meaning. */
+int sk_read_probe(const uint8_t* d_x, int64_t bytes, int32_t workgroups, uint32_t* d_sink, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

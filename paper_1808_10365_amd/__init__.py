@@ -108,6 +108,7 @@ def load_library():
     lib.sk_batch_get_tiles.argtypes = [VP, I32, ctypes.POINTER(I32), ctypes.POINTER(I32)]
     lib.sk_batch_destroy.argtypes = [VP]
     lib.sk_batch_get_state.argtypes = [VP, I32, ctypes.POINTER(I32)]
+    lib.sk_read_probe.argtypes = [VP, I64, I32, VP, VP]
     lib.sk_server_now.restype = ctypes.c_double
     lib.sk_server_create.argtypes = [ctypes.POINTER(ServerDesc), ctypes.POINTER(VP)]
     lib.sk_server_add_array.argtypes = [VP, ctypes.POINTER(PlanDesc), ctypes.POINTER(I32)]
@@ -134,7 +135,7 @@ def load_library():
     for name in ("sk_plan_create", "sk_plan_destroy", "sk_plan_device_bytes", "sk_compute", "sk_flags",
                  "sk_state_reset", "sk_state_size", "sk_state_export", "sk_state_import",
                  "sk_digitised_expectation", "sk_plan_set_pass_a_tile", "sk_plan_get_pass_a_tile",
-                 "sk_profile_enable", "sk_profile_read", "sk_plan_set_pass_a_variant"):
+                 "sk_profile_enable", "sk_profile_read", "sk_plan_set_pass_a_variant", "sk_read_probe"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -181,6 +182,16 @@ def calibrate_mc(n_inputs: int, block_len: int, sigma: float, n_sim: int, seed: 
     vals = torch.empty(int(n_sim), dtype=torch.float64, device=device) if return_values else None
     _check(load_library().sk_calibrate_mc(ctypes.byref(d), m.ctypes.data, _ptr(vals), _stream_handle(None)))
     return (m, vals) if return_values else m
+
+
+def read_probe(x: torch.Tensor, workgroups: int, sink: torch.Tensor,
+               stream: Optional[torch.cuda.Stream] = None):
+    """Launch the read-only stream probe over the bytes of ``x`` (16-byte
+    aligned, size a multiple of 16) on ``stream``; ``sink`` is a device int32
+    tensor of at least workgroups * 256 elements."""
+    assert x.is_contiguous() and sink.dtype == torch.int32 and sink.numel() >= workgroups * 256
+    _check(load_library().sk_read_probe(_ptr(x), x.numel() * x.element_size(), int(workgroups), _ptr(sink),
+                                        _stream_handle(stream)))
 
 
 def channel_stats(v: torch.Tensor, block_len: int, stream: Optional[torch.cuda.Stream] = None):
