@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--variant", type=int, default=-1, help="force pass A row batching variant (0..11; -1 = library choice)")
     ap.add_argument("--grid", type=int, default=0, help="force pass A workgroup count (persistent loop)")
     ap.add_argument("--chunk", type=int, default=0, help="force pass B chunk length (blocks)")
-    ap.add_argument("--bvec", type=int, default=0, help="force pass B inputs per lane (1 or 4)")
+    ap.add_argument("--bvec", type=int, default=0, help="force pass B inputs per lane (1, 4 or 8)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
     ap.add_argument("--serving-frames", type=int, default=10000)
     ap.add_argument("--serving-loads", default="0.3,0.6,0.9",

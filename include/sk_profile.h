@@ -46,7 +46,8 @@ int sk_plan_set_pass_a_tile(sk_plan_t plan, int32_t lanes_per_row);
 int sk_plan_set_pass_a_variant(sk_plan_t plan, int32_t variant, int32_t grid);
 
 /* Pass B's chunk length (blocks per wavefront, power of two; 0 keeps the
- * library's choice) and inputs per lane (1 or 4; 0 = library choice). */
+ * library's choice) and inputs per lane (1, 4 or 8; 0 = library choice; 8
+ * needs N % 8 == 0 and 32-byte aligned sums, else the library's choice). */
 int sk_plan_set_pass_b_tile(sk_plan_t plan, int32_t chunk, int32_t inputs_per_lane);
 
 /* Pass A's lanes per row and workgroup count for the next call (after

@@ -236,7 +236,7 @@ int sk_plan_set_pass_a_variant(sk_plan_t p, int32_t variant, int32_t grid) {
 
 int sk_plan_set_pass_b_tile(sk_plan_t p, int32_t chunk, int32_t vec) {
   clear_error();
-  if (!p || chunk < 0 || chunk > 1024 || (chunk & (chunk - 1)) || (vec != 0 && vec != 1 && vec != 4)) {
+  if (!p || chunk < 0 || chunk > 1024 || (chunk & (chunk - 1)) || (vec != 0 && vec != 1 && vec != 4 && vec != 8)) {
     set_error("bad pass B tile");
     return SK_ERR_INVALID_ARG;
   }
@@ -358,6 +358,8 @@ int sk_compute(sk_plan_t p, const uint8_t* d_packed, const uint8_t* d_mask, cons
   a.vec = pass_b_vec((int32_t)N);
   if (((uintptr_t)s1 | (uintptr_t)s2 | (uintptr_t)outs->sk_i) % 16 != 0) a.vec = 1;
   if (p->pass_b_vec == 1) a.vec = 1;
+  if (p->pass_b_vec == 8 && a.vec == 4 && N % 8 == 0 && ((uintptr_t)s1 | (uintptr_t)s2 | (uintptr_t)outs->sk_i) % 32 == 0)
+    a.vec = 8;
   a.n_groups = (int32_t)((N + 64 * a.vec - 1) / (64 * a.vec));
   a.estimator = d.estimator;
   a.k_sigma = d.k_sigma;

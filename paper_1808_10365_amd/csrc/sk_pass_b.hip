@@ -35,6 +35,8 @@ __global__ __launch_bounds__(256) void chunk_sum_kernel_1(PassBArgs a) { chunk_s
 __global__ __launch_bounds__(256) void chunk_sum_kernel_4(PassBArgs a) { chunk_sum_body<4>(a, blockIdx.x, blockIdx.y, blockIdx.z); }
 __global__ __launch_bounds__(256) void partial_kernel_1(PassBArgs a) { partial_body<1>(a, blockIdx.x, blockIdx.y, blockIdx.z); }
 __global__ __launch_bounds__(256) void partial_kernel_4(PassBArgs a) { partial_body<4>(a, blockIdx.x, blockIdx.y, blockIdx.z); }
+__global__ __launch_bounds__(256) void chunk_sum_kernel_8(PassBArgs a) { chunk_sum_body<8>(a, blockIdx.x, blockIdx.y, blockIdx.z); }
+__global__ __launch_bounds__(256) void partial_kernel_8(PassBArgs a) { partial_body<8>(a, blockIdx.x, blockIdx.y, blockIdx.z); }
 __global__ __launch_bounds__(256) void finalize_kernel(PassBArgs a) { finalize_body(a, blockIdx.x); }
 __global__ __launch_bounds__(256) void hist_copy_kernel(PassBArgs a) { hist_copy_body(a, blockIdx.x, blockIdx.y, blockIdx.z); }
 
@@ -43,7 +45,8 @@ static int launch_v(const PassBArgs& a, hipStream_t s) {
   const int F = a.n_channels;
   const int zc = (a.n_inputs + 256 * V - 1) / (256 * V);
   if (a.window >= 2) {
-    if (V == 4) chunk_sum_kernel_4<<<dim3(a.n_chunks, F, zc), dim3(256), 0, s>>>(a);
+    if (V == 8) chunk_sum_kernel_8<<<dim3(a.n_chunks, F, zc), dim3(256), 0, s>>>(a);
+    else if (V == 4) chunk_sum_kernel_4<<<dim3(a.n_chunks, F, zc), dim3(256), 0, s>>>(a);
     else chunk_sum_kernel_1<<<dim3(a.n_chunks, F, zc), dim3(256), 0, s>>>(a);
     SK_HIP_TRY(hipGetLastError());
     const int n_old = a.hist_next_len - a.n_blocks;
@@ -52,7 +55,8 @@ static int launch_v(const PassBArgs& a, hipStream_t s) {
       SK_HIP_TRY(hipGetLastError());
     }
   }
-  if (V == 4) partial_kernel_4<<<dim3(a.n_chunks, F, (a.n_groups + 3) / 4), dim3(256), 0, s>>>(a);
+  if (V == 8) partial_kernel_8<<<dim3(a.n_chunks, F, (a.n_groups + 3) / 4), dim3(256), 0, s>>>(a);
+  else if (V == 4) partial_kernel_4<<<dim3(a.n_chunks, F, (a.n_groups + 3) / 4), dim3(256), 0, s>>>(a);
   else partial_kernel_1<<<dim3(a.n_chunks, F, (a.n_groups + 3) / 4), dim3(256), 0, s>>>(a);
   SK_HIP_TRY(hipGetLastError());
   const int64_t fb = (int64_t)F * a.n_blocks;
@@ -65,6 +69,7 @@ int pass_b_vec(int32_t n_inputs) { return n_inputs % 4 == 0 ? 4 : 1; }
 
 int launch_pass_b(const PassBArgs& a, hipStream_t s) {
   if (a.n_blocks <= 0) return SK_OK;
+  if (a.vec == 8) return launch_v<8>(a, s);
   return a.vec == 4 ? launch_v<4>(a, s) : launch_v<1>(a, s);
 }
 

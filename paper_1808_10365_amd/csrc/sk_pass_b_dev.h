@@ -31,6 +31,21 @@ struct IVec<4> {
   }
 };
 
+template <>
+struct IVec<8> {
+  int32_t v[8];
+  __device__ __forceinline__ void load(const int32_t* p) {
+    const int4 q = *reinterpret_cast<const int4*>(p);
+    const int4 r = *reinterpret_cast<const int4*>(p + 4);
+    v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+    v[4] = r.x; v[5] = r.y; v[6] = r.z; v[7] = r.w;
+  }
+  __device__ __forceinline__ void store(int32_t* p) const {
+    *reinterpret_cast<int4*>(p) = make_int4(v[0], v[1], v[2], v[3]);
+    *reinterpret_cast<int4*>(p + 4) = make_int4(v[4], v[5], v[6], v[7]);
+  }
+};
+
 // Row of S1 for sequence position e (history or this call), channel f.
 __device__ __forceinline__ const int32_t* seq_row(const PassBArgs& a, int f, int64_t e) {
   if (e < a.hist_len) return a.hist + ((int64_t)f * a.hist_cap + e) * a.n_inputs;

@@ -7,6 +7,8 @@ configuration the benchmark times.
 import os
 import sys
 
+from types import SimpleNamespace
+
 import numpy as np
 import pytest
 
@@ -316,19 +318,21 @@ def test_false_alarm_thresholds(L, est):
     assert np.array_equal(fl2[clear], f0[clear])
 
 
-@pytest.mark.parametrize("chunk,vec", [(1, 4), (2, 1), (8, 4), (64, 1), (128, 4)])
-def test_pass_b_tiles(chunk, vec):
+@pytest.mark.parametrize("chunk,vec", [(1, 4), (2, 1), (8, 4), (64, 1), (128, 4), (4, 8), (16, 8), (32, 8)])
+@pytest.mark.parametrize("N", [96, 1040])
+def test_pass_b_tiles(chunk, vec, N):
     # Every chunk length and lane width gives the oracle's results, across
-    # calls (history) and with a window longer than the chunk.
-    N, F, M, L = 96, 3, 32, 9
+    # calls (history) and with a window longer than the chunk; N = 1040 leaves
+    # a partial group of inputs for every lane width.
+    F, M, L = 3, 32, 9
     T = 32 * 20
     x = synth.generate(synth.Workload("pb", N, F, 3 * T, M, 8, np.full(N, 2.2), []), nthreads=2)
     ref = oracle.sk(x, M, L)
     p = sk.Plan(N, F, T, M, norm_window=L)
     p.set_pass_b_tile(chunk, vec)
-    vs = []
-    for k in range(3):
-        out = p.compute(torch.from_numpy(x[k * T:(k + 1) * T].copy()).to(DEV))
-        vs.append(out.v.cpu().numpy())
-    v = np.concatenate(vs, axis=1)
-    assert np.allclose(v, ref.V, rtol=0, atol=1e-6)
+    outs = [p.compute(torch.from_numpy(x[k * T:(k + 1) * T].copy()).to(DEV), want=sk.ALL_OUTPUTS)
+            for k in range(3)]
+    torch.cuda.synchronize()
+    cat = {name: torch.cat([getattr(o, name) for o in outs], dim=1) for name in sk.ALL_OUTPUTS}
+    check_result(SimpleNamespace(**cat), ref, M, L, what=f"pass B chunk={chunk} vec={vec} N={N}")
+    p.close()
