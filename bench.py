@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--lpr", type=int, default=0, help="force pass A lanes per row")
     ap.add_argument("--variant", type=int, default=-1, help="force pass A row batching variant (0..11; -1 = library choice)")
     ap.add_argument("--grid", type=int, default=0, help="force pass A workgroup count (persistent loop)")
+    ap.add_argument("--segments", type=int, default=0,
+                    help="block segments per call (0 = library choice, 1 = pass B after pass A)")
     ap.add_argument("--chunk", type=int, default=0, help="force pass B chunk length (blocks)")
     ap.add_argument("--bvec", type=int, default=0, help="force pass B inputs per lane (1, 4 or 8)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
@@ -356,6 +358,8 @@ def main():
         plan.set_pass_a_variant(args.variant, args.grid)
     if args.chunk or args.bvec:
         plan.set_pass_b_tile(args.chunk, args.bvec)
+    if args.segments:
+        plan.set_segments(args.segments)
     # Inputs resident in HBM. Inputs smaller than the 256 MB last-level cache
     # rotate over enough copies that repeats cannot be served from it.
     nbuf = max(1, int(np.ceil(1.0e9 / x.nbytes))) if x.nbytes < 1 << 30 else 1
@@ -412,8 +416,12 @@ def main():
     fbn = w.n_channels * B * w.n_inputs
     # Pass A algorithmic bytes per launch: every input byte once, 8 B of
     # per-input sums (S1, S2 int32) per (channel, block, input).
-    pass_a_bytes = in_bytes + 8 * fbn
-    a_avg = float(ms_a.mean())
+    # A call runs pass A as `launches` kernels over consecutive block ranges
+    # of (near) equal size; per launch: the call's bytes and pass A time over
+    # the launch count.
+    launches = max(1, plan.last_segments())
+    pass_a_bytes = (in_bytes + 8 * fbn) / launches
+    a_avg = float(ms_a.mean()) / launches
     achieved = pass_a_bytes / (a_avg * 1e-3) / 1e9
     traffic = traffic_from_profile(args.workload, pass_a_bytes)
     step_ms = ms_a + ms_b
@@ -446,12 +454,15 @@ def main():
         "frame_latency_ms": {"p50": round(float(np.percentile(step_ms, 50)), 4),
                              "p99": round(float(np.percentile(step_ms, 99)), 4),
                              "note": "device time of one sk_compute (pass A + pass B), HIP events"},
-        "pass_ms": {"pass_a_avg": round(a_avg, 4), "pass_b_avg": round(float(ms_b.mean()), 4)},
+        "pass_ms": {"pass_a_avg": round(float(ms_a.mean()), 4), "pass_b_avg": round(float(ms_b.mean()), 4),
+                    "pass_a_launches": launches,
+                    "note": "pass A: all of a call's pass A launches; pass B: what is left after them "
+                            "(pass B of earlier segments overlaps pass A on a second stream)"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
                      "kernel": "pass_a_kernel (per-input block sums)",
-                     "algorithmic_bytes_per_launch": pass_a_bytes},
+                     "algorithmic_bytes_per_launch": round(pass_a_bytes), "launches_per_step": launches},
         "flagged_fraction": round(flagged, 5),
     }
     if not args.no_ceiling and x.nbytes % 16 == 0:

@@ -45,6 +45,21 @@ int sk_plan_set_pass_a_tile(sk_plan_t plan, int32_t lanes_per_row);
  * to 256 for them. */
 int sk_plan_set_pass_a_variant(sk_plan_t plan, int32_t variant, int32_t grid);
 
+/* Block segments per call (1..64; 0 = library choice, currently 1: on
+ * MI355X the extra pass A launches cost more than the overlap gains for the
+ * CHIME shapes). With K > 1 a call
+ * runs pass A over K consecutive block ranges on the caller's stream and
+ * pass B of each range on a plan-owned stream as soon as that range's pass A
+ * is done, so pass B overlaps the next range's pass A; the caller's stream
+ * then waits for the last pass B. Results are identical for every K. The
+ * plan stream is created on the first segmented call made outside stream
+ * capture (a call under capture before that runs unsegmented). */
+int sk_plan_set_segments(sk_plan_t plan, int32_t segments);
+
+/* Segments (pass A launches) the plan's last sk_compute used; 0 before the
+ * first call. */
+int sk_plan_get_last_segments(sk_plan_t plan, int32_t* segments);
+
 /* Pass B's chunk length (blocks per wavefront, power of two; 0 keeps the
  * library's choice) and inputs per lane (1, 4 or 8; 0 = library choice; 8
  * needs N % 8 == 0 and 32-byte aligned sums, else the library's choice). */

@@ -109,6 +109,8 @@ def load_library():
     lib.sk_batch_destroy.argtypes = [VP]
     lib.sk_batch_get_state.argtypes = [VP, I32, ctypes.POINTER(I32)]
     lib.sk_read_probe.argtypes = [VP, I64, I32, VP, VP]
+    lib.sk_plan_set_segments.argtypes = [VP, I32]
+    lib.sk_plan_get_last_segments.argtypes = [VP, ctypes.POINTER(I32)]
     lib.sk_server_now.restype = ctypes.c_double
     lib.sk_server_create.argtypes = [ctypes.POINTER(ServerDesc), ctypes.POINTER(VP)]
     lib.sk_server_add_array.argtypes = [VP, ctypes.POINTER(PlanDesc), ctypes.POINTER(I32)]
@@ -135,7 +137,8 @@ def load_library():
     for name in ("sk_plan_create", "sk_plan_destroy", "sk_plan_device_bytes", "sk_compute", "sk_flags",
                  "sk_state_reset", "sk_state_size", "sk_state_export", "sk_state_import",
                  "sk_digitised_expectation", "sk_plan_set_pass_a_tile", "sk_plan_get_pass_a_tile",
-                 "sk_profile_enable", "sk_profile_read", "sk_plan_set_pass_a_variant", "sk_read_probe"):
+                 "sk_profile_enable", "sk_profile_read", "sk_plan_set_pass_a_variant", "sk_read_probe", "sk_plan_set_segments",
+                 "sk_plan_get_last_segments"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -272,6 +275,17 @@ class Plan:
         lo, hi = ctypes.c_double(), ctypes.c_double()
         _check(self._lib.sk_plan_get_thresholds(self.handle, int(n_eff), ctypes.byref(lo), ctypes.byref(hi)))
         return lo.value, hi.value
+
+    def set_segments(self, segments: int):
+        """Block segments per call (0: library choice, 1: none); pass B of each
+        segment overlaps pass A of the next on a plan-owned stream."""
+        _check(self._lib.sk_plan_set_segments(self.handle, int(segments)))
+
+    def last_segments(self) -> int:
+        """Segments (pass A launches) of the last call."""
+        k = ctypes.c_int32()
+        _check(self._lib.sk_plan_get_last_segments(self.handle, ctypes.byref(k)))
+        return k.value
 
     def set_pass_a_variant(self, variant: int, grid: int = 0):
         """Row batching variant of pass A (-1: library choice, 0..11) and workgroup

@@ -55,6 +55,10 @@ struct sk_plan_s {
   int pass_a_variant = -1; // row batching variant of pass A; -1 = heuristic
   int pass_a_grid;         // 0 = one workgroup per task
   int pass_b_vec;          // 0 = library choice, else 1 or 4 inputs per lane
+  int segments = 0;        // block segments per call (0 = library choice, 1 = none)
+  int last_segments = 0;   // segments the last call used
+  hipStream_t side = nullptr;          // pass B of segmented calls
+  std::vector<hipEvent_t> seg_ev;      // pass A segment k done (on the caller's stream); last: join
   std::vector<hipEvent_t> prof;   // 3 events per recorded call
   double* thresholds;             // [N + 1][2] false-alarm thresholds by N_eff, or null
   double fap;
@@ -100,6 +104,10 @@ static void free_profile(sk_plan_s* p) {
 
 static void free_plan_memory(sk_plan_s* p) {
   free_profile(p);
+  for (hipEvent_t e : p->seg_ev) (void)hipEventDestroy(e);
+  p->seg_ev.clear();
+  if (p->side) (void)hipStreamDestroy(p->side);
+  p->side = nullptr;
   if (p->thresholds) (void)hipFree(p->thresholds);
   if (p->s1_s2_owned) {
     if (p->s1) (void)hipFree(p->s1);
@@ -212,6 +220,7 @@ static PassAConfig plan_pass_a_config(const sk_plan_s* p, const uint8_t* d_packe
   const int vec = pick_vec(d_packed, (int32_t)N);
   t->row_bytes = F * N;
   t->n_inputs = (int32_t)N;
+  t->block0 = 0;
   t->block_len = p->d.block_len;
   t->n_blocks = (int32_t)B;
   PassAConfig c = default_pass_a_config(vec, t->row_bytes, B, p->pass_a_lpr == 0 && p->pass_a_variant < 0);
@@ -231,6 +240,20 @@ int sk_plan_set_pass_a_variant(sk_plan_t p, int32_t variant, int32_t grid) {
   if (!p || variant < -1 || variant > 11 || grid < 0) { set_error("bad variant"); return SK_ERR_INVALID_ARG; }
   p->pass_a_variant = variant;
   p->pass_a_grid = grid;
+  return SK_OK;
+}
+
+int sk_plan_set_segments(sk_plan_t p, int32_t segments) {
+  clear_error();
+  if (!p || segments < 0 || segments > 64) { set_error("segments must be in 0..64"); return SK_ERR_INVALID_ARG; }
+  p->segments = segments;
+  return SK_OK;
+}
+
+int sk_plan_get_last_segments(sk_plan_t p, int32_t* segments) {
+  clear_error();
+  if (!p || !segments) { set_error("NULL argument"); return SK_ERR_INVALID_ARG; }
+  *segments = p->last_segments;
   return SK_OK;
 }
 
@@ -314,11 +337,6 @@ int sk_compute(sk_plan_t p, const uint8_t* d_packed, const uint8_t* d_mask, cons
   t.x = d_packed;
   t.s1 = s1;
   t.s2 = s2;
-  const bool rec = p->prof_n < p->prof_max;
-  if (rec) SK_HIP_TRY(hipEventRecord(p->prof[3 * p->prof_n], s));
-  int rc = launch_pass_a(t, c, s);
-  if (rc) return rc;
-  if (rec) SK_HIP_TRY(hipEventRecord(p->prof[3 * p->prof_n + 1], s));
 
   PassBArgs a;
   memset(&a, 0, sizeof a);
@@ -365,8 +383,86 @@ int sk_compute(sk_plan_t p, const uint8_t* d_packed, const uint8_t* d_mask, cons
   a.k_sigma = d.k_sigma;
   a.expect_offset = d.expect_offset;
   a.sigma_override = d.sigma_override;
-  rc = launch_pass_b(a, s);
-  if (rc) return rc;
+
+  // Segments: pass B of blocks [b_k, b_k+1) needs S1 of those blocks and of
+  // earlier ones only, so it can run on a second stream while pass A streams
+  // the next segment. Boundaries sit on chunk boundaries of the sequence
+  // (history + this call), so each segment's chunk sums read finished rows.
+  int K = p->segments;
+  // Library choice: one segment. Measured on MI355X (CHIME shapes), every
+  // extra pass A launch adds a drain of its last workgroups (each streams
+  // about 1 MiB, tens of microseconds) while pass B, latency-bound, takes
+  // nearly as long for a quarter of the blocks as for all of them.
+  if (K == 0) K = 1;
+  if (K > a.n_chunks) K = a.n_chunks;
+  if (K > 1 && !p->side) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    SK_HIP_TRY(hipStreamIsCapturing(s, &cs));
+    if (cs != hipStreamCaptureStatusNone) {
+      K = 1;   // no stream creation under capture; later calls segment
+    } else {
+      SK_HIP_TRY(hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking));
+    }
+  }
+  if (K > 1 && (int)p->seg_ev.size() < K + 1) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    SK_HIP_TRY(hipStreamIsCapturing(s, &cs));
+    if (cs != hipStreamCaptureStatusNone) {
+      K = 1;
+    } else {
+      while ((int)p->seg_ev.size() < K + 1) {
+        hipEvent_t e;
+        SK_HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        p->seg_ev.push_back(e);
+      }
+    }
+  }
+
+  p->last_segments = K < 1 ? 1 : K;
+  const bool rec = p->prof_n < p->prof_max;
+  if (rec) SK_HIP_TRY(hipEventRecord(p->prof[3 * p->prof_n], s));
+  int rc = SK_OK;
+  if (K <= 1) {
+    rc = launch_pass_a(t, c, s);
+    if (rc) return rc;
+    if (rec) SK_HIP_TRY(hipEventRecord(p->prof[3 * p->prof_n + 1], s));
+    rc = launch_pass_b(a, s);
+    if (rc) return rc;
+  } else {
+    const int64_t H = p->hist_len, R = p->chunk;
+    int32_t c_prev = 0;
+    int32_t b_prev = 0;
+    for (int k = 0; k < K; ++k) {
+      int32_t c_next = a.n_chunks;
+      if (k + 1 < K) {
+        const int64_t target = H + (int64_t)B * (k + 1) / K;     // sequence position
+        int64_t cn = (target + R / 2) / R;
+        if (cn < c_prev) cn = c_prev;
+        if (cn > a.n_chunks) cn = a.n_chunks;
+        c_next = (int32_t)cn;
+      }
+      int64_t bn = (int64_t)c_next * R - H;
+      if (k + 1 == K || bn > B) bn = B;
+      if (bn < b_prev) bn = b_prev;
+      const int32_t b_next = (int32_t)bn;
+      if (b_next > b_prev) {
+        PassATask ts = t;
+        ts.block0 = b_prev;
+        ts.n_tasks = (int64_t)(b_next - b_prev) * t.chunks;
+        rc = launch_pass_a(ts, c, s);
+        if (rc) return rc;
+      }
+      SK_HIP_TRY(hipEventRecord(p->seg_ev[k], s));
+      SK_HIP_TRY(hipStreamWaitEvent(p->side, p->seg_ev[k], 0));
+      rc = launch_pass_b_range(a, c_prev, c_next, b_prev, b_next, k == 0, p->side);
+      if (rc) return rc;
+      c_prev = c_next;
+      b_prev = b_next;
+    }
+    if (rec) SK_HIP_TRY(hipEventRecord(p->prof[3 * p->prof_n + 1], s));
+    SK_HIP_TRY(hipEventRecord(p->seg_ev[K], p->side));
+    SK_HIP_TRY(hipStreamWaitEvent(s, p->seg_ev[K], 0));
+  }
   if (rec) {
     SK_HIP_TRY(hipEventRecord(p->prof[3 * p->prof_n + 2], s));
     p->prof_n += 1;

@@ -85,6 +85,9 @@ __device__ __forceinline__ PassBArgs make_args(const BatchProb& P, const BatchSt
   a.n_chunks = (int32_t)((total + P.chunk - 1) / P.chunk);
   a.n_groups = P.n_groups;
   a.vec = 4;
+  a.chunk0 = 0;
+  a.fin_b0 = 0;
+  a.fin_nb = P.a.n_blocks;
   a.estimator = P.estimator;
   a.k_sigma = P.k_sigma;
   a.expect_offset = P.expect_offset;

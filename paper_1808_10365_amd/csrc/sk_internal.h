@@ -42,7 +42,8 @@ struct PassATask {
   int32_t n_blocks;     // B
   int32_t col_groups;   // G / VEC
   int32_t chunks;       // ceil(col_groups / (LPR * groups per lane))
-  int64_t n_tasks;      // B * chunks
+  int64_t n_tasks;      // blocks of this launch * chunks
+  int32_t block0;       // first block of this launch (tasks cover blocks block0 ..)
 };
 
 struct PassAConfig {
@@ -93,11 +94,20 @@ struct PassBArgs {
   const double* thresholds;  // [N + 1][2] (lo, hi) by N_eff, or null: E -+ k sigma
   int32_t n_inputs, n_channels, n_blocks, block_len, window, hist_len, hist_cap, hist_next_len;
   int32_t chunk, n_chunks, n_groups, vec, estimator;
+  // Range of one launch sequence: chunks [chunk0, chunk0 + grid) of the
+  // chunk-sum and partial kernels, blocks [fin_b0, fin_b0 + fin_nb) of the
+  // finalize kernel (a whole call: 0, n_chunks, 0, n_blocks).
+  int32_t chunk0, fin_b0, fin_nb;
   double k_sigma, expect_offset, sigma_override;
 };
 
 int pass_b_vec(int32_t n_inputs);
 int launch_pass_b(const PassBArgs& a, hipStream_t s);
+// Pass B kernels for chunks [c_begin, c_end) and blocks [b_begin, b_end) of
+// one call; the history carry (when a call is shorter than the window) runs
+// with the range that has with_hist_copy set.
+int launch_pass_b_range(PassBArgs a, int32_t c_begin, int32_t c_end, int32_t b_begin, int32_t b_end,
+                        bool with_hist_copy, hipStream_t s);
 
 double pearson3_quantile(double mean, double sd, double skew, double p);
 

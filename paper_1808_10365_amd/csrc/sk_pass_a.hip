@@ -84,7 +84,7 @@ __global__ __launch_bounds__(wg_size<LPR>()) void pass_a_kernel(PassATask t) {
   const int64_t G = t.row_bytes;
 
   for (int64_t task = blockIdx.x; task < t.n_tasks; task += gridDim.x) {
-    const int b = (int)(task / t.chunks);
+    const int b = t.block0 + (int)(task / t.chunks);
     const int ch = (int)(task % t.chunks);
     const int g0 = ch * LPR * GPL + lc;
     uint32_t s1[GPL][VEC], s2[GPL][VEC];

@@ -31,46 +31,64 @@
 
 namespace sk {
 
-__global__ __launch_bounds__(256) void chunk_sum_kernel_1(PassBArgs a) { chunk_sum_body<1>(a, blockIdx.x, blockIdx.y, blockIdx.z); }
-__global__ __launch_bounds__(256) void chunk_sum_kernel_4(PassBArgs a) { chunk_sum_body<4>(a, blockIdx.x, blockIdx.y, blockIdx.z); }
-__global__ __launch_bounds__(256) void partial_kernel_1(PassBArgs a) { partial_body<1>(a, blockIdx.x, blockIdx.y, blockIdx.z); }
-__global__ __launch_bounds__(256) void partial_kernel_4(PassBArgs a) { partial_body<4>(a, blockIdx.x, blockIdx.y, blockIdx.z); }
-__global__ __launch_bounds__(256) void chunk_sum_kernel_8(PassBArgs a) { chunk_sum_body<8>(a, blockIdx.x, blockIdx.y, blockIdx.z); }
-__global__ __launch_bounds__(256) void partial_kernel_8(PassBArgs a) { partial_body<8>(a, blockIdx.x, blockIdx.y, blockIdx.z); }
+__global__ __launch_bounds__(256) void chunk_sum_kernel_1(PassBArgs a) { chunk_sum_body<1>(a, a.chunk0 + blockIdx.x, blockIdx.y, blockIdx.z); }
+__global__ __launch_bounds__(256) void chunk_sum_kernel_4(PassBArgs a) { chunk_sum_body<4>(a, a.chunk0 + blockIdx.x, blockIdx.y, blockIdx.z); }
+__global__ __launch_bounds__(256) void partial_kernel_1(PassBArgs a) { partial_body<1>(a, a.chunk0 + blockIdx.x, blockIdx.y, blockIdx.z); }
+__global__ __launch_bounds__(256) void partial_kernel_4(PassBArgs a) { partial_body<4>(a, a.chunk0 + blockIdx.x, blockIdx.y, blockIdx.z); }
+__global__ __launch_bounds__(256) void chunk_sum_kernel_8(PassBArgs a) { chunk_sum_body<8>(a, a.chunk0 + blockIdx.x, blockIdx.y, blockIdx.z); }
+__global__ __launch_bounds__(256) void partial_kernel_8(PassBArgs a) { partial_body<8>(a, a.chunk0 + blockIdx.x, blockIdx.y, blockIdx.z); }
 __global__ __launch_bounds__(256) void finalize_kernel(PassBArgs a) { finalize_body(a, blockIdx.x); }
 __global__ __launch_bounds__(256) void hist_copy_kernel(PassBArgs a) { hist_copy_body(a, blockIdx.x, blockIdx.y, blockIdx.z); }
 
 template <int V>
-static int launch_v(const PassBArgs& a, hipStream_t s) {
+static int launch_v(const PassBArgs& a0, int32_t c_begin, int32_t c_end, int32_t b_begin, int32_t b_end,
+                    bool with_hist_copy, hipStream_t s) {
+  PassBArgs a = a0;
   const int F = a.n_channels;
+  const int nc = c_end - c_begin;
+  a.chunk0 = c_begin;
+  a.fin_b0 = b_begin;
+  a.fin_nb = b_end - b_begin;
   const int zc = (a.n_inputs + 256 * V - 1) / (256 * V);
   if (a.window >= 2) {
-    if (V == 8) chunk_sum_kernel_8<<<dim3(a.n_chunks, F, zc), dim3(256), 0, s>>>(a);
-    else if (V == 4) chunk_sum_kernel_4<<<dim3(a.n_chunks, F, zc), dim3(256), 0, s>>>(a);
-    else chunk_sum_kernel_1<<<dim3(a.n_chunks, F, zc), dim3(256), 0, s>>>(a);
-    SK_HIP_TRY(hipGetLastError());
+    if (nc > 0) {
+      if (V == 8) chunk_sum_kernel_8<<<dim3(nc, F, zc), dim3(256), 0, s>>>(a);
+      else if (V == 4) chunk_sum_kernel_4<<<dim3(nc, F, zc), dim3(256), 0, s>>>(a);
+      else chunk_sum_kernel_1<<<dim3(nc, F, zc), dim3(256), 0, s>>>(a);
+      SK_HIP_TRY(hipGetLastError());
+    }
     const int n_old = a.hist_next_len - a.n_blocks;
-    if (n_old > 0) {
+    if (with_hist_copy && n_old > 0) {
       hist_copy_kernel<<<dim3(n_old, F, (a.n_inputs + 255) / 256), dim3(256), 0, s>>>(a);
       SK_HIP_TRY(hipGetLastError());
     }
   }
-  if (V == 8) partial_kernel_8<<<dim3(a.n_chunks, F, (a.n_groups + 3) / 4), dim3(256), 0, s>>>(a);
-  else if (V == 4) partial_kernel_4<<<dim3(a.n_chunks, F, (a.n_groups + 3) / 4), dim3(256), 0, s>>>(a);
-  else partial_kernel_1<<<dim3(a.n_chunks, F, (a.n_groups + 3) / 4), dim3(256), 0, s>>>(a);
-  SK_HIP_TRY(hipGetLastError());
-  const int64_t fb = (int64_t)F * a.n_blocks;
-  finalize_kernel<<<dim3((unsigned)((fb + 255) / 256)), dim3(256), 0, s>>>(a);
-  SK_HIP_TRY(hipGetLastError());
+  if (nc > 0) {
+    if (V == 8) partial_kernel_8<<<dim3(nc, F, (a.n_groups + 3) / 4), dim3(256), 0, s>>>(a);
+    else if (V == 4) partial_kernel_4<<<dim3(nc, F, (a.n_groups + 3) / 4), dim3(256), 0, s>>>(a);
+    else partial_kernel_1<<<dim3(nc, F, (a.n_groups + 3) / 4), dim3(256), 0, s>>>(a);
+    SK_HIP_TRY(hipGetLastError());
+  }
+  const int64_t fb = (int64_t)F * a.fin_nb;
+  if (fb > 0) {
+    finalize_kernel<<<dim3((unsigned)((fb + 255) / 256)), dim3(256), 0, s>>>(a);
+    SK_HIP_TRY(hipGetLastError());
+  }
   return SK_OK;
 }
 
 int pass_b_vec(int32_t n_inputs) { return n_inputs % 4 == 0 ? 4 : 1; }
 
-int launch_pass_b(const PassBArgs& a, hipStream_t s) {
+int launch_pass_b_range(PassBArgs a, int32_t c_begin, int32_t c_end, int32_t b_begin, int32_t b_end,
+                        bool with_hist_copy, hipStream_t s) {
   if (a.n_blocks <= 0) return SK_OK;
-  if (a.vec == 8) return launch_v<8>(a, s);
-  return a.vec == 4 ? launch_v<4>(a, s) : launch_v<1>(a, s);
+  if (a.vec == 8) return launch_v<8>(a, c_begin, c_end, b_begin, b_end, with_hist_copy, s);
+  if (a.vec == 4) return launch_v<4>(a, c_begin, c_end, b_begin, b_end, with_hist_copy, s);
+  return launch_v<1>(a, c_begin, c_end, b_begin, b_end, with_hist_copy, s);
+}
+
+int launch_pass_b(const PassBArgs& a, hipStream_t s) {
+  return launch_pass_b_range(a, 0, a.n_chunks, 0, a.n_blocks, true, s);
 }
 
 __global__ __launch_bounds__(256) void flags_kernel(FlagArgs a) {

@@ -332,8 +332,8 @@ __device__ __forceinline__ void finish(const PassBArgs& a, int f, int b, double 
 
 __device__ __forceinline__ void finalize_body(const PassBArgs& a, int64_t blk) {
   const int64_t j = blk * 256 + threadIdx.x;
-  if (j >= (int64_t)a.n_channels * a.n_blocks) return;
-  const int f = (int)(j / a.n_blocks), b = (int)(j % a.n_blocks);
+  if (j >= (int64_t)a.n_channels * a.fin_nb) return;
+  const int f = (int)(j / a.fin_nb), b = a.fin_b0 + (int)(j % a.fin_nb);
   double A = 0.0, Bq = 0.0;
   int64_t R1 = 0, R2 = 0;
   int32_t n = 0;

@@ -336,3 +336,31 @@ def test_pass_b_tiles(chunk, vec, N):
     cat = {name: torch.cat([getattr(o, name) for o in outs], dim=1) for name in sk.ALL_OUTPUTS}
     check_result(SimpleNamespace(**cat), ref, M, L, what=f"pass B chunk={chunk} vec={vec} N={N}")
     p.close()
+
+
+@pytest.mark.parametrize("K", [2, 3, 4, 7, 64])
+@pytest.mark.parametrize("L", [0, 1, 5, 40, 80])
+def test_segmented_calls(K, L):
+    # Pass B of each block segment runs on the plan's second stream while
+    # pass A streams the next segment. Every output equals the unsegmented
+    # plan's bit for bit and the oracle's to the usual bar, over three calls
+    # (L = 80 > B: the history carry runs too; K = 64 exceeds the chunk count).
+    N, F, M = 96, 3, 32
+    T = 32 * 50
+    x = synth.generate(synth.Workload("seg", N, F, 3 * T, M, 21 + L, np.full(N, 2.4), []), nthreads=2)
+    ref = oracle.sk(x, M, L)
+    res = {}
+    for k in (K, 1):
+        p = sk.Plan(N, F, T, M, norm_window=L)
+        p.set_segments(k)
+        outs = [p.compute(torch.from_numpy(x[c * T:(c + 1) * T].copy()).to(DEV), want=sk.ALL_OUTPUTS)
+                for c in range(3)]
+        torch.cuda.synchronize()
+        if k > 1:
+            assert 2 <= p.last_segments() <= k
+        res[k] = {name: torch.cat([getattr(o, name) for o in outs], dim=1) for name in sk.ALL_OUTPUTS}
+        p.close()
+    check_result(SimpleNamespace(**res[K]), ref, M, L, what=f"segments={K} L={L}")
+    for name in sk.ALL_OUTPUTS:
+        a, b = res[K][name].cpu().numpy(), res[1][name].cpu().numpy()
+        assert np.array_equal(a, b, equal_nan=a.dtype.kind == "f"), name
