@@ -38,11 +38,13 @@ int sk_plan_set_pass_a_tile(sk_plan_t plan, int32_t lanes_per_row);
  * 8 rows; 6: four groups, 2 rows; 7: power table replicated per lane (64 KiB
  * of LDS, free of bank conflicts), 8 rows; 8: replicated table, two groups,
  * 4 rows; 9: replicated table, 8 rows with prefetch; 10: replicated table,
- * 16 rows; 11: replicated table, 16 rows with prefetch) and workgroup count
- * (0: one per task; fewer: workgroups loop over tasks). Variants 1..11 apply
- * to the 16-byte path (N % 16 == 0, aligned input); the others use variant
- * 0. Variants 7..11 use one row phase, so lanes per row below 256 are raised
- * to 256 for them. */
+ * 16 rows; 11: replicated table, 16 rows with prefetch; 12: replicated table
+ * shared by 512-lane workgroups of 512 / lanes_per_row row phases, 8 rows;
+ * 13: as 12 with two groups, 4 rows) and workgroup count (0: one per task;
+ * fewer: workgroups loop over tasks). Variants 1..13 apply to the 16-byte
+ * path (N % 16 == 0, aligned input); the others use variant 0. Lanes per
+ * row are clamped to 256..1024 for variants 7..11 (one row phase) and to
+ * 64..512 for variants 12 and 13. */
 int sk_plan_set_pass_a_variant(sk_plan_t plan, int32_t variant, int32_t grid);
 
 /* Block segments per call (1..64; 0 = library choice, currently 1: on

@@ -226,7 +226,12 @@ static PassAConfig plan_pass_a_config(const sk_plan_s* p, const uint8_t* d_packe
   PassAConfig c = default_pass_a_config(vec, t->row_bytes, B, p->pass_a_lpr == 0 && p->pass_a_variant < 0);
   if (p->pass_a_lpr) c.lpr = p->pass_a_lpr;
   if (p->pass_a_variant >= 0) c.variant = p->pass_a_variant;
-  if (pass_a_lane_table(vec, c.variant) && c.lpr < 256) c.lpr = 256;
+  {
+    int lo, hi;
+    pass_a_lane_range(vec, c.variant, &lo, &hi);
+    if (c.lpr < lo) c.lpr = lo;
+    if (c.lpr > hi) c.lpr = hi;
+  }
   const int gpl = pass_a_groups_per_lane(vec, c.variant);
   t->col_groups = (int32_t)(t->row_bytes / vec);
   t->chunks = (t->col_groups + c.lpr * gpl - 1) / (c.lpr * gpl);
@@ -237,7 +242,7 @@ static PassAConfig plan_pass_a_config(const sk_plan_s* p, const uint8_t* d_packe
 }
 
 int sk_plan_set_pass_a_variant(sk_plan_t p, int32_t variant, int32_t grid) {
-  if (!p || variant < -1 || variant > 11 || grid < 0) { set_error("bad variant"); return SK_ERR_INVALID_ARG; }
+  if (!p || variant < -1 || variant > 13 || grid < 0) { set_error("bad variant"); return SK_ERR_INVALID_ARG; }
   p->pass_a_variant = variant;
   p->pass_a_grid = grid;
   return SK_OK;

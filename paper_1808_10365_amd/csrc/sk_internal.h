@@ -49,7 +49,7 @@ struct PassATask {
 struct PassAConfig {
   int vec;     // 16, 4 or 1 bytes per lane per row
   int lpr;     // lanes per row: power of two, 1..256
-  int variant; // row batching variant (0..8, 16-byte path; see pass_a_groups_per_lane)
+  int variant; // row batching variant (0..13, 16-byte path; see pass_a_groups_per_lane)
   int grid;    // workgroups launched (<= tasks; grid-stride beyond)
 };
 
@@ -60,6 +60,8 @@ int pass_a_groups_per_lane(int vec, int variant);
 // Whether this variant uses the lane-replicated power table (needs >= 256
 // lanes per row: one row phase).
 bool pass_a_lane_table(int vec, int variant);
+// Lanes per row the variant supports; the planner clamps into [lo, hi].
+void pass_a_lane_range(int vec, int variant, int* lo, int* hi);
 // lane_table: the lane-replicated table variants may be chosen (single-plan
 // kernel only; the batched kernel has its own table).
 PassAConfig default_pass_a_config(int vec, int64_t row_bytes, int64_t n_blocks, bool lane_table);

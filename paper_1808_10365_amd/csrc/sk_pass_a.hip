@@ -56,15 +56,18 @@ __device__ __forceinline__ void store_group(const PassATask& t, int b, int g, co
 // row phase ph owns groups ch * LPR * GPL + j * LPR + lc (j < GPL), so for
 // every j a wavefront's loads of one row are 64 * VEC contiguous bytes.
 //
-// REP selects the lane-replicated 64 KiB power table (16-byte lanes and one
-// row phase only): bank-conflict free whatever the codes, at the price of
-// LDS that limits a CU to two workgroups.
-template <int VEC, int LPR, int U, bool PF, int GPL, bool REP>
-__global__ __launch_bounds__(wg_size<LPR>()) void pass_a_kernel(PassATask t) {
-  constexpr int WG = wg_size<LPR>();
+// REP selects the lane-replicated 64 KiB power table (16-byte lanes only):
+// bank-conflict free whatever the codes, at the price of LDS that limits a
+// CU to two workgroups. With several row phases the table's LDS is reused
+// for their reduction (S1, then S2) and refilled if the workgroup takes
+// another task.
+template <int VEC, int LPR, int U, bool PF, int GPL, bool REP, int WG = wg_size<LPR>()>
+__global__ __launch_bounds__(WG) void pass_a_kernel(PassATask t) {
   constexpr int RP = WG / LPR;          // row phases per workgroup
   constexpr int W = 2 * VEC + 1;        // LDS stride of one lane's partials (odd: no bank conflicts)
-  static_assert(!REP || (VEC == 16 && RP == 1), "lane table: 16-byte lanes, one row phase");
+  static_assert(WG % LPR == 0, "whole row phases");
+  static_assert(!REP || (VEC == 16 && (RP == 1 || WG * (VEC + 1) <= LANE_LUT_DWORDS)),
+                "lane table: 16-byte lanes; the row-phase reduction must fit in the table's LDS");
   __shared__ uint16_t lut16[REP ? 1 : 256];
   __shared__ __attribute__((aligned(16))) uint32_t lut32[REP ? LANE_LUT_DWORDS : 1];
   extern __shared__ uint32_t red[];     // [RP * LPR][W] when RP > 1
@@ -121,6 +124,39 @@ __global__ __launch_bounds__(wg_size<LPR>()) void pass_a_kernel(PassATask t) {
         const int g = g0 + j * LPR;
         if (g < t.col_groups) store_group<VEC>(t, b, g, s1[j], s2[j]);
       }
+    } else if constexpr (REP) {
+      // Every lane is done with the table: reuse it for the reduction, one
+      // sum (S1, then S2) at a time, VEC + 1 words per lane (odd stride).
+      const int N = t.n_inputs;
+      const int B = t.n_blocks;
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < GPL; ++j) {
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+          uint32_t* mine = lut32 + tid * (VEC + 1);
+#pragma unroll
+          for (int k = 0; k < VEC; ++k) mine[k] = half ? s2[j][k] : s1[j][k];
+          __syncthreads();
+          for (int o = tid; o < LPR * VEC; o += WG) {
+            const int l = o / VEC, k = o % VEC;
+            uint32_t sum = 0;
+#pragma unroll
+            for (int q = 0; q < RP; ++q) sum += lut32[(q * LPR + l) * (VEC + 1) + k];
+            const int gg = ch * LPR * GPL + j * LPR + l;
+            if (gg < t.col_groups) {
+              const int64_t col = (int64_t)gg * VEC + k;
+              const int64_t f = col / N, i = col % N;
+              (half ? t.s2 : t.s1)[(f * B + b) * N + i] = (int32_t)sum;
+            }
+          }
+          __syncthreads();
+        }
+      }
+      if (task + gridDim.x < t.n_tasks) {
+        fill_lane_lut<WG>(lut32, tid);
+        __syncthreads();
+      }
     } else {
       const int N = t.n_inputs;
       const int B = t.n_blocks;
@@ -175,6 +211,28 @@ static int launch_rep(const PassATask& t, int lpr, int grid, hipStream_t s) {
   return SK_ERR_INVALID_ARG;
 }
 
+// Lane table shared by 512-lane workgroups of 512 / lpr row phases (16
+// wavefronts per CU at two workgroups); lanes per row 64..512 (the planner
+// clamps others into that range).
+template <int LPR, int U, int GPL>
+static int launch_rep512_one(const PassATask& t, int grid, hipStream_t s) {
+  pass_a_kernel<16, LPR, U, false, GPL, true, 512><<<dim3(grid), dim3(512), 0, s>>>(t);
+  SK_HIP_TRY(hipGetLastError());
+  return SK_OK;
+}
+
+template <int U, int GPL>
+static int launch_rep512(const PassATask& t, int lpr, int grid, hipStream_t s) {
+  switch (lpr) {
+    case 64: return launch_rep512_one<64, U, GPL>(t, grid, s);
+    case 128: return launch_rep512_one<128, U, GPL>(t, grid, s);
+    case 256: return launch_rep512_one<256, U, GPL>(t, grid, s);
+    case 512: return launch_rep512_one<512, U, GPL>(t, grid, s);
+  }
+  set_error("pass A: 512-lane lane-table variant needs 64..512 lanes per row, got %d", lpr);
+  return SK_ERR_INVALID_ARG;
+}
+
 template <int VEC, int U, bool PF, int GPL = 1>
 static int launch_lpr(const PassATask& t, int lpr, int grid, hipStream_t s) {
   switch (lpr) {
@@ -205,16 +263,25 @@ static int launch_lpr(const PassATask& t, int lpr, int grid, hipStream_t s) {
 //   9: lane-replicated power table, 8 rows, next batch prefetched
 //  10: lane-replicated power table, 16 rows per batch
 //  11: lane-replicated power table, 16 rows, next batch prefetched
+//  12: lane-replicated table in 512-lane workgroups (512 / LPR row phases), 8 rows
+//  13: as 12 with 2 column groups per lane, 4 rows
 int pass_a_groups_per_lane(int vec, int variant) {
   if (vec != 16) return 1;
   switch (variant) {
-    case 4: case 5: case 8: return 2;
+    case 4: case 5: case 8: case 13: return 2;
     case 6: return 4;
     default: return 1;
   }
 }
 
-bool pass_a_lane_table(int vec, int variant) { return vec == 16 && variant >= 7 && variant <= 11; }
+bool pass_a_lane_table(int vec, int variant) { return vec == 16 && variant >= 7 && variant <= 13; }
+
+void pass_a_lane_range(int vec, int variant, int* lo, int* hi) {
+  *lo = 1;
+  *hi = 1024;
+  if (!pass_a_lane_table(vec, variant)) return;
+  if (variant >= 12) { *lo = 64; *hi = 512; } else { *lo = 256; }
+}
 
 template <int VEC>
 static int launch_vec(const PassATask& t, int lpr, int variant, int grid, hipStream_t s) {
@@ -231,6 +298,8 @@ static int launch_vec(const PassATask& t, int lpr, int variant, int grid, hipStr
       case 9: return launch_rep<8, 1, true>(t, lpr, grid, s);
       case 10: return launch_rep<16, 1>(t, lpr, grid, s);
       case 11: return launch_rep<16, 1, true>(t, lpr, grid, s);
+      case 12: return launch_rep512<8, 1>(t, lpr, grid, s);
+      case 13: return launch_rep512<4, 2>(t, lpr, grid, s);
       default: break;
     }
   }

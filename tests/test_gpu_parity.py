@@ -92,13 +92,14 @@ def test_ragged_random_bytes(shape, L):
 
 
 @pytest.mark.parametrize("lpr", [1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1024])
-@pytest.mark.parametrize("variant", list(range(12)))
+@pytest.mark.parametrize("variant", list(range(14)))
 def test_every_pass_a_tile(lpr, variant):
     # M = 48 and M = 100 leave partial batches and odd row counts for every
     # row-phase count; rows of 96 and 32 column groups leave the second and
     # later groups of a lane (variants 4..6, 8) partly past the row's end, and
     # the 512-group row fills them exactly at 256 lanes per row. Variants
-    # 7..11 (lane-replicated table) widen tiles below 256 lanes to 256.
+    # 7..11 (lane-replicated table) widen tiles below 256 lanes to 256;
+    # 12 and 13 clamp lanes per row to 64..512 (row phases in 512 lanes).
     rng = np.random.default_rng(lpr + 7 * variant)
     for T, F, N, M in ((96, 3, 512, 48), (200, 2, 256, 100), (64, 4, 2048, 32)):
         x = rng.integers(0, 256, size=(T, F, N), dtype=np.uint8)
@@ -111,7 +112,7 @@ def test_pass_a_persistent_grid(grid):
     rng = np.random.default_rng(grid)
     T, F, N, M = 512, 2, 1024, 64
     x = rng.integers(0, 256, size=(T, F, N), dtype=np.uint8)
-    for variant in (0, 1, 4, 6, 7, 8):
+    for variant in (0, 1, 4, 6, 7, 8, 12, 13):
         both(x, M, 3, what=f"grid={grid} variant={variant}", lpr=64, variant=variant, grid=grid)
 
 
