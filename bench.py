@@ -44,6 +44,7 @@ def parse():
                     help="block segments per call (0 = library choice, 1 = pass B after pass A)")
     ap.add_argument("--chunk", type=int, default=0, help="force pass B chunk length (blocks)")
     ap.add_argument("--bvec", type=int, default=0, help="force pass B inputs per lane (1, 4 or 8)")
+    ap.add_argument("--bdepth", type=int, default=0, help="force pass B blocks loaded together (2, 4, 8)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
     ap.add_argument("--serving-frames", type=int, default=10000)
     ap.add_argument("--serving-loads", default="0.3,0.6,0.9",
@@ -360,6 +361,8 @@ def main():
         plan.set_pass_b_tile(args.chunk, args.bvec)
     if args.segments:
         plan.set_segments(args.segments)
+    if args.bdepth:
+        plan.set_pass_b_depth(args.bdepth)
     # Inputs resident in HBM. Inputs smaller than the 256 MB last-level cache
     # rotate over enough copies that repeats cannot be served from it.
     nbuf = max(1, int(np.ceil(1.0e9 / x.nbytes))) if x.nbytes < 1 << 30 else 1

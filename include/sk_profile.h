@@ -62,6 +62,10 @@ int sk_plan_set_segments(sk_plan_t plan, int32_t segments);
  * first call. */
 int sk_plan_get_last_segments(sk_plan_t plan, int32_t* segments);
 
+/* Blocks whose sums a pass B partial-kernel wavefront loads together (2, 4
+ * or 8; 0 = library choice, 4). Applies to 4 inputs per lane. */
+int sk_plan_set_pass_b_depth(sk_plan_t plan, int32_t depth);
+
 /* Pass B's chunk length (blocks per wavefront, power of two; 0 keeps the
  * library's choice) and inputs per lane (1, 4 or 8; 0 = library choice; 8
  * needs N % 8 == 0 and 32-byte aligned sums, else the library's choice). */

@@ -56,6 +56,7 @@ struct sk_plan_s {
   int pass_a_grid;         // 0 = one workgroup per task
   int pass_b_vec;          // 0 = library choice, else 1 or 4 inputs per lane
   int segments = 0;        // block segments per call (0 = library choice, 1 = none)
+  int pass_b_depth = 0;    // blocks a partial wavefront loads together (0 = library choice)
   int last_segments = 0;   // segments the last call used
   hipStream_t side = nullptr;          // pass B of segmented calls
   std::vector<hipEvent_t> seg_ev;      // pass A segment k done (on the caller's stream); last: join
@@ -255,6 +256,13 @@ int sk_plan_set_segments(sk_plan_t p, int32_t segments) {
   return SK_OK;
 }
 
+int sk_plan_set_pass_b_depth(sk_plan_t p, int32_t depth) {
+  clear_error();
+  if (!p || (depth != 0 && depth != 2 && depth != 4 && depth != 8)) { set_error("depth must be 0, 2, 4 or 8"); return SK_ERR_INVALID_ARG; }
+  p->pass_b_depth = depth;
+  return SK_OK;
+}
+
 int sk_plan_get_last_segments(sk_plan_t p, int32_t* segments) {
   clear_error();
   if (!p || !segments) { set_error("NULL argument"); return SK_ERR_INVALID_ARG; }
@@ -384,6 +392,7 @@ int sk_compute(sk_plan_t p, const uint8_t* d_packed, const uint8_t* d_mask, cons
   if (p->pass_b_vec == 8 && a.vec == 4 && N % 8 == 0 && ((uintptr_t)s1 | (uintptr_t)s2 | (uintptr_t)outs->sk_i) % 32 == 0)
     a.vec = 8;
   a.n_groups = (int32_t)((N + 64 * a.vec - 1) / (64 * a.vec));
+  a.depth = p->pass_b_depth ? p->pass_b_depth : 4;
   a.estimator = d.estimator;
   a.k_sigma = d.k_sigma;
   a.expect_offset = d.expect_offset;

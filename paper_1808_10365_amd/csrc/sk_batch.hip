@@ -88,6 +88,7 @@ __device__ __forceinline__ PassBArgs make_args(const BatchProb& P, const BatchSt
   a.chunk0 = 0;
   a.fin_b0 = 0;
   a.fin_nb = P.a.n_blocks;
+  a.depth = 4;
   a.estimator = P.estimator;
   a.k_sigma = P.k_sigma;
   a.expect_offset = P.expect_offset;

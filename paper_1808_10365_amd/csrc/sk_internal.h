@@ -100,6 +100,7 @@ struct PassBArgs {
   // chunk-sum and partial kernels, blocks [fin_b0, fin_b0 + fin_nb) of the
   // finalize kernel (a whole call: 0, n_chunks, 0, n_blocks).
   int32_t chunk0, fin_b0, fin_nb;
+  int32_t depth;          // blocks a partial-kernel wavefront loads together (2, 4 or 8)
   double k_sigma, expect_offset, sigma_override;
 };
 

@@ -34,7 +34,11 @@ namespace sk {
 __global__ __launch_bounds__(256) void chunk_sum_kernel_1(PassBArgs a) { chunk_sum_body<1>(a, a.chunk0 + blockIdx.x, blockIdx.y, blockIdx.z); }
 __global__ __launch_bounds__(256) void chunk_sum_kernel_4(PassBArgs a) { chunk_sum_body<4>(a, a.chunk0 + blockIdx.x, blockIdx.y, blockIdx.z); }
 __global__ __launch_bounds__(256) void partial_kernel_1(PassBArgs a) { partial_body<1>(a, a.chunk0 + blockIdx.x, blockIdx.y, blockIdx.z); }
-__global__ __launch_bounds__(256) void partial_kernel_4(PassBArgs a) { partial_body<4>(a, a.chunk0 + blockIdx.x, blockIdx.y, blockIdx.z); }
+__global__ __launch_bounds__(256) void partial_kernel_4(PassBArgs a) {
+  if (a.depth == 8) partial_body<4, 8>(a, a.chunk0 + blockIdx.x, blockIdx.y, blockIdx.z);
+  else if (a.depth == 2) partial_body<4, 2>(a, a.chunk0 + blockIdx.x, blockIdx.y, blockIdx.z);
+  else partial_body<4, 4>(a, a.chunk0 + blockIdx.x, blockIdx.y, blockIdx.z);
+}
 __global__ __launch_bounds__(256) void chunk_sum_kernel_8(PassBArgs a) { chunk_sum_body<8>(a, a.chunk0 + blockIdx.x, blockIdx.y, blockIdx.z); }
 __global__ __launch_bounds__(256) void partial_kernel_8(PassBArgs a) { partial_body<8>(a, a.chunk0 + blockIdx.x, blockIdx.y, blockIdx.z); }
 __global__ __launch_bounds__(256) void finalize_kernel(PassBArgs a) { finalize_body(a, blockIdx.x); }

@@ -168,9 +168,9 @@ __device__ __forceinline__ double recip_pos(double p) {
 
 // RI: integer type of the per-wavefront R1/R2 sums: int32_t when a
 // wavefront's sums provably fit (64 V M 2^14 < 2^31), else int64_t.
-template <int V, typename RI>
+template <int V, typename RI, int U>
 __device__ __forceinline__ void partial_body_t(const PassBArgs& a, int c, int f, int z) {
-  constexpr int U = 4;                                         // blocks loaded together
+  // U: blocks whose rows are loaded together.
   const int lane = threadIdx.x & 63;
   const int g = z * 4 + (threadIdx.x >> 6);                   // input group of 64*V
   const int N = a.n_inputs, L = a.window, H = a.hist_len;
@@ -266,13 +266,13 @@ __device__ __forceinline__ void partial_body_t(const PassBArgs& a, int c, int f,
   }
 }
 
-template <int V>
+template <int V, int U = 4>
 __device__ __forceinline__ void partial_body(const PassBArgs& a, int c, int f, int z) {
   // S2 of one input is at most M * 128^2 = M * 2^14 (Eq. singlesums).
   if ((int64_t)64 * V * a.block_len * 16384 < ((int64_t)1 << 31))
-    partial_body_t<V, int32_t>(a, c, f, z);
+    partial_body_t<V, int32_t, U>(a, c, f, z);
   else
-    partial_body_t<V, int64_t>(a, c, f, z);
+    partial_body_t<V, int64_t, U>(a, c, f, z);
 }
 
 // Estimator and flags from the combined sums (Eq. avgSK, final; Sec. 3.2).

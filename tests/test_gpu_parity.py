@@ -319,9 +319,10 @@ def test_false_alarm_thresholds(L, est):
     assert np.array_equal(fl2[clear], f0[clear])
 
 
-@pytest.mark.parametrize("chunk,vec", [(1, 4), (2, 1), (8, 4), (64, 1), (128, 4), (4, 8), (16, 8), (32, 8)])
+@pytest.mark.parametrize("chunk,vec,depth", [(1, 4, 0), (2, 1, 0), (8, 4, 0), (64, 1, 0), (128, 4, 0), (4, 8, 0),
+                                             (16, 8, 0), (32, 8, 0), (16, 4, 2), (16, 4, 8), (8, 4, 8), (32, 4, 2)])
 @pytest.mark.parametrize("N", [96, 1040])
-def test_pass_b_tiles(chunk, vec, N):
+def test_pass_b_tiles(chunk, vec, depth, N):
     # Every chunk length and lane width gives the oracle's results, across
     # calls (history) and with a window longer than the chunk; N = 1040 leaves
     # a partial group of inputs for every lane width.
@@ -331,11 +332,12 @@ def test_pass_b_tiles(chunk, vec, N):
     ref = oracle.sk(x, M, L)
     p = sk.Plan(N, F, T, M, norm_window=L)
     p.set_pass_b_tile(chunk, vec)
+    p.set_pass_b_depth(depth)
     outs = [p.compute(torch.from_numpy(x[k * T:(k + 1) * T].copy()).to(DEV), want=sk.ALL_OUTPUTS)
             for k in range(3)]
     torch.cuda.synchronize()
     cat = {name: torch.cat([getattr(o, name) for o in outs], dim=1) for name in sk.ALL_OUTPUTS}
-    check_result(SimpleNamespace(**cat), ref, M, L, what=f"pass B chunk={chunk} vec={vec} N={N}")
+    check_result(SimpleNamespace(**cat), ref, M, L, what=f"pass B chunk={chunk} vec={vec} depth={depth} N={N}")
     p.close()
 
 
