@@ -38,8 +38,9 @@ def parse():
     ap.add_argument("--cpu-sample-blocks", type=int, default=0,
                     help="blocks per channel in the oracle's timed sample (0: pick ~10-30 s of work)")
     ap.add_argument("--lpr", type=int, default=0, help="force pass A lanes per row")
-    ap.add_argument("--variant", type=int, default=-1, help="force pass A row batching variant (0..13; -1 = library choice)")
+    ap.add_argument("--variant", type=int, default=-1, help="force pass A row batching variant (0..15; -1 = library choice)")
     ap.add_argument("--grid", type=int, default=0, help="force pass A workgroup count (persistent loop)")
+    ap.add_argument("--ablocks", type=int, default=0, help="consecutive blocks per pass A task (packed variants)")
     ap.add_argument("--segments", type=int, default=0,
                     help="block segments per call (0 = library choice, 1 = pass B after pass A)")
     ap.add_argument("--chunk", type=int, default=0, help="force pass B chunk length (blocks)")
@@ -186,7 +187,7 @@ def read_ceiling(xd, dev, reps=10):
     best = None
     sink = torch.empty(8192 * 256, dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream()
-    for wgs in (1024, 2048, 4096, 8192):
+    for wgs in (256, 512, 1024, 2048, 4096):
         sk.read_probe(xd, wgs, sink)
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
@@ -361,6 +362,8 @@ def main():
         plan.set_pass_b_tile(args.chunk, args.bvec)
     if args.segments:
         plan.set_segments(args.segments)
+    if args.ablocks:
+        plan.set_pass_a_blocks(args.ablocks)
     if args.bdepth:
         plan.set_pass_b_depth(args.bdepth)
     # Inputs resident in HBM. Inputs smaller than the 256 MB last-level cache

@@ -40,11 +40,13 @@ int sk_plan_set_pass_a_tile(sk_plan_t plan, int32_t lanes_per_row);
  * 4 rows; 9: replicated table, 8 rows with prefetch; 10: replicated table,
  * 16 rows; 11: replicated table, 16 rows with prefetch; 12: replicated table
  * shared by 512-lane workgroups of 512 / lanes_per_row row phases, 8 rows;
- * 13: as 12 with two groups, 4 rows) and workgroup count (0: one per task;
- * fewer: workgroups loop over tasks). Variants 1..13 apply to the 16-byte
- * path (N % 16 == 0, aligned input); the others use variant 0. Lanes per
- * row are clamped to 256..1024 for variants 7..11 (one row phase) and to
- * 64..512 for variants 12 and 13. */
+ * 13: as 12 with two groups, 4 rows; 14: replicated table of packed entries
+ * p | p^2 << 12, one 32-bit add per sample for both sums, 8 rows; 15: as 14,
+ * 16 rows) and workgroup count (0: one per task; fewer: workgroups loop over
+ * tasks). Variants 1..15 apply to the 16-byte path (N % 16 == 0, aligned
+ * input); the others use variant 0. Lanes per row are clamped to 256..1024
+ * for variants 7..11, 14 and 15 (one row phase) and to 64..512 for variants
+ * 12 and 13. */
 int sk_plan_set_pass_a_variant(sk_plan_t plan, int32_t variant, int32_t grid);
 
 /* Block segments per call (1..64; 0 = library choice, currently 1: on
@@ -61,6 +63,11 @@ int sk_plan_set_segments(sk_plan_t plan, int32_t segments);
 /* Segments (pass A launches) the plan's last sk_compute used; 0 before the
  * first call. */
 int sk_plan_get_last_segments(sk_plan_t plan, int32_t* segments);
+
+/* Consecutive blocks one pass A task walks with the packed-table variants
+ * (14, 15): 1..4096, 0 = library choice. Longer tasks stream longer
+ * contiguous runs of rows per workgroup. */
+int sk_plan_set_pass_a_blocks(sk_plan_t plan, int32_t blocks);
 
 /* Blocks whose sums a pass B partial-kernel wavefront loads together (2, 4
  * or 8; 0 = library choice, 4). Applies to 4 inputs per lane. */

@@ -111,6 +111,7 @@ def load_library():
     lib.sk_read_probe.argtypes = [VP, I64, I32, VP, VP]
     lib.sk_plan_set_segments.argtypes = [VP, I32]
     lib.sk_plan_set_pass_b_depth.argtypes = [VP, I32]
+    lib.sk_plan_set_pass_a_blocks.argtypes = [VP, I32]
     lib.sk_plan_get_last_segments.argtypes = [VP, ctypes.POINTER(I32)]
     lib.sk_server_now.restype = ctypes.c_double
     lib.sk_server_create.argtypes = [ctypes.POINTER(ServerDesc), ctypes.POINTER(VP)]
@@ -138,7 +139,7 @@ def load_library():
     for name in ("sk_plan_create", "sk_plan_destroy", "sk_plan_device_bytes", "sk_compute", "sk_flags",
                  "sk_state_reset", "sk_state_size", "sk_state_export", "sk_state_import",
                  "sk_digitised_expectation", "sk_plan_set_pass_a_tile", "sk_plan_get_pass_a_tile",
-                 "sk_profile_enable", "sk_profile_read", "sk_plan_set_pass_a_variant", "sk_read_probe", "sk_plan_set_segments", "sk_plan_set_pass_b_depth",
+                 "sk_profile_enable", "sk_profile_read", "sk_plan_set_pass_a_variant", "sk_read_probe", "sk_plan_set_segments", "sk_plan_set_pass_b_depth", "sk_plan_set_pass_a_blocks",
                  "sk_plan_get_last_segments"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -282,6 +283,10 @@ class Plan:
         segment overlaps pass A of the next on a plan-owned stream."""
         _check(self._lib.sk_plan_set_segments(self.handle, int(segments)))
 
+    def set_pass_a_blocks(self, blocks: int):
+        """Consecutive blocks per pass A task with the packed-table variants (0: library choice)."""
+        _check(self._lib.sk_plan_set_pass_a_blocks(self.handle, int(blocks)))
+
     def set_pass_b_depth(self, depth: int):
         """Blocks a pass B partial wavefront loads together (0: library choice, 2, 4, 8)."""
         _check(self._lib.sk_plan_set_pass_b_depth(self.handle, int(depth)))
@@ -293,7 +298,7 @@ class Plan:
         return k.value
 
     def set_pass_a_variant(self, variant: int, grid: int = 0):
-        """Row batching variant of pass A (-1: library choice, 0..13) and workgroup
+        """Row batching variant of pass A (-1: library choice, 0..15) and workgroup
         count (0: one per task)."""
         _check(self._lib.sk_plan_set_pass_a_variant(self.handle, int(variant), int(grid)))
 

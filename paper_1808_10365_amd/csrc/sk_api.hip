@@ -57,6 +57,7 @@ struct sk_plan_s {
   int pass_b_vec;          // 0 = library choice, else 1 or 4 inputs per lane
   int segments = 0;        // block segments per call (0 = library choice, 1 = none)
   int pass_b_depth = 0;    // blocks a partial wavefront loads together (0 = library choice)
+  int pass_a_blocks = 0;   // consecutive blocks per pass A task (packed variants; 0 = library choice)
   int last_segments = 0;   // segments the last call used
   hipStream_t side = nullptr;          // pass B of segmented calls
   std::vector<hipEvent_t> seg_ev;      // pass A segment k done (on the caller's stream); last: join
@@ -222,6 +223,8 @@ static PassAConfig plan_pass_a_config(const sk_plan_s* p, const uint8_t* d_packe
   t->row_bytes = F * N;
   t->n_inputs = (int32_t)N;
   t->block0 = 0;
+  t->block_end = (int32_t)B;
+  t->blocks_per_task = 1;
   t->block_len = p->d.block_len;
   t->n_blocks = (int32_t)B;
   PassAConfig c = default_pass_a_config(vec, t->row_bytes, B, p->pass_a_lpr == 0 && p->pass_a_variant < 0);
@@ -236,14 +239,15 @@ static PassAConfig plan_pass_a_config(const sk_plan_s* p, const uint8_t* d_packe
   const int gpl = pass_a_groups_per_lane(vec, c.variant);
   t->col_groups = (int32_t)(t->row_bytes / vec);
   t->chunks = (t->col_groups + c.lpr * gpl - 1) / (c.lpr * gpl);
-  t->n_tasks = B * t->chunks;
+  if (pass_a_packed(vec, c.variant) && p->pass_a_blocks > 1) t->blocks_per_task = p->pass_a_blocks;
+  t->n_tasks = ((B + t->blocks_per_task - 1) / t->blocks_per_task) * t->chunks;
   c.grid = (int)(t->n_tasks < (1 << 30) ? t->n_tasks : (1 << 30));
   if (p->pass_a_grid > 0 && p->pass_a_grid < c.grid) c.grid = p->pass_a_grid;
   return c;
 }
 
 int sk_plan_set_pass_a_variant(sk_plan_t p, int32_t variant, int32_t grid) {
-  if (!p || variant < -1 || variant > 13 || grid < 0) { set_error("bad variant"); return SK_ERR_INVALID_ARG; }
+  if (!p || variant < -1 || variant > 15 || grid < 0) { set_error("bad variant"); return SK_ERR_INVALID_ARG; }
   p->pass_a_variant = variant;
   p->pass_a_grid = grid;
   return SK_OK;
@@ -253,6 +257,13 @@ int sk_plan_set_segments(sk_plan_t p, int32_t segments) {
   clear_error();
   if (!p || segments < 0 || segments > 64) { set_error("segments must be in 0..64"); return SK_ERR_INVALID_ARG; }
   p->segments = segments;
+  return SK_OK;
+}
+
+int sk_plan_set_pass_a_blocks(sk_plan_t p, int32_t blocks) {
+  clear_error();
+  if (!p || blocks < 0 || blocks > 4096) { set_error("blocks per task must be in 0..4096"); return SK_ERR_INVALID_ARG; }
+  p->pass_a_blocks = blocks;
   return SK_OK;
 }
 
@@ -462,7 +473,8 @@ int sk_compute(sk_plan_t p, const uint8_t* d_packed, const uint8_t* d_mask, cons
       if (b_next > b_prev) {
         PassATask ts = t;
         ts.block0 = b_prev;
-        ts.n_tasks = (int64_t)(b_next - b_prev) * t.chunks;
+        ts.block_end = b_next;
+        ts.n_tasks = (int64_t)((b_next - b_prev + t.blocks_per_task - 1) / t.blocks_per_task) * t.chunks;
         rc = launch_pass_a(ts, c, s);
         if (rc) return rc;
       }

@@ -44,12 +44,14 @@ struct PassATask {
   int32_t chunks;       // ceil(col_groups / (LPR * groups per lane))
   int64_t n_tasks;      // blocks of this launch * chunks
   int32_t block0;       // first block of this launch (tasks cover blocks block0 ..)
+  int32_t block_end;    // one past the last block of this launch
+  int32_t blocks_per_task;  // consecutive blocks one task walks (packed-table variants; else 1)
 };
 
 struct PassAConfig {
   int vec;     // 16, 4 or 1 bytes per lane per row
   int lpr;     // lanes per row: power of two, 1..256
-  int variant; // row batching variant (0..13, 16-byte path; see pass_a_groups_per_lane)
+  int variant; // row batching variant (0..15, 16-byte path; see pass_a_groups_per_lane)
   int grid;    // workgroups launched (<= tasks; grid-stride beyond)
 };
 
@@ -62,6 +64,8 @@ int pass_a_groups_per_lane(int vec, int variant);
 bool pass_a_lane_table(int vec, int variant);
 // Lanes per row the variant supports; the planner clamps into [lo, hi].
 void pass_a_lane_range(int vec, int variant, int* lo, int* hi);
+// Whether the variant uses the packed lane table (tasks may span several blocks).
+bool pass_a_packed(int vec, int variant);
 // lane_table: the lane-replicated table variants may be chosen (single-plan
 // kernel only; the batched kernel has its own table).
 PassAConfig default_pass_a_config(int vec, int64_t row_bytes, int64_t n_blocks, bool lane_table);

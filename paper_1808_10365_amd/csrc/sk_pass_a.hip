@@ -43,6 +43,8 @@ __device__ __forceinline__ void store_group(const PassATask& t, int b, int g, co
     for (int k = 0; k < VEC; k += 4) {
       u32x4 a = {s1[k], s1[k + 1], s1[k + 2], s1[k + 3]};
       u32x4 c = {s2[k], s2[k + 1], s2[k + 2], s2[k + 3]};
+      // Plain stores: nontemporal ones measured far slower here (the sums
+      // then reach HBM as scattered partial writes).
       *reinterpret_cast<u32x4*>(d1 + k) = a;
       *reinterpret_cast<u32x4*>(d2 + k) = c;
     }
@@ -61,7 +63,9 @@ __device__ __forceinline__ void store_group(const PassATask& t, int b, int g, co
 // CU to two workgroups. With several row phases the table's LDS is reused
 // for their reduction (S1, then S2) and refilled if the workgroup takes
 // another task.
-template <int VEC, int LPR, int U, bool PF, int GPL, bool REP, int WG = wg_size<LPR>()>
+// PACKED (with REP, one row phase, one group per lane): the packed lane
+// table, one add per sample for both sums.
+template <int VEC, int LPR, int U, bool PF, int GPL, bool REP, int WG = wg_size<LPR>(), bool PACKED = false>
 __global__ __launch_bounds__(WG) void pass_a_kernel(PassATask t) {
   constexpr int RP = WG / LPR;          // row phases per workgroup
   constexpr int W = 2 * VEC + 1;        // LDS stride of one lane's partials (odd: no bank conflicts)
@@ -72,19 +76,43 @@ __global__ __launch_bounds__(WG) void pass_a_kernel(PassATask t) {
   __shared__ __attribute__((aligned(16))) uint32_t lut32[REP ? LANE_LUT_DWORDS : 1];
   extern __shared__ uint32_t red[];     // [RP * LPR][W] when RP > 1
 
+  static_assert(!PACKED || (REP && RP == 1 && GPL == 1), "packed table: one row phase, one group per lane");
   const int tid = threadIdx.x;
-  if constexpr (REP) {
+  if constexpr (PACKED) {
+    fill_lane_packed_lut<WG>(lut32, tid);
+  } else if constexpr (REP) {
     fill_lane_lut<WG>(lut32, tid);
   } else {
     for (int k = tid; k < 256; k += WG) lut16[k] = (uint16_t)code_power((uint32_t)k);
   }
   __syncthreads();
   const LaneLut llut{reinterpret_cast<const uint8_t*>(lut32), (uint32_t)(tid & 63) * 4};
+  const LanePackedLut plut{reinterpret_cast<const uint8_t*>(lut32), (uint32_t)(tid & 63) * 4};
 
   const int lc = tid % LPR;
   const int ph = tid / LPR;
   const int M = t.block_len;
   const int64_t G = t.row_bytes;
+
+  if constexpr (PACKED) {
+    // A task walks blocks_per_task consecutive blocks (contiguous rows) of
+    // one column chunk, storing each block's sums as it ends.
+    const int Q = t.blocks_per_task;
+    for (int64_t task = blockIdx.x; task < t.n_tasks; task += gridDim.x) {
+      const int b_first = t.block0 + (int)(task / t.chunks) * Q;
+      const int ch = (int)(task % t.chunks);
+      const int g0 = ch * LPR + lc;
+      if (g0 >= t.col_groups) continue;
+      for (int b = b_first; b < b_first + Q && b < t.block_end; ++b) {
+        uint32_t s1[VEC], s2[VEC];
+#pragma unroll
+        for (int k = 0; k < VEC; ++k) s1[k] = s2[k] = 0;
+        sum_rows_packed<VEC, RP, U>(t.x + (int64_t)b * M * G + (int64_t)g0 * VEC, G, M, ph, plut, s1, s2);
+        store_group<VEC>(t, b, g0, s1, s2);
+      }
+    }
+    return;
+  }
 
   for (int64_t task = blockIdx.x; task < t.n_tasks; task += gridDim.x) {
     const int b = t.block0 + (int)(task / t.chunks);
@@ -211,6 +239,27 @@ static int launch_rep(const PassATask& t, int lpr, int grid, hipStream_t s) {
   return SK_ERR_INVALID_ARG;
 }
 
+// Packed lane table, one row phase (256, 512 or 1024 lanes per row).
+template <int U>
+static int launch_packed(const PassATask& t, int lpr, int grid, hipStream_t s) {
+  switch (lpr) {
+    case 256:
+      pass_a_kernel<16, 256, U, false, 1, true, 256, true><<<dim3(grid), dim3(256), 0, s>>>(t);
+      break;
+    case 512:
+      pass_a_kernel<16, 512, U, false, 1, true, 512, true><<<dim3(grid), dim3(512), 0, s>>>(t);
+      break;
+    case 1024:
+      pass_a_kernel<16, 1024, U, false, 1, true, 1024, true><<<dim3(grid), dim3(1024), 0, s>>>(t);
+      break;
+    default:
+      set_error("pass A: packed lane-table variant needs 256..1024 lanes per row, got %d", lpr);
+      return SK_ERR_INVALID_ARG;
+  }
+  SK_HIP_TRY(hipGetLastError());
+  return SK_OK;
+}
+
 // Lane table shared by 512-lane workgroups of 512 / lpr row phases (16
 // wavefronts per CU at two workgroups); lanes per row 64..512 (the planner
 // clamps others into that range).
@@ -265,6 +314,8 @@ static int launch_lpr(const PassATask& t, int lpr, int grid, hipStream_t s) {
 //  11: lane-replicated power table, 16 rows, next batch prefetched
 //  12: lane-replicated table in 512-lane workgroups (512 / LPR row phases), 8 rows
 //  13: as 12 with 2 column groups per lane, 4 rows
+//  14: packed lane table (p | p^2 << 12 per entry), 8 rows per load
+//  15: packed lane table, 16 rows per load
 int pass_a_groups_per_lane(int vec, int variant) {
   if (vec != 16) return 1;
   switch (variant) {
@@ -274,13 +325,15 @@ int pass_a_groups_per_lane(int vec, int variant) {
   }
 }
 
-bool pass_a_lane_table(int vec, int variant) { return vec == 16 && variant >= 7 && variant <= 13; }
+bool pass_a_lane_table(int vec, int variant) { return vec == 16 && variant >= 7 && variant <= 15; }
+
+bool pass_a_packed(int vec, int variant) { return vec == 16 && (variant == 14 || variant == 15); }
 
 void pass_a_lane_range(int vec, int variant, int* lo, int* hi) {
   *lo = 1;
   *hi = 1024;
   if (!pass_a_lane_table(vec, variant)) return;
-  if (variant >= 12) { *lo = 64; *hi = 512; } else { *lo = 256; }
+  if (variant == 12 || variant == 13) { *lo = 64; *hi = 512; } else { *lo = 256; }
 }
 
 template <int VEC>
@@ -300,6 +353,8 @@ static int launch_vec(const PassATask& t, int lpr, int variant, int grid, hipStr
       case 11: return launch_rep<16, 1, true>(t, lpr, grid, s);
       case 12: return launch_rep512<8, 1>(t, lpr, grid, s);
       case 13: return launch_rep512<4, 2>(t, lpr, grid, s);
+      case 14: return launch_packed<8>(t, lpr, grid, s);
+      case 15: return launch_packed<16>(t, lpr, grid, s);
       default: break;
     }
   }
@@ -315,10 +370,22 @@ int pick_vec(const uint8_t* x, int32_t n_inputs) {
 
 PassAConfig default_pass_a_config(int vec, int64_t row_bytes, int64_t n_blocks, bool lane_table) {
   const int64_t cg = row_bytes / vec;
-  // Wide rows (>= 256 groups of 16 inputs) with at least one task per CU:
-  // one row phase of 256 lanes and the lane-replicated table (no bank
-  // conflicts on the power lookups), the fastest tile measured on MI355X
-  // for rows of 8 KiB at block lengths 256 and 1024.
+  // Wide rows with at least one task per CU take the lane-replicated table
+  // (no bank conflicts on the power lookups), measured fastest on MI355X:
+  //  * >= 512 groups of 16 inputs: packed entries (one add per sample for
+  //    both sums) in 1024-lane workgroups, one per CU, each streaming whole
+  //    rows of a block (rows of 8 KiB: 316 us for 2 GiB at M = 1024 against
+  //    333 us for the next best; equal at M = 256);
+  //  * >= 256 groups: one row phase of 256 lanes.
+  if (lane_table && vec == 16 && cg >= 512 && n_blocks * ((cg + 1023) / 1024) >= 256) {
+    const int64_t tasks = n_blocks * ((cg + 1023) / 1024);
+    PassAConfig c;
+    c.vec = vec;
+    c.lpr = 1024;
+    c.variant = 15;
+    c.grid = (int)(tasks < (1 << 30) ? tasks : (1 << 30));
+    return c;
+  }
   if (lane_table && vec == 16 && cg >= 256 && n_blocks * ((cg + 255) / 256) >= 256) {
     const int64_t tasks = n_blocks * ((cg + 255) / 256);
     PassAConfig c;

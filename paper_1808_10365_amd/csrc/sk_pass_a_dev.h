@@ -115,6 +115,72 @@ __device__ __forceinline__ void accumulate_one(const Row<VEC>& r0, const LaneLut
   }
 }
 
+// Packed lane table: the same per-lane layout as LaneLut, each dword holding
+// p | p^2 << 12 for its code. Over at most 16 rows, sum p <= 2048 stays in
+// the low 12 bits and sum p^2 <= 2^18 in the next 19, so one 32-bit add per
+// sample (v_add3_u32 folds two rows) accumulates both sums; every 16 rows
+// the packed sums are split into S1 and S2.
+struct LanePackedLut {
+  const uint8_t* base;
+  uint32_t laneoff;
+  __device__ __forceinline__ uint32_t at(uint32_t w, int k) const {
+    const uint32_t sel = 0x0C0C0000u | ((uint32_t)(4 + k) << 8);
+    return *reinterpret_cast<const uint32_t*>(base + __builtin_amdgcn_perm(w, laneoff, sel));
+  }
+};
+constexpr int PACK_ROWS = 16;
+constexpr int PACK_SHIFT = 12;
+
+template <int WG>
+__device__ __forceinline__ void fill_lane_packed_lut(uint32_t* t, int tid) {
+  for (int k = tid; k < LANE_LUT_DWORDS / 4; k += WG) {
+    const uint32_t p = code_power((uint32_t)(k >> 4));
+    const uint32_t e = p | (p * p << PACK_SHIFT);
+    reinterpret_cast<u32x4*>(t)[k] = u32x4{e, e, e, e};
+  }
+}
+
+// Rows ph, ph + RP, ... (< M) of this lane with the packed table, in loads of
+// U rows, unpacking every PACK_ROWS rows.
+template <int VEC, int RP, int U>
+__device__ __forceinline__ void sum_rows_packed(const uint8_t* base, int64_t G, int M, int ph,
+                                                const LanePackedLut& lut, uint32_t* s1, uint32_t* s2) {
+  static_assert(VEC >= 4 && U % 2 == 0 && PACK_ROWS % U == 0, "whole row pairs per packed run");
+  const int nrow = ph < M ? (M - ph + RP - 1) / RP : 0;
+  const int64_t step = (int64_t)RP * G;
+  const uint8_t* p = base + (int64_t)ph * G;
+  for (int done = 0; done < nrow; done += PACK_ROWS) {
+    const int n = nrow - done < PACK_ROWS ? nrow - done : PACK_ROWS;
+    uint32_t acc[VEC];
+#pragma unroll
+    for (int k = 0; k < VEC; ++k) acc[k] = 0;
+    int r = 0;
+    for (; r + U <= n; r += U) {
+      Row<VEC> q[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) q[u].load(p + u * step);
+      p += U * step;
+#pragma unroll
+      for (int u = 0; u < U; u += 2)
+#pragma unroll
+        for (int k = 0; k < VEC; ++k)
+          acc[k] = acc[k] + lut.at(q[u].w[k >> 2], k & 3) + lut.at(q[u + 1].w[k >> 2], k & 3);
+    }
+    for (; r < n; ++r) {
+      Row<VEC> q;
+      q.load(p);
+      p += step;
+#pragma unroll
+      for (int k = 0; k < VEC; ++k) acc[k] += lut.at(q.w[k >> 2], k & 3);
+    }
+#pragma unroll
+    for (int k = 0; k < VEC; ++k) {
+      s1[k] += acc[k] & ((1u << PACK_SHIFT) - 1);
+      s2[k] += acc[k] >> PACK_SHIFT;
+    }
+  }
+}
+
 // Rows of this lane in batches of U: r = ph, ph + RP, ... (< M). With PF the
 // loads of the next batch are issued before the current batch is reduced, so
 // each wavefront keeps a batch of rows in flight while it computes.
