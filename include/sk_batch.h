@@ -5,12 +5,15 @@
  * estimator and flag parameters, Sec. 2.2.1 and Sec. 3.2) with its own input,
  * outputs and normaliser state. sk_batch_compute runs one call of every
  * problem: pass A for all problems is one persistent kernel whose workgroups
- * take (problem, block, column chunk) tasks from a device work queue, largest
- * tasks first; pass B for all problems follows in a few more persistent
- * kernels; the whole sequence is captured once into a HIP graph, so one call
- * is one graph launch. Pass A's lanes per row are chosen per problem shape by
- * the library's autotuner (timed trial launches on the device), cached in a
- * JSON file keyed by (device arch, N, F, T, M).
+ * take tasks from a device work queue, largest problems first. A task is a
+ * block and a chunk of 256 column groups for wide rows, or 256 / L
+ * consecutive blocks side by side for rows of L <= 128 column groups (L a
+ * power of two); every lane sums whole rows with the lane-replicated packed
+ * power table. Pass B for all problems follows in a few more kernels; the
+ * whole sequence is captured once into a HIP graph, so one call is one graph
+ * launch. Pass A's rows per load (8 or 16) are chosen by the library's
+ * autotuner (timed trial launches of the whole batch on the device), cached
+ * in a JSON file keyed by the device arch and the batch's shapes.
  *
  * Requirements: every problem has N % 16 == 0 and a 16-byte aligned input.
  * Errors as in sk.h.
@@ -29,7 +32,7 @@ extern "C" {
 typedef struct sk_batch_s* sk_batch_t;
 
 typedef struct {
-  int32_t autotune;        /* 1: time candidate tiles on the device (cached); 0: heuristic */
+  int32_t autotune;        /* 1: time the rows-per-load candidates on the device (cached); 0: 16 */
   int32_t use_graph;       /* 1: capture the launch sequence into a HIP graph */
   const char* tune_cache;  /* JSON tuning cache path; NULL: env SK_TUNE_CACHE, or none */
 } sk_batch_opts;
@@ -50,8 +53,9 @@ int sk_batch_compute(sk_batch_t batch, const uint8_t* const* d_inputs, void* str
 /* Forget every problem's normaliser history. Synchronises `stream`. */
 int sk_batch_state_reset(sk_batch_t batch, void* stream);
 
-/* Lanes per row chosen for problem j (after tuning) and the persistent
- * workgroup count of pass A. */
+/* Lanes per block row of problem j's pass A tasks (256 for wide rows, else
+ * the power of two covering its column groups) and the persistent workgroup
+ * count of pass A. */
 int sk_batch_get_tiles(sk_batch_t batch, int32_t j, int32_t* lanes_per_row, int32_t* pass_a_grid);
 
 /* History length (blocks) problem j's normaliser holds on the device now.

@@ -1,5 +1,5 @@
 // Batched form: many independent problems per launch (persistent kernels,
-// device work queue, HIP graph) and the pass A tile autotuner.
+// device work queue, HIP graph) and the pass A autotuner.
 #include <hip/hip_runtime.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -23,7 +23,8 @@ int validate_desc(const sk_plan_desc* d);
 // One problem as the batched kernels see it (device table entry).
 struct BatchProb {
   PassATask a;                 // pass A task geometry (x, s1, s2, shapes, chunks, n_tasks)
-  int32_t lpr;                 // pass A lanes per row
+  int32_t lpr;                 // pass A lanes per block row (256: wide rows in chunks; else one
+                               // workgroup holds 256 / lpr blocks side by side)
   int32_t window, hist_cap, chunk, n_chunks_max, n_groups, estimator, pad;
   double k_sigma, expect_offset, sigma_override;
   int32_t* hist[2];
@@ -107,70 +108,56 @@ __device__ __forceinline__ int find_prob(const BatchProb* probs, int n, int64_t 
   return lo;
 }
 
-// Pass A, one task, lanes per row known at run time.
+// Pass A, one task, with the packed lane table (Eq. singlesums). Wide rows
+// (lpb = 256): a task is (block, chunk of 256 column groups). Narrow rows
+// (lpb < 256, a power of two >= the row's column groups): a task holds
+// 256 / lpb consecutive blocks side by side, lane l walking all M rows of
+// block task * (256 / lpb) + l / lpb, column group l % lpb. Every lane owns
+// whole sums, so no reduction across lanes is needed.
 template <int U>
-__device__ void pass_a_task_rt(const PassATask& t, int lpr, int64_t task, const uint16_t* lut, uint32_t* red) {
-  constexpr int VEC = 16, W = 2 * VEC + 1;
+__device__ __forceinline__ void pass_a_task_packed(const PassATask& t, int lpb, int64_t task,
+                                                   const LanePackedLut& lut) {
+  constexpr int VEC = 16;
   const int tid = threadIdx.x;
-  const int rp = 256 / lpr;
-  const int lc = tid % lpr, ph = tid / lpr;
+  int64_t b;
+  int g;
+  if (lpb >= 256) {
+    b = task / t.chunks;
+    g = (int)(task % t.chunks) * 256 + tid;
+  } else {
+    b = task * (256 / lpb) + tid / lpb;
+    g = tid % lpb;
+  }
+  if (b >= t.n_blocks || g >= t.col_groups) return;
   const int M = t.block_len;
   const int64_t G = t.row_bytes;
-  const int b = (int)(task / t.chunks);
-  const int ch = (int)(task % t.chunks);
-  const int g = ch * lpr + lc;
   uint32_t s1[VEC], s2[VEC];
 #pragma unroll
   for (int k = 0; k < VEC; ++k) s1[k] = s2[k] = 0;
-  if (g < t.col_groups) sum_rows_rt<VEC, U>(t.x + (int64_t)b * M * G + (int64_t)g * VEC, G, M, ph, rp, lut, s1, s2);
+  sum_rows_packed<VEC, 1, U>(t.x + b * M * G + (int64_t)g * VEC, G, M, 0, lut, s1, s2);
   const int N = t.n_inputs, B = t.n_blocks;
-  if (rp == 1) {
-    if (g < t.col_groups) {
-      const int64_t col = (int64_t)g * VEC;
-      const int64_t f = col / N, i = col % N;
-      int32_t* d1 = t.s1 + (f * B + b) * N + i;
-      int32_t* d2 = t.s2 + (f * B + b) * N + i;
+  const int64_t col = (int64_t)g * VEC;
+  const int64_t f = col / N, i = col % N;
+  int32_t* d1 = t.s1 + (f * B + b) * N + i;
+  int32_t* d2 = t.s2 + (f * B + b) * N + i;
 #pragma unroll
-      for (int k = 0; k < VEC; k += 4) {
-        u32x4 x1 = {s1[k], s1[k + 1], s1[k + 2], s1[k + 3]};
-        u32x4 x2 = {s2[k], s2[k + 1], s2[k + 2], s2[k + 3]};
-        *reinterpret_cast<u32x4*>(d1 + k) = x1;
-        *reinterpret_cast<u32x4*>(d2 + k) = x2;
-      }
-    }
-  } else {
-    uint32_t* mine = red + (ph * lpr + lc) * W;
-#pragma unroll
-    for (int k = 0; k < VEC; ++k) {
-      mine[k] = s1[k];
-      mine[VEC + k] = s2[k];
-    }
-    __syncthreads();
-    for (int o = tid; o < lpr * 2 * VEC; o += 256) {
-      const int l = o / (2 * VEC), k = o % (2 * VEC);
-      uint32_t s = 0;
-      for (int p = 0; p < rp; ++p) s += red[(p * lpr + l) * W + k];
-      const int gg = ch * lpr + l;
-      if (gg < t.col_groups) {
-        const int64_t col = (int64_t)gg * VEC + (k % VEC);
-        const int64_t f = col / N, i = col % N;
-        int32_t* dst = k < VEC ? t.s1 : t.s2;
-        dst[(f * B + b) * N + i] = (int32_t)s;
-      }
-    }
-    __syncthreads();
+  for (int k = 0; k < VEC; k += 4) {
+    *reinterpret_cast<u32x4*>(d1 + k) = u32x4{s1[k], s1[k + 1], s1[k + 2], s1[k + 3]};
+    *reinterpret_cast<u32x4*>(d2 + k) = u32x4{s2[k], s2[k + 1], s2[k + 2], s2[k + 3]};
   }
 }
 
-// Persistent pass A over the whole batch: every workgroup takes tasks from
-// one device counter until the queue is empty (every wavefront then exits).
+// Persistent pass A over the whole batch: every workgroup fills its table
+// once, then takes tasks from one device counter until the queue is empty
+// (every wavefront then exits).
+template <int U>
 __global__ __launch_bounds__(256) void batch_pass_a_kernel(const BatchProb* __restrict__ probs, int n,
                                                            int64_t total, uint32_t* counter) {
-  __shared__ uint16_t lut[256];
+  __shared__ __attribute__((aligned(16))) uint32_t lut32[LANE_LUT_DWORDS];
   __shared__ int64_t s_task;
-  extern __shared__ uint32_t red[];
   const int tid = threadIdx.x;
-  lut[tid] = (uint16_t)code_power((uint32_t)tid);
+  fill_lane_packed_lut<256>(lut32, tid);
+  const LanePackedLut lut{reinterpret_cast<const uint8_t*>(lut32), (uint32_t)(tid & 63) * 4};
   for (;;) {
     if (tid == 0) s_task = (int64_t)atomicAdd(counter, 1u);
     __syncthreads();
@@ -179,7 +166,7 @@ __global__ __launch_bounds__(256) void batch_pass_a_kernel(const BatchProb* __re
     if (task >= total) break;
     const int p = find_prob<&BatchProb::a_begin>(probs, n, task);
     const BatchProb& P = probs[p];
-    pass_a_task_rt<8>(P.a, P.lpr, task - P.a_begin, lut, red);
+    pass_a_task_packed<U>(P.a, P.lpr, task - P.a_begin, lut);
   }
 }
 
@@ -206,11 +193,11 @@ __global__ __launch_bounds__(256) void batch_hist_copy_kernel(const BatchProb* _
   const int64_t lt = task - P.hc_begin;
   if (lt >= P.hc_count) return;
   const PassBArgs a = make_args(P, st[p]);
-  const int zc = (a.n_inputs + 255) / 256;
+  const int zc = (a.n_inputs + 1023) / 1024;
   const int z = (int)(lt % zc);
   const int64_t rest = lt / zc;
   const int f = (int)(rest % a.n_channels), j = (int)(rest / a.n_channels);
-  hist_copy_body(a, j, f, z);
+  hist_copy_body_v4(a, j, f, z);
 }
 
 __global__ __launch_bounds__(256) void batch_partial_kernel(const BatchProb* __restrict__ probs,
@@ -309,7 +296,7 @@ struct sk_batch_s {
   std::vector<void*> owned;
   int64_t total_a = 0, total_cs = 0, total_hc = 0, total_pt = 0, total_fn = 0;
   int grid_a = 0;
-  size_t lds_a = 0;
+  int rows_a = 16;                 // pass A rows per load (autotuned: 8 or 16)
   bool use_graph = false;
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
@@ -340,7 +327,10 @@ static int batch_alloc(sk_batch_s* b, void** p, size_t bytes) {
 }
 
 static int launch_sequence(sk_batch_s* b, hipStream_t s) {
-  batch_pass_a_kernel<<<dim3(b->grid_a), dim3(256), b->lds_a, s>>>(b->d_probs, b->n, b->total_a, b->d_counter);
+  if (b->rows_a == 8)
+    batch_pass_a_kernel<8><<<dim3(b->grid_a), dim3(256), 0, s>>>(b->d_probs, b->n, b->total_a, b->d_counter);
+  else
+    batch_pass_a_kernel<16><<<dim3(b->grid_a), dim3(256), 0, s>>>(b->d_probs, b->n, b->total_a, b->d_counter);
   SK_HIP_TRY(hipGetLastError());
   if (b->total_cs > 0) {
     batch_chunk_sum_kernel<<<dim3((unsigned)b->total_cs), dim3(256), 0, s>>>(b->d_probs, b->d_state, b->n);
@@ -359,37 +349,30 @@ static int launch_sequence(sk_batch_s* b, hipStream_t s) {
   return SK_OK;
 }
 
-// Time batched pass A on problem j alone for one lanes-per-row value.
-static float time_pass_a_alone(sk_batch_s* b, const BatchProb& prob, int lpr, hipStream_t s) {
-  BatchProb one = prob;
-  one.lpr = lpr;
-  one.a.chunks = (one.a.col_groups + lpr - 1) / lpr;
-  one.a.n_tasks = (int64_t)one.a.n_blocks * one.a.chunks;
-  one.a_begin = 0;
-  BatchProb* d_one = nullptr;
-  uint32_t* d_cnt = nullptr;
-  if (hipMalloc((void**)&d_one, sizeof one) != hipSuccess) return 1e30f;
-  if (hipMalloc((void**)&d_cnt, sizeof(uint32_t)) != hipSuccess) { (void)hipFree(d_one); return 1e30f; }
-  (void)hipMemcpyAsync(d_one, &one, sizeof one, hipMemcpyHostToDevice, s);
+// Time batched pass A over the whole batch for one rows-per-load value
+// (best of three after a warm-up run). Runs before the graph is captured.
+static float time_pass_a_batch(sk_batch_s* b, int rows, hipStream_t s) {
   hipEvent_t e0, e1;
-  (void)hipEventCreate(&e0);
-  (void)hipEventCreate(&e1);
-  const int grid = (int)std::min<int64_t>(one.a.n_tasks, b->grid_a);
+  if (hipEventCreate(&e0) != hipSuccess) return 1e30f;
+  if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return 1e30f; }
   float best = 1e30f;
   for (int rep = 0; rep < 4; ++rep) {
-    (void)hipMemsetAsync(d_cnt, 0, sizeof(uint32_t), s);
+    (void)hipMemsetAsync(b->d_counter, 0, sizeof(uint32_t), s);
     (void)hipEventRecord(e0, s);
-    batch_pass_a_kernel<<<dim3(grid), dim3(256), b->lds_a, s>>>(d_one, 1, one.a.n_tasks, d_cnt);
+    if (rows == 8)
+      batch_pass_a_kernel<8><<<dim3(b->grid_a), dim3(256), 0, s>>>(b->d_probs, b->n, b->total_a, b->d_counter);
+    else
+      batch_pass_a_kernel<16><<<dim3(b->grid_a), dim3(256), 0, s>>>(b->d_probs, b->n, b->total_a, b->d_counter);
     (void)hipEventRecord(e1, s);
     (void)hipEventSynchronize(e1);
     float ms = 0;
     (void)hipEventElapsedTime(&ms, e0, e1);
     if (rep > 0) best = std::min(best, ms);   // first run warms up
   }
+  (void)hipMemsetAsync(b->d_counter, 0, sizeof(uint32_t), s);
+  (void)hipStreamSynchronize(s);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  (void)hipFree(d_one);
-  (void)hipFree(d_cnt);
   return best;
 }
 
@@ -415,9 +398,11 @@ int sk_batch_create(const sk_plan_desc* descs, int32_t n, const sk_batch_opts* o
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, b->device) != hipSuccess) { batch_free(b); set_error("device query failed"); return SK_ERR_DEVICE; }
   b->arch = prop.gcnArchName;
-  b->lds_a = sizeof(uint32_t) * 256 * 33;
   int occ = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, batch_pass_a_kernel, 256, b->lds_a) != hipSuccess || occ < 1) occ = 4;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, batch_pass_a_kernel<16>, 256, 0) != hipSuccess || occ < 1) occ = 2;
+  int occ8 = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ8, batch_pass_a_kernel<8>, 256, 0) == hipSuccess && occ8 >= 1)
+    occ = std::min(occ, occ8);
   b->grid_a = occ * prop.multiProcessorCount;
   b->use_graph = !opts || opts->use_graph;
 
@@ -444,8 +429,11 @@ int sk_batch_create(const sk_plan_desc* descs, int32_t n, const sk_batch_opts* o
     P.a.block_len = d.block_len;
     P.a.n_blocks = (int32_t)B;
     P.a.col_groups = (int32_t)(F * N / 16);
-    PassAConfig c = default_pass_a_config(16, F * N, B, false);
-    P.lpr = c.lpr;
+    {
+      int lpb = 1;
+      while (lpb < 256 && lpb < P.a.col_groups) lpb *= 2;
+      P.lpr = lpb;
+    }
     P.window = L;
     P.hist_cap = L >= 2 ? L - 1 : 0;
     P.estimator = d.estimator;
@@ -507,45 +495,19 @@ int sk_batch_create(const sk_plan_desc* descs, int32_t n, const sk_batch_opts* o
   if (hipStreamCreate(&b->cap_stream) != hipSuccess) { batch_free(b); set_error("stream create failed"); return SK_ERR_DEVICE; }
   s = b->cap_stream;
 
-  // Autotune pass A lanes per row per problem shape (cached).
-  const bool tune = !opts || opts->autotune;
-  const std::string path = cache_path(opts);
-  std::map<std::string, int> cache = load_cache(path);
-  bool cache_dirty = false;
-  if (tune) {
-    std::map<std::string, int> seen;
-    for (int q = 0; q < n; ++q) {
-      BatchProb& P = b->host[q];
-      const sk_plan_desc& d = b->desc[b->order[q]];
-      char key[256];
-      snprintf(key, sizeof key, "%s|pass_a_batch|N=%d|F=%d|T=%lld|M=%d", b->arch.c_str(), d.n_inputs,
-               d.n_channels, (long long)d.n_samples, d.block_len);
-      auto it = cache.find(key);
-      if (it != cache.end()) { P.lpr = it->second; continue; }
-      auto sn = seen.find(key);
-      if (sn != seen.end()) { P.lpr = sn->second; continue; }
-      int best_lpr = P.lpr;
-      float best = 1e30f;
-      for (int lpr : {32, 64, 128, 256}) {
-        if (lpr > 2 * P.a.col_groups && lpr != 32) continue;
-        const float ms = time_pass_a_alone(b, P, lpr, s);
-        if (ms < best) { best = ms; best_lpr = lpr; }
-      }
-      P.lpr = best_lpr;
-      seen[key] = best_lpr;
-      cache[key] = best_lpr;
-      cache_dirty = true;
-    }
-  }
-  if (cache_dirty) save_cache(path, cache);
-
   // Task ranges.
   int64_t ta = 0, tcs = 0, thc = 0, tpt = 0, tfn = 0;
   for (int q = 0; q < n; ++q) {
     BatchProb& P = b->host[q];
     const int64_t F = P.a.row_bytes / P.a.n_inputs;
-    P.a.chunks = (P.a.col_groups + P.lpr - 1) / P.lpr;
-    P.a.n_tasks = (int64_t)P.a.n_blocks * P.a.chunks;
+    if (P.lpr >= 256) {
+      P.a.chunks = (P.a.col_groups + 255) / 256;
+      P.a.n_tasks = (int64_t)P.a.n_blocks * P.a.chunks;
+    } else {
+      const int bpt = 256 / P.lpr;
+      P.a.chunks = 1;
+      P.a.n_tasks = ((int64_t)P.a.n_blocks + bpt - 1) / bpt;
+    }
     P.a_begin = ta;
     ta += P.a.n_tasks;
     const int zc = (P.a.n_inputs + 1023) / 1024;
@@ -554,7 +516,7 @@ int sk_batch_create(const sk_plan_desc* descs, int32_t n, const sk_batch_opts* o
     tcs += P.cs_count;
     P.hc_begin = thc;
     P.hc_count = (P.window >= 2 && P.a.n_blocks < P.hist_cap)
-                     ? (int64_t)(P.hist_cap - P.a.n_blocks) * F * ((P.a.n_inputs + 255) / 256) : 0;
+                     ? (int64_t)(P.hist_cap - P.a.n_blocks) * F * ((P.a.n_inputs + 1023) / 1024) : 0;
     thc += P.hc_count;
     P.pt_begin = tpt;
     P.pt_count = (int64_t)P.n_chunks_max * F * ((P.n_groups + 3) / 4);
@@ -591,6 +553,33 @@ int sk_batch_create(const sk_plan_desc* descs, int32_t n, const sk_batch_opts* o
     batch_free(b);
     set_error("batch table upload failed");
     return SK_ERR_DEVICE;
+  }
+
+  // Autotune pass A rows per load over the whole batch (cached by the
+  // batch's shapes).
+  const bool tune = !opts || opts->autotune;
+  if (tune) {
+    const std::string path = cache_path(opts);
+    std::map<std::string, int> cache = load_cache(path);
+    uint64_t h = 1469598103934665603ull;    // FNV-1a over the shape list
+    for (int q = 0; q < n; ++q) {
+      const sk_plan_desc& d = b->desc[b->order[q]];
+      const int64_t v[4] = {d.n_inputs, d.n_channels, d.n_samples, d.block_len};
+      for (int64_t x : v)
+        for (int k = 0; k < 8; ++k) { h ^= (uint64_t)((x >> (8 * k)) & 0xFF); h *= 1099511628211ull; }
+    }
+    char key[256];
+    snprintf(key, sizeof key, "%s|batch_pass_a_rows|n=%d|%016llx", b->arch.c_str(), n, (unsigned long long)h);
+    auto it = cache.find(key);
+    if (it != cache.end() && (it->second == 8 || it->second == 16)) {
+      b->rows_a = it->second;
+    } else {
+      const float t8 = time_pass_a_batch(b, 8, s);
+      const float t16 = time_pass_a_batch(b, 16, s);
+      b->rows_a = t8 < t16 ? 8 : 16;
+      cache[key] = b->rows_a;
+      save_cache(path, cache);
+    }
   }
 
   if (b->use_graph) {

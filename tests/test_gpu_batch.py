@@ -93,11 +93,34 @@ def test_batch_tiles_and_cache(tmp_path):
     cache = tmp_path / "tune.json"
     b1 = sk.Batch([kw for _, kw in probs], xs, autotune=True, tune_cache=str(cache))
     tiles = [b1.tiles(j) for j in range(len(probs))]
-    assert cache.exists() and cache.read_text().count("pass_a_batch") >= 1
+    assert cache.exists() and cache.read_text().count("batch_pass_a_rows") == 1
     b2 = sk.Batch([kw for _, kw in probs], xs, autotune=True, tune_cache=str(cache))
     assert [b2.tiles(j) for j in range(len(probs))] == tiles
-    for lpr, grid in tiles:
-        assert lpr in (32, 64, 128, 256) and grid > 0
+    for (lpr, grid), (_, kw) in zip(tiles, probs):
+        groups = kw["n_inputs"] * kw["n_channels"] // 16
+        want = 256 if groups >= 256 else 1 << max(0, (groups - 1).bit_length())
+        assert lpr == want and grid > 0
+
+
+def test_batch_wide_and_narrow_rows(tmp_path):
+    # Rows of 512 column groups (two 256-lane chunks per block), of 1 group
+    # (256 blocks side by side per workgroup) and of 48 groups (a block row
+    # padded to 64 lanes), with a block count that leaves a partial last task.
+    shapes = [(2048, 4, 64 * 9, 64, 3), (16, 1, 16 * 301, 16, 4), (256, 3, 32 * 45, 32, 2)]
+    probs, xs, outs = [], [], []
+    for k, (N, F, T, M, L) in enumerate(shapes):
+        w = synth.Workload(f"wide{k}", N, F, T, M, 70 + k, np.full(N, 2.3), [])
+        x = synth.generate(w, nthreads=2)
+        probs.append(dict(n_inputs=N, n_channels=F, n_samples=T, block_len=M, norm_window=L, k_sigma=5.0))
+        xs.append(x)
+    dx = [torch.from_numpy(x).to(DEV) for x in xs]
+    batch = sk.Batch(probs, dx, autotune=True, use_graph=True, tune_cache=str(tmp_path / "t.json"))
+    res = batch.compute()
+    torch.cuda.synchronize()
+    for j, (x, kw) in enumerate(zip(xs, probs)):
+        ref = oracle.sk(x, kw["block_len"], kw["norm_window"], 0, 5.0, 0.0, 0.0)
+        check_result(res[j], ref, kw["block_len"], kw["norm_window"], what=f"wide/narrow problem {j}")
+    batch.close()
 
 
 def test_batch_rejects_unsupported():
