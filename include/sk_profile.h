@@ -42,8 +42,11 @@ int sk_plan_set_pass_a_tile(sk_plan_t plan, int32_t lanes_per_row);
  * shared by 512-lane workgroups of 512 / lanes_per_row row phases, 8 rows;
  * 13: as 12 with two groups, 4 rows; 14: replicated table of packed entries
  * p | p^2 << 12, one 32-bit add per sample for both sums, 8 rows; 15: as 14,
- * 16 rows) and workgroup count (0: one per task; fewer: workgroups loop over
- * tasks). Variants 1..15 apply to the 16-byte path (N % 16 == 0, aligned
+ * 16 rows; 16: packed table in 256-lane workgroups whose lanes each sum whole
+ * rows: narrow rows put 256 / L blocks side by side, L = the power of two
+ * covering the row's column groups, which replaces the lanes-per-row
+ * setting) and workgroup count (0: one per task; fewer: workgroups loop over
+ * tasks). Variants 1..16 apply to the 16-byte path (N % 16 == 0, aligned
  * input); the others use variant 0. Lanes per row are clamped to 256..1024
  * for variants 7..11, 14 and 15 (one row phase) and to 64..512 for variants
  * 12 and 13. */

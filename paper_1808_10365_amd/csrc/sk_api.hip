@@ -240,6 +240,11 @@ static PassAConfig plan_pass_a_config(const sk_plan_s* p, const uint8_t* d_packe
   t->col_groups = (int32_t)(t->row_bytes / vec);
   t->chunks = (t->col_groups + c.lpr * gpl - 1) / (c.lpr * gpl);
   if (pass_a_packed(vec, c.variant) && p->pass_a_blocks > 1) t->blocks_per_task = p->pass_a_blocks;
+  if (pass_a_side_by_side(vec, c.variant)) {
+    c.lpr = pass_a_side_by_side_lanes(t->col_groups);
+    t->blocks_per_task = c.lpr >= 256 ? 1 : 256 / c.lpr;
+    t->chunks = c.lpr >= 256 ? (t->col_groups + 255) / 256 : 1;
+  }
   t->n_tasks = ((B + t->blocks_per_task - 1) / t->blocks_per_task) * t->chunks;
   c.grid = (int)(t->n_tasks < (1 << 30) ? t->n_tasks : (1 << 30));
   if (p->pass_a_grid > 0 && p->pass_a_grid < c.grid) c.grid = p->pass_a_grid;
@@ -247,7 +252,7 @@ static PassAConfig plan_pass_a_config(const sk_plan_s* p, const uint8_t* d_packe
 }
 
 int sk_plan_set_pass_a_variant(sk_plan_t p, int32_t variant, int32_t grid) {
-  if (!p || variant < -1 || variant > 15 || grid < 0) { set_error("bad variant"); return SK_ERR_INVALID_ARG; }
+  if (!p || variant < -1 || variant > 16 || grid < 0) { set_error("bad variant"); return SK_ERR_INVALID_ARG; }
   p->pass_a_variant = variant;
   p->pass_a_grid = grid;
   return SK_OK;

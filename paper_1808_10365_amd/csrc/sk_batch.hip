@@ -108,45 +108,6 @@ __device__ __forceinline__ int find_prob(const BatchProb* probs, int n, int64_t 
   return lo;
 }
 
-// Pass A, one task, with the packed lane table (Eq. singlesums). Wide rows
-// (lpb = 256): a task is (block, chunk of 256 column groups). Narrow rows
-// (lpb < 256, a power of two >= the row's column groups): a task holds
-// 256 / lpb consecutive blocks side by side, lane l walking all M rows of
-// block task * (256 / lpb) + l / lpb, column group l % lpb. Every lane owns
-// whole sums, so no reduction across lanes is needed.
-template <int U>
-__device__ __forceinline__ void pass_a_task_packed(const PassATask& t, int lpb, int64_t task,
-                                                   const LanePackedLut& lut) {
-  constexpr int VEC = 16;
-  const int tid = threadIdx.x;
-  int64_t b;
-  int g;
-  if (lpb >= 256) {
-    b = task / t.chunks;
-    g = (int)(task % t.chunks) * 256 + tid;
-  } else {
-    b = task * (256 / lpb) + tid / lpb;
-    g = tid % lpb;
-  }
-  if (b >= t.n_blocks || g >= t.col_groups) return;
-  const int M = t.block_len;
-  const int64_t G = t.row_bytes;
-  uint32_t s1[VEC], s2[VEC];
-#pragma unroll
-  for (int k = 0; k < VEC; ++k) s1[k] = s2[k] = 0;
-  sum_rows_packed<VEC, 1, U>(t.x + b * M * G + (int64_t)g * VEC, G, M, 0, lut, s1, s2);
-  const int N = t.n_inputs, B = t.n_blocks;
-  const int64_t col = (int64_t)g * VEC;
-  const int64_t f = col / N, i = col % N;
-  int32_t* d1 = t.s1 + (f * B + b) * N + i;
-  int32_t* d2 = t.s2 + (f * B + b) * N + i;
-#pragma unroll
-  for (int k = 0; k < VEC; k += 4) {
-    *reinterpret_cast<u32x4*>(d1 + k) = u32x4{s1[k], s1[k + 1], s1[k + 2], s1[k + 3]};
-    *reinterpret_cast<u32x4*>(d2 + k) = u32x4{s2[k], s2[k + 1], s2[k + 2], s2[k + 3]};
-  }
-}
-
 // Persistent pass A over the whole batch: every workgroup fills its table
 // once, then takes tasks from one device counter until the queue is empty
 // (every wavefront then exits).
@@ -166,7 +127,7 @@ __global__ __launch_bounds__(256) void batch_pass_a_kernel(const BatchProb* __re
     if (task >= total) break;
     const int p = find_prob<&BatchProb::a_begin>(probs, n, task);
     const BatchProb& P = probs[p];
-    pass_a_task_packed<U>(P.a, P.lpr, task - P.a_begin, lut);
+    pass_a_task_side_by_side<U>(P.a, P.lpr, task - P.a_begin, lut);
   }
 }
 
@@ -500,14 +461,11 @@ int sk_batch_create(const sk_plan_desc* descs, int32_t n, const sk_batch_opts* o
   for (int q = 0; q < n; ++q) {
     BatchProb& P = b->host[q];
     const int64_t F = P.a.row_bytes / P.a.n_inputs;
-    if (P.lpr >= 256) {
-      P.a.chunks = (P.a.col_groups + 255) / 256;
-      P.a.n_tasks = (int64_t)P.a.n_blocks * P.a.chunks;
-    } else {
-      const int bpt = 256 / P.lpr;
-      P.a.chunks = 1;
-      P.a.n_tasks = ((int64_t)P.a.n_blocks + bpt - 1) / bpt;
-    }
+    P.a.block0 = 0;
+    P.a.block_end = P.a.n_blocks;
+    P.a.blocks_per_task = P.lpr >= 256 ? 1 : 256 / P.lpr;
+    P.a.chunks = P.lpr >= 256 ? (P.a.col_groups + 255) / 256 : 1;
+    P.a.n_tasks = (((int64_t)P.a.n_blocks + P.a.blocks_per_task - 1) / P.a.blocks_per_task) * P.a.chunks;
     P.a_begin = ta;
     ta += P.a.n_tasks;
     const int zc = (P.a.n_inputs + 1023) / 1024;

@@ -51,7 +51,7 @@ struct PassATask {
 struct PassAConfig {
   int vec;     // 16, 4 or 1 bytes per lane per row
   int lpr;     // lanes per row: power of two, 1..256
-  int variant; // row batching variant (0..15, 16-byte path; see pass_a_groups_per_lane)
+  int variant; // row batching variant (0..16, 16-byte path; see pass_a_groups_per_lane)
   int grid;    // workgroups launched (<= tasks; grid-stride beyond)
 };
 
@@ -66,6 +66,9 @@ bool pass_a_lane_table(int vec, int variant);
 void pass_a_lane_range(int vec, int variant, int* lo, int* hi);
 // Whether the variant uses the packed lane table (tasks may span several blocks).
 bool pass_a_packed(int vec, int variant);
+// Variant 16: 256-lane tasks, blocks side by side for narrow rows.
+bool pass_a_side_by_side(int vec, int variant);
+int pass_a_side_by_side_lanes(int64_t col_groups);
 // lane_table: the lane-replicated table variants may be chosen (single-plan
 // kernel only; the batched kernel has its own table).
 PassAConfig default_pass_a_config(int vec, int64_t row_bytes, int64_t n_blocks, bool lane_table);

@@ -260,6 +260,25 @@ static int launch_packed(const PassATask& t, int lpr, int grid, hipStream_t s) {
   return SK_OK;
 }
 
+// Variant 16: packed lane table, 256-lane tasks with blocks side by side for
+// narrow rows (t.blocks_per_task blocks per task) or 256-group chunks of one
+// block for wide rows; no row phases, so no reduction across lanes.
+template <int U>
+__global__ __launch_bounds__(256) void pass_a_side_by_side_kernel(PassATask t, int lpb) {
+  __shared__ __attribute__((aligned(16))) uint32_t lut32[LANE_LUT_DWORDS];
+  const int tid = threadIdx.x;
+  fill_lane_packed_lut<256>(lut32, tid);
+  __syncthreads();
+  const LanePackedLut lut{reinterpret_cast<const uint8_t*>(lut32), (uint32_t)(tid & 63) * 4};
+  for (int64_t task = blockIdx.x; task < t.n_tasks; task += gridDim.x) pass_a_task_side_by_side<U>(t, lpb, task, lut);
+}
+
+int pass_a_side_by_side_lanes(int64_t col_groups) {
+  int lpb = 1;
+  while (lpb < 256 && lpb < col_groups) lpb *= 2;
+  return lpb;
+}
+
 // Lane table shared by 512-lane workgroups of 512 / lpr row phases (16
 // wavefronts per CU at two workgroups); lanes per row 64..512 (the planner
 // clamps others into that range).
@@ -316,6 +335,8 @@ static int launch_lpr(const PassATask& t, int lpr, int grid, hipStream_t s) {
 //  13: as 12 with 2 column groups per lane, 4 rows
 //  14: packed lane table (p | p^2 << 12 per entry), 8 rows per load
 //  15: packed lane table, 16 rows per load
+//  16: packed lane table, 256-lane workgroups, blocks side by side for
+//      narrow rows (lanes per row = power of two covering the row, <= 256)
 int pass_a_groups_per_lane(int vec, int variant) {
   if (vec != 16) return 1;
   switch (variant) {
@@ -325,15 +346,17 @@ int pass_a_groups_per_lane(int vec, int variant) {
   }
 }
 
-bool pass_a_lane_table(int vec, int variant) { return vec == 16 && variant >= 7 && variant <= 15; }
+bool pass_a_lane_table(int vec, int variant) { return vec == 16 && variant >= 7 && variant <= 16; }
 
 bool pass_a_packed(int vec, int variant) { return vec == 16 && (variant == 14 || variant == 15); }
+
+bool pass_a_side_by_side(int vec, int variant) { return vec == 16 && variant == 16; }
 
 void pass_a_lane_range(int vec, int variant, int* lo, int* hi) {
   *lo = 1;
   *hi = 1024;
   if (!pass_a_lane_table(vec, variant)) return;
-  if (variant == 12 || variant == 13) { *lo = 64; *hi = 512; } else { *lo = 256; }
+  if (variant == 12 || variant == 13) { *lo = 64; *hi = 512; } else if (variant == 16) { *lo = 1; *hi = 256; } else { *lo = 256; }
 }
 
 template <int VEC>
@@ -355,6 +378,10 @@ static int launch_vec(const PassATask& t, int lpr, int variant, int grid, hipStr
       case 13: return launch_rep512<4, 2>(t, lpr, grid, s);
       case 14: return launch_packed<8>(t, lpr, grid, s);
       case 15: return launch_packed<16>(t, lpr, grid, s);
+      case 16:
+        pass_a_side_by_side_kernel<16><<<dim3(grid), dim3(256), 0, s>>>(t, lpr);
+        SK_HIP_TRY(hipGetLastError());
+        return SK_OK;
       default: break;
     }
   }
@@ -394,6 +421,22 @@ PassAConfig default_pass_a_config(int vec, int64_t row_bytes, int64_t n_blocks, 
     c.variant = 7;
     c.grid = (int)(tasks < (1 << 30) ? tasks : (1 << 30));
     return c;
+  }
+  // Narrow rows with at least one task per CU: blocks side by side in
+  // 256-lane workgroups with the packed table, every lane summing whole rows
+  // (the Pathfinder shape: 53 against 57 us with row phases).
+  if (lane_table && vec == 16 && cg < 256) {
+    int lpb = 1;
+    while (lpb < cg) lpb *= 2;
+    const int64_t tasks = (n_blocks + 256 / lpb - 1) / (256 / lpb);
+    if (tasks >= 256) {
+      PassAConfig c;
+      c.vec = vec;
+      c.lpr = lpb;
+      c.variant = 16;
+      c.grid = (int)(tasks < (1 << 30) ? tasks : (1 << 30));
+      return c;
+    }
   }
   int lpr = 1;
   while (lpr < 256 && lpr < cg) lpr *= 2;
