@@ -34,10 +34,9 @@ namespace sk {
 __global__ __launch_bounds__(256) void chunk_sum_kernel_1(PassBArgs a) { chunk_sum_body<1>(a, a.chunk0 + blockIdx.x, blockIdx.y, blockIdx.z); }
 __global__ __launch_bounds__(256) void chunk_sum_kernel_4(PassBArgs a) { chunk_sum_body<4>(a, a.chunk0 + blockIdx.x, blockIdx.y, blockIdx.z); }
 __global__ __launch_bounds__(256) void partial_kernel_1(PassBArgs a) { partial_body<1>(a, a.chunk0 + blockIdx.x, blockIdx.y, blockIdx.z); }
+template <int D>
 __global__ __launch_bounds__(256) void partial_kernel_4(PassBArgs a) {
-  if (a.depth == 8) partial_body<4, 8>(a, a.chunk0 + blockIdx.x, blockIdx.y, blockIdx.z);
-  else if (a.depth == 2) partial_body<4, 2>(a, a.chunk0 + blockIdx.x, blockIdx.y, blockIdx.z);
-  else partial_body<4, 4>(a, a.chunk0 + blockIdx.x, blockIdx.y, blockIdx.z);
+  partial_body<4, D>(a, a.chunk0 + blockIdx.x, blockIdx.y, blockIdx.z);
 }
 __global__ __launch_bounds__(256) void chunk_sum_kernel_8(PassBArgs a) { chunk_sum_body<8>(a, a.chunk0 + blockIdx.x, blockIdx.y, blockIdx.z); }
 __global__ __launch_bounds__(256) void partial_kernel_8(PassBArgs a) { partial_body<8>(a, a.chunk0 + blockIdx.x, blockIdx.y, blockIdx.z); }
@@ -69,7 +68,9 @@ static int launch_v(const PassBArgs& a0, int32_t c_begin, int32_t c_end, int32_t
   }
   if (nc > 0) {
     if (V == 8) partial_kernel_8<<<dim3(nc, F, (a.n_groups + 3) / 4), dim3(256), 0, s>>>(a);
-    else if (V == 4) partial_kernel_4<<<dim3(nc, F, (a.n_groups + 3) / 4), dim3(256), 0, s>>>(a);
+    else if (V == 4 && a.depth == 8) partial_kernel_4<8><<<dim3(nc, F, (a.n_groups + 3) / 4), dim3(256), 0, s>>>(a);
+    else if (V == 4 && a.depth == 2) partial_kernel_4<2><<<dim3(nc, F, (a.n_groups + 3) / 4), dim3(256), 0, s>>>(a);
+    else if (V == 4) partial_kernel_4<4><<<dim3(nc, F, (a.n_groups + 3) / 4), dim3(256), 0, s>>>(a);
     else partial_kernel_1<<<dim3(nc, F, (a.n_groups + 3) / 4), dim3(256), 0, s>>>(a);
     SK_HIP_TRY(hipGetLastError());
   }

@@ -62,7 +62,18 @@ __device__ __forceinline__ void chunk_sum_body(const PassBArgs& a, int c, int f,
   IVec<V> s;
 #pragma unroll
   for (int k = 0; k < V; ++k) s.v[k] = 0;
-  for (int64_t e = e0; e < e1; ++e) {
+  // Rows in groups of 8 loaded together (independent loads in flight).
+  int64_t e = e0;
+  for (; e + 8 <= e1; e += 8) {
+    IVec<V> x[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) x[u].load(seq_row(a, f, e + u) + i0);
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int k = 0; k < V; ++k) s.v[k] += x[u].v[k];
+  }
+  for (; e < e1; ++e) {
     IVec<V> x;
     x.load(seq_row(a, f, e) + i0);
 #pragma unroll
@@ -337,6 +348,8 @@ __device__ __forceinline__ void finalize_body(const PassBArgs& a, int64_t blk) {
   double A = 0.0, Bq = 0.0;
   int64_t R1 = 0, R2 = 0;
   int32_t n = 0;
+  // Group order is fixed; the loads of 8 groups are issued together.
+#pragma unroll 8
   for (int g = 0; g < a.n_groups; ++g) {
     const int64_t o = ((int64_t)f * a.n_groups + g) * a.n_blocks + b;
     A += a.part_a[o];
