@@ -120,30 +120,43 @@ __device__ void window_sum(const PassBArgs& a, int f, int64_t lo, int64_t hi, in
 // inside each row of 16 lanes (quad_perm xor 1, xor 2, half-row mirror, row
 // mirror), then row_bcast:15 and row_bcast:31 fold the four rows; the total
 // lands in lane 63. The order of additions is fixed.
+// With every row enabled (the butterflies) each lane is written, so a plain
+// DPP move suffices; the broadcast steps enable some rows only, and the
+// others must read 0, so they keep an explicit zero as the old value.
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ uint32_t dpp_mov(uint32_t v) {
-  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, 0xF, false);
+  if constexpr (ROW_MASK == 0xF)
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, ROW_MASK, 0xF, false);
+  else
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, 0xF, false);
 }
+
+// 64-bit values move as their two 32-bit halves; the halves are regrouped
+// through a two-lane vector (a register pair, no shifts or adds).
+typedef uint32_t dpp_u32x2 __attribute__((ext_vector_type(2)));
 
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ double dpp_step(double v) {
-  const uint64_t u = __builtin_bit_cast(uint64_t, v);
-  const uint32_t lo = dpp_mov<CTRL, ROW_MASK>((uint32_t)u);
-  const uint32_t hi = dpp_mov<CTRL, ROW_MASK>((uint32_t)(u >> 32));
-  return v + __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+  const dpp_u32x2 u = __builtin_bit_cast(dpp_u32x2, v);
+  dpp_u32x2 m;
+  m.x = dpp_mov<CTRL, ROW_MASK>(u.x);
+  m.y = dpp_mov<CTRL, ROW_MASK>(u.y);
+  return v + __builtin_bit_cast(double, m);
 }
 
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ int64_t dpp_step(int64_t v) {
-  const uint64_t u = (uint64_t)v;
-  const uint32_t lo = dpp_mov<CTRL, ROW_MASK>((uint32_t)u);
-  const uint32_t hi = dpp_mov<CTRL, ROW_MASK>((uint32_t)(u >> 32));
-  return v + (int64_t)(((uint64_t)hi << 32) | lo);
+  const dpp_u32x2 u = __builtin_bit_cast(dpp_u32x2, v);
+  dpp_u32x2 m;
+  m.x = dpp_mov<CTRL, ROW_MASK>(u.x);
+  m.y = dpp_mov<CTRL, ROW_MASK>(u.y);
+  return v + __builtin_bit_cast(int64_t, m);
 }
 
+// 32-bit sums: the zero-old form folds into one v_add_u32 with a DPP source.
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ int32_t dpp_step(int32_t v) {
-  return v + (int32_t)dpp_mov<CTRL, ROW_MASK>((uint32_t)v);
+  return v + __builtin_amdgcn_update_dpp(0, v, CTRL, ROW_MASK, 0xF, false);
 }
 
 // Sum over the 64 lanes, valid in lane 63.
