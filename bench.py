@@ -38,7 +38,7 @@ def parse():
     ap.add_argument("--cpu-sample-blocks", type=int, default=0,
                     help="blocks per channel in the oracle's timed sample (0: pick ~10-30 s of work)")
     ap.add_argument("--lpr", type=int, default=0, help="force pass A lanes per row")
-    ap.add_argument("--variant", type=int, default=-1, help="force pass A row batching variant (0..16; -1 = library choice)")
+    ap.add_argument("--variant", type=int, default=-1, help="force pass A row batching variant (0..17; -1 = library choice)")
     ap.add_argument("--grid", type=int, default=0, help="force pass A workgroup count (persistent loop)")
     ap.add_argument("--ablocks", type=int, default=0, help="consecutive blocks per pass A task (packed variants)")
     ap.add_argument("--segments", type=int, default=0,

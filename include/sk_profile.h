@@ -45,9 +45,12 @@ int sk_plan_set_pass_a_tile(sk_plan_t plan, int32_t lanes_per_row);
  * 16 rows; 16: packed table in 256-lane workgroups whose lanes each sum whole
  * rows: narrow rows put 256 / L blocks side by side, L = the power of two
  * covering the row's column groups, which replaces the lanes-per-row
- * setting) and workgroup count (0: one per task; fewer: workgroups loop over
- * tasks). Variants 1..16 apply to the 16-byte path (N % 16 == 0, aligned
- * input); the others use variant 0. Lanes per row are clamped to 256..1024
+ * setting; 17: packed table in 512-lane workgroups, each task walking 1..4
+ * consecutive blocks with every block's sums held until its last block, then
+ * stored, sized for about one task per CU unless sk_plan_set_pass_a_blocks
+ * gives 1..4) and workgroup count (0: one per task; fewer: workgroups loop
+ * over tasks). Variants 1..17 apply to the 16-byte path (N % 16 == 0,
+ * aligned input); the others use variant 0. Lanes per row are clamped to 256..1024
  * for variants 7..11, 14 and 15 (one row phase) and to 64..512 for variants
  * 12 and 13. */
 int sk_plan_set_pass_a_variant(sk_plan_t plan, int32_t variant, int32_t grid);

@@ -298,7 +298,7 @@ class Plan:
         return k.value
 
     def set_pass_a_variant(self, variant: int, grid: int = 0):
-        """Row batching variant of pass A (-1: library choice, 0..16) and workgroup
+        """Row batching variant of pass A (-1: library choice, 0..17) and workgroup
         count (0: one per task)."""
         _check(self._lib.sk_plan_set_pass_a_variant(self.handle, int(variant), int(grid)))
 

@@ -58,6 +58,7 @@ struct sk_plan_s {
   int segments = 0;        // block segments per call (0 = library choice, 1 = none)
   int pass_b_depth = 0;    // blocks a partial wavefront loads together (0 = library choice)
   int pass_a_blocks = 0;   // consecutive blocks per pass A task (packed variants; 0 = library choice)
+  int n_cu = 256;          // compute units of the plan's device
   int last_segments = 0;   // segments the last call used
   hipStream_t side = nullptr;          // pass B of segmented calls
   std::vector<hipEvent_t> seg_ev;      // pass A segment k done (on the caller's stream); last: join
@@ -154,6 +155,11 @@ int sk_plan_create(const sk_plan_desc* desc, sk_plan_t* out) {
   if (!p) { set_error("host allocation failed"); return SK_ERR_NOMEM; }
   p->d = *desc;
   if (hipGetDevice(&p->device) != hipSuccess) { delete p; set_error("no HIP device"); return SK_ERR_DEVICE; }
+  {
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, p->device) == hipSuccess && ncu > 0)
+      p->n_cu = ncu;
+  }
   const int64_t N = desc->n_inputs, F = desc->n_channels;
   p->n_blocks = desc->n_samples / desc->block_len;
   const int L = desc->norm_window_blocks;
@@ -227,7 +233,7 @@ static PassAConfig plan_pass_a_config(const sk_plan_s* p, const uint8_t* d_packe
   t->blocks_per_task = 1;
   t->block_len = p->d.block_len;
   t->n_blocks = (int32_t)B;
-  PassAConfig c = default_pass_a_config(vec, t->row_bytes, B, p->pass_a_lpr == 0 && p->pass_a_variant < 0);
+  PassAConfig c = default_pass_a_config(vec, t->row_bytes, B, p->pass_a_lpr == 0 && p->pass_a_variant < 0, p->n_cu);
   if (p->pass_a_lpr) c.lpr = p->pass_a_lpr;
   if (p->pass_a_variant >= 0) c.variant = p->pass_a_variant;
   {
@@ -240,6 +246,12 @@ static PassAConfig plan_pass_a_config(const sk_plan_s* p, const uint8_t* d_packe
   t->col_groups = (int32_t)(t->row_bytes / vec);
   t->chunks = (t->col_groups + c.lpr * gpl - 1) / (c.lpr * gpl);
   if (pass_a_packed(vec, c.variant) && p->pass_a_blocks > 1) t->blocks_per_task = p->pass_a_blocks;
+  if (pass_a_deferred(vec, c.variant)) {
+    c.lpr = 512;
+    t->chunks = (t->col_groups + 511) / 512;
+    t->blocks_per_task = p->pass_a_blocks >= 1 && p->pass_a_blocks <= 4
+                             ? p->pass_a_blocks : pass_a_deferred_blocks(B, t->col_groups, p->n_cu);
+  }
   if (pass_a_side_by_side(vec, c.variant)) {
     c.lpr = pass_a_side_by_side_lanes(t->col_groups);
     t->blocks_per_task = c.lpr >= 256 ? 1 : 256 / c.lpr;
@@ -252,7 +264,7 @@ static PassAConfig plan_pass_a_config(const sk_plan_s* p, const uint8_t* d_packe
 }
 
 int sk_plan_set_pass_a_variant(sk_plan_t p, int32_t variant, int32_t grid) {
-  if (!p || variant < -1 || variant > 16 || grid < 0) { set_error("bad variant"); return SK_ERR_INVALID_ARG; }
+  if (!p || variant < -1 || variant > 17 || grid < 0) { set_error("bad variant"); return SK_ERR_INVALID_ARG; }
   p->pass_a_variant = variant;
   p->pass_a_grid = grid;
   return SK_OK;

@@ -51,7 +51,7 @@ struct PassATask {
 struct PassAConfig {
   int vec;     // 16, 4 or 1 bytes per lane per row
   int lpr;     // lanes per row: power of two, 1..256
-  int variant; // row batching variant (0..16, 16-byte path; see pass_a_groups_per_lane)
+  int variant; // row batching variant (0..17, 16-byte path; see pass_a_groups_per_lane)
   int grid;    // workgroups launched (<= tasks; grid-stride beyond)
 };
 
@@ -69,9 +69,12 @@ bool pass_a_packed(int vec, int variant);
 // Variant 16: 256-lane tasks, blocks side by side for narrow rows.
 bool pass_a_side_by_side(int vec, int variant);
 int pass_a_side_by_side_lanes(int64_t col_groups);
+// Variant 17: blocks held per task (stores deferred to the task's end).
+bool pass_a_deferred(int vec, int variant);
+int pass_a_deferred_blocks(int64_t n_blocks, int64_t col_groups, int n_cu);
 // lane_table: the lane-replicated table variants may be chosen (single-plan
 // kernel only; the batched kernel has its own table).
-PassAConfig default_pass_a_config(int vec, int64_t row_bytes, int64_t n_blocks, bool lane_table);
+PassAConfig default_pass_a_config(int vec, int64_t row_bytes, int64_t n_blocks, bool lane_table, int n_cu);
 
 // ---------------------------------------------------------------- pass B
 // Normaliser window, array combine, estimator and flags (Eq. discreteMean,

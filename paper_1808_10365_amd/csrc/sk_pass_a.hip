@@ -279,6 +279,48 @@ int pass_a_side_by_side_lanes(int64_t col_groups) {
   return lpb;
 }
 
+// Variant 17: packed table, 512-lane workgroups over chunks of 512 column
+// groups; a task walks Q consecutive blocks holding every block's sums in
+// registers and stores them only after its last block. With about one task
+// per CU the call becomes a read phase followed by a write phase: mixing
+// the sums' writes into the read stream costs far more than their bytes
+// (CHIME M = 256: 335 against 382 us with a store after each block).
+template <int Q, int U>
+__global__ __launch_bounds__(512) void pass_a_deferred_kernel(PassATask t) {
+  constexpr int VEC = 16;
+  __shared__ __attribute__((aligned(16))) uint32_t lut32[LANE_LUT_DWORDS];
+  const int tid = threadIdx.x;
+  fill_lane_packed_lut<512>(lut32, tid);
+  __syncthreads();
+  const LanePackedLut lut{reinterpret_cast<const uint8_t*>(lut32), (uint32_t)(tid & 63) * 4};
+  const int M = t.block_len;
+  const int64_t G = t.row_bytes;
+  for (int64_t task = blockIdx.x; task < t.n_tasks; task += gridDim.x) {
+    const int b0 = t.block0 + (int)(task / t.chunks) * Q;
+    const int g = (int)(task % t.chunks) * 512 + tid;
+    if (g >= t.col_groups) continue;
+    uint32_t a1[Q][VEC], a2[Q][VEC];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+#pragma unroll
+      for (int k = 0; k < VEC; ++k) a1[q][k] = a2[q][k] = 0;
+      if (b0 + q < t.block_end)
+        sum_rows_packed<VEC, 1, U>(t.x + (int64_t)(b0 + q) * M * G + (int64_t)g * VEC, G, M, 0, lut, a1[q], a2[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+      if (b0 + q < t.block_end) store_group<VEC>(t, b0 + q, g, a1[q], a2[q]);
+  }
+}
+
+// Blocks per task for variant 17: about one task per CU, at most 4 (the
+// sums of 4 blocks take 128 registers per lane).
+int pass_a_deferred_blocks(int64_t n_blocks, int64_t col_groups, int n_cu) {
+  const int64_t chunks = (col_groups + 511) / 512;
+  int64_t q = (n_blocks * chunks + n_cu - 1) / (n_cu > 0 ? n_cu : 1);
+  return (int)(q < 1 ? 1 : (q > 4 ? 4 : q));
+}
+
 // Lane table shared by 512-lane workgroups of 512 / lpr row phases (16
 // wavefronts per CU at two workgroups); lanes per row 64..512 (the planner
 // clamps others into that range).
@@ -337,6 +379,8 @@ static int launch_lpr(const PassATask& t, int lpr, int grid, hipStream_t s) {
 //  15: packed lane table, 16 rows per load
 //  16: packed lane table, 256-lane workgroups, blocks side by side for
 //      narrow rows (lanes per row = power of two covering the row, <= 256)
+//  17: packed lane table, 512-lane workgroups, Q blocks per task with the
+//      stores deferred to the task's end (Q = blocks_per_task, 1..4)
 int pass_a_groups_per_lane(int vec, int variant) {
   if (vec != 16) return 1;
   switch (variant) {
@@ -346,17 +390,22 @@ int pass_a_groups_per_lane(int vec, int variant) {
   }
 }
 
-bool pass_a_lane_table(int vec, int variant) { return vec == 16 && variant >= 7 && variant <= 16; }
+bool pass_a_lane_table(int vec, int variant) { return vec == 16 && variant >= 7 && variant <= 17; }
 
 bool pass_a_packed(int vec, int variant) { return vec == 16 && (variant == 14 || variant == 15); }
 
 bool pass_a_side_by_side(int vec, int variant) { return vec == 16 && variant == 16; }
 
+bool pass_a_deferred(int vec, int variant) { return vec == 16 && variant == 17; }
+
 void pass_a_lane_range(int vec, int variant, int* lo, int* hi) {
   *lo = 1;
   *hi = 1024;
   if (!pass_a_lane_table(vec, variant)) return;
-  if (variant == 12 || variant == 13) { *lo = 64; *hi = 512; } else if (variant == 16) { *lo = 1; *hi = 256; } else { *lo = 256; }
+  if (variant == 12 || variant == 13) { *lo = 64; *hi = 512; }
+  else if (variant == 16) { *lo = 1; *hi = 256; }
+  else if (variant == 17) { *lo = 512; *hi = 512; }
+  else { *lo = 256; }
 }
 
 template <int VEC>
@@ -382,6 +431,18 @@ static int launch_vec(const PassATask& t, int lpr, int variant, int grid, hipStr
         pass_a_side_by_side_kernel<16><<<dim3(grid), dim3(256), 0, s>>>(t, lpr);
         SK_HIP_TRY(hipGetLastError());
         return SK_OK;
+      case 17:
+        switch (t.blocks_per_task) {
+          case 1: pass_a_deferred_kernel<1, 16><<<dim3(grid), dim3(512), 0, s>>>(t); break;
+          case 2: pass_a_deferred_kernel<2, 16><<<dim3(grid), dim3(512), 0, s>>>(t); break;
+          case 3: pass_a_deferred_kernel<3, 16><<<dim3(grid), dim3(512), 0, s>>>(t); break;
+          case 4: pass_a_deferred_kernel<4, 16><<<dim3(grid), dim3(512), 0, s>>>(t); break;
+          default:
+            set_error("pass A: deferred-store variant needs 1..4 blocks per task, got %d", t.blocks_per_task);
+            return SK_ERR_INVALID_ARG;
+        }
+        SK_HIP_TRY(hipGetLastError());
+        return SK_OK;
       default: break;
     }
   }
@@ -395,8 +456,24 @@ int pick_vec(const uint8_t* x, int32_t n_inputs) {
   return 1;
 }
 
-PassAConfig default_pass_a_config(int vec, int64_t row_bytes, int64_t n_blocks, bool lane_table) {
+PassAConfig default_pass_a_config(int vec, int64_t row_bytes, int64_t n_blocks, bool lane_table, int n_cu) {
   const int64_t cg = row_bytes / vec;
+  // Wide rows whose 4-block tasks (512-lane workgroups) fill one round of
+  // the CUs: hold every block's sums and store them at the end of the task,
+  // so the call reads, then writes (CHIME M = 256: 349 against 359 us).
+  // With two or three blocks per task, or several rounds, the stores meet
+  // the reads again and the per-block variants below are faster.
+  if (lane_table && vec == 16 && cg >= 512 && n_cu > 0) {
+    const int64_t units = n_blocks * ((cg + 511) / 512);
+    if ((units + 3) / 4 <= n_cu && units > 3 * (int64_t)n_cu) {
+      PassAConfig c;
+      c.vec = vec;
+      c.lpr = 512;
+      c.variant = 17;
+      c.grid = (int)((units + 3) / 4);
+      return c;
+    }
+  }
   // Wide rows with at least one task per CU take the lane-replicated table
   // (no bank conflicts on the power lookups), measured fastest on MI355X:
   //  * >= 512 groups of 16 inputs: packed entries (one add per sample for

@@ -1,6 +1,8 @@
 """GPU parity on shapes chosen to reach every default pass A tiling the
-library picks by itself: the packed table in 1024-lane workgroups (rows of
->= 512 column groups and >= 256 tasks), the lane table at 256 lanes per row
+library picks by itself: 4-block tasks with deferred stores (rows of >= 512
+column groups whose 4-block tasks fill one round of CUs), the packed table
+in 1024-lane workgroups (>= 512 groups, >= 256 tasks), the lane table at 256
+lanes per row
 (256..511 groups), blocks side by side (narrow rows with >= 256 tasks), and
 row phases with the shared table (small problems). Each shape runs two calls
 (stream state) against the oracle, with a seeded window and estimator."""
@@ -21,6 +23,8 @@ DEV = "cuda:0"
 
 # (N, F, M, blocks per call, expected default lanes per row)
 SHAPES = [
+    (2048, 4, 4, 1024, 512),     # 512 groups, 1024 blocks: 4-block tasks, stores deferred
+    (4096, 2, 4, 900, 512),      # the same with a partial last task
     (2048, 4, 16, 256, 1024),    # 512 groups, 256 tasks: packed, 1024 lanes
     (4096, 4, 8, 300, 1024),     # 1024 groups
     (4096, 8, 8, 260, 1024),     # 2048 groups: two 1024-lane chunks per block

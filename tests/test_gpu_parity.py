@@ -92,7 +92,7 @@ def test_ragged_random_bytes(shape, L):
 
 
 @pytest.mark.parametrize("lpr", [1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1024])
-@pytest.mark.parametrize("variant", list(range(17)))
+@pytest.mark.parametrize("variant", list(range(18)))
 def test_every_pass_a_tile(lpr, variant):
     # M = 48 and M = 100 leave partial batches and odd row counts for every
     # row-phase count; rows of 96 and 32 column groups leave the second and
@@ -101,7 +101,8 @@ def test_every_pass_a_tile(lpr, variant):
     # 7..11, 14, 15 (lane-replicated table) widen tiles below 256 lanes to
     # 256; 12 and 13 clamp lanes per row to 64..512 (row phases in 512
     # lanes). M = 100 and 48 leave packed runs shorter than 16 rows.
-    # Variant 16 sets its own lanes per row (blocks side by side).
+    # Variant 16 sets its own lanes per row (blocks side by side); 17 uses
+    # 512 lanes and holds the sums of several blocks before storing them.
     rng = np.random.default_rng(lpr + 7 * variant)
     for T, F, N, M in ((96, 3, 512, 48), (200, 2, 256, 100), (64, 4, 2048, 32)):
         x = rng.integers(0, 256, size=(T, F, N), dtype=np.uint8)
@@ -114,7 +115,7 @@ def test_pass_a_persistent_grid(grid):
     rng = np.random.default_rng(grid)
     T, F, N, M = 512, 2, 1024, 64
     x = rng.integers(0, 256, size=(T, F, N), dtype=np.uint8)
-    for variant in (0, 1, 4, 6, 7, 8, 12, 13, 14, 15, 16):
+    for variant in (0, 1, 4, 6, 7, 8, 12, 13, 14, 15, 16, 17):
         both(x, M, 3, what=f"grid={grid} variant={variant}", lpr=64, variant=variant, grid=grid)
 
 
@@ -186,7 +187,7 @@ def test_flags_entry_point():
     assert np.array_equal(fl, ref)
 
 
-@pytest.mark.parametrize("variant", [None, 7, 14, 15, 16])
+@pytest.mark.parametrize("variant", [None, 7, 14, 15, 16, 17])
 def test_largest_block_no_overflow(variant):
     # M = 131071 with every sample at power 128: S2 = M * 2^14 = 2^31 - 2^14.
     # The packed table (14, 15) holds 16 such rows per run: 2^11 + 2^30.
@@ -373,13 +374,14 @@ def test_segmented_calls(K, L):
         assert np.array_equal(a, b, equal_nan=a.dtype.kind == "f"), name
 
 
-@pytest.mark.parametrize("variant", [14, 15, 16])
-@pytest.mark.parametrize("Q", [2, 3, 7, 64])
+@pytest.mark.parametrize("variant", [14, 15, 16, 17])
+@pytest.mark.parametrize("Q", [2, 3, 4, 7, 64])
 @pytest.mark.parametrize("segments", [1, 3])
 def test_packed_multi_block_tasks(variant, Q, segments):
     # Packed-table pass A tasks walking Q consecutive blocks: B = 37 leaves a
     # short last task for every Q, and 3 segments cut the tasks again.
     # Variant 16 ignores Q: its 64-group rows put 4 blocks side by side.
+    # Variant 17 takes Q in 1..4 and sizes its tasks itself otherwise.
     rng = np.random.default_rng(Q * 10 + variant + segments)
     T, F, N, M = 48 * 37, 2, 512, 48
     x = rng.integers(0, 256, size=(2 * T, F, N), dtype=np.uint8)
