@@ -38,3 +38,23 @@ def build_library(verbose: bool = False) -> str:
     subprocess.run(cmd, check=True, env=env)
     os.replace(tmp, LIB)
     return LIB
+
+
+C_ABI_CHECK_SRC = os.path.join(ROOT, "tests", "c_abi", "sk_c_abi_check.c")
+C_ABI_CHECK_BIN = os.path.join(ROOT, "tests", "c_abi", "sk_c_abi_check")
+
+
+def build_c_abi_check(verbose: bool = False) -> str:
+    """Compile the plain C client of the library (gcc; links libsk.so and the
+    HIP runtime's C API)."""
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    tmp = C_ABI_CHECK_BIN + ".tmp"
+    cmd = ["gcc", "-O2", "-std=c11", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(rocm, "include"),
+           "-I", os.path.join(ROOT, "include"), C_ABI_CHECK_SRC, "-o", tmp,
+           "-L", _HERE, "-lsk", "-L", os.path.join(rocm, "lib"), "-lamdhip64",
+           "-Wl,-rpath," + _HERE, "-Wl,-rpath,$ORIGIN/../../paper_1808_10365_amd", "-Wl,-rpath," + os.path.join(rocm, "lib")]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, C_ABI_CHECK_BIN)
+    return C_ABI_CHECK_BIN
