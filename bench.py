@@ -33,7 +33,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="chime256",
-                    choices=["chime256", "chime1024", "pathfinder", "tiny"])
+                    choices=["chime256", "chime1024", "pathfinder", "tiny", "serve2048", "serve256"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-blocks", type=int, default=0,
                     help="blocks per channel in the oracle's timed sample (0: pick ~10-30 s of work)")
@@ -68,6 +68,10 @@ def workload(name):
         return synth.chime(seed=3, block_len=1024)
     if name == "pathfinder":
         return synth.pathfinder(seed=2)
+    if name == "serve2048":
+        return synth.serving_array(2048)
+    if name == "serve256":
+        return synth.serving_array(256)
     return synth.tiny(seed=1, norm_window=4)
 
 
