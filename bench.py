@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--variant", type=int, default=-1, help="force pass A row batching variant (0..17; -1 = library choice)")
     ap.add_argument("--grid", type=int, default=0, help="force pass A workgroup count (persistent loop)")
     ap.add_argument("--ablocks", type=int, default=0, help="consecutive blocks per pass A task (packed variants)")
+    ap.add_argument("--fused", type=int, default=0,
+                    help="single-launch path: 0 never (default), 1 whenever the shape allows")
     ap.add_argument("--segments", type=int, default=0,
                     help="block segments per call (0 = library choice, 1 = pass B after pass A)")
     ap.add_argument("--chunk", type=int, default=0, help="force pass B chunk length (blocks)")
@@ -394,6 +396,8 @@ def main():
         plan.set_pass_a_variant(args.variant, args.grid)
     if args.chunk or args.bvec:
         plan.set_pass_b_tile(args.chunk, args.bvec)
+    if args.fused:
+        plan.set_fused(args.fused)
     if args.segments:
         plan.set_segments(args.segments)
     if args.ablocks:
@@ -460,6 +464,7 @@ def main():
     # of (near) equal size; per launch: the call's bytes and pass A time over
     # the launch count.
     launches = max(1, plan.last_segments())
+    fused = plan.last_fused()
     pass_a_bytes = (in_bytes + 8 * fbn) / launches
     a_avg = float(ms_a.mean()) / launches
     achieved = pass_a_bytes / (a_avg * 1e-3) / 1e9
@@ -495,13 +500,16 @@ def main():
                              "p99": round(float(np.percentile(step_ms, 99)), 4),
                              "note": "device time of one sk_compute (pass A + pass B), HIP events"},
         "pass_ms": {"pass_a_avg": round(float(ms_a.mean()), 4), "pass_b_avg": round(float(ms_b.mean()), 4),
-                    "pass_a_launches": launches,
-                    "note": "pass A: all of a call's pass A launches; pass B: what is left after them "
-                            "(pass B of earlier segments overlaps pass A on a second stream)"},
+                    "pass_a_launches": launches, "single_launch": fused,
+                    "note": ("single launch: pass A time is the whole cooperative kernel (pass A, window scans "
+                             "and pass B); pass B time is what follows it" if fused else
+                             "pass A: all of a call's pass A launches; pass B: what is left after them "
+                             "(pass B of earlier segments overlaps pass A on a second stream)")},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
-                     "kernel": "pass_a_kernel (per-input block sums)",
+                     "kernel": ("fused_kernel (pass A, window scans and pass B in one cooperative launch)"
+                                if fused else "pass_a kernel (per-input block sums)"),
                      "algorithmic_bytes_per_launch": round(pass_a_bytes), "launches_per_step": launches},
         "flagged_fraction": round(flagged, 5),
     }

@@ -70,6 +70,22 @@ int sk_plan_set_segments(sk_plan_t plan, int32_t segments);
  * first call. */
 int sk_plan_get_last_segments(sk_plan_t plan, int32_t* segments);
 
+/* Single-launch path: one cooperative kernel per call (pass A, the window
+ * prefix scans across workgroups, then the combine, V and flags of each
+ * workgroup's blocks), for 16-byte lanes, N % 1024 == 0, F N / 16 <= 512
+ * column groups, a window of L >= 2 blocks, one segment, and at most 4
+ * blocks per workgroup with one workgroup per CU. mode 0 (the default):
+ * never; 1: whenever the shape allows (its scratch, 2 n_cu F N + (L-1) F N
+ * int32, is allocated by this call; SK_ERR_NOMEM if that fails). Calls of
+ * other shapes run the two-pass path. Results equal the two-pass path's
+ * integer outputs and flags; V differs only by the order of its FP64 sums.
+ * Off by default because each of its two grid-wide barriers costs more
+ * than the separate launches and the S1/S2 re-read that it saves. */
+int sk_plan_set_fused(sk_plan_t plan, int32_t mode);
+
+/* 1 if the plan's last sk_compute ran the single-launch path. */
+int sk_plan_get_last_fused(sk_plan_t plan, int32_t* fused);
+
 /* Consecutive blocks one pass A task walks with the packed-table variants
  * (14, 15): 1..4096, 0 = library choice. Longer tasks stream longer
  * contiguous runs of rows per workgroup. */

@@ -113,6 +113,8 @@ def load_library():
     lib.sk_plan_set_pass_b_depth.argtypes = [VP, I32]
     lib.sk_plan_set_pass_a_blocks.argtypes = [VP, I32]
     lib.sk_plan_get_last_segments.argtypes = [VP, ctypes.POINTER(I32)]
+    lib.sk_plan_set_fused.argtypes = [VP, I32]
+    lib.sk_plan_get_last_fused.argtypes = [VP, ctypes.POINTER(I32)]
     lib.sk_server_now.restype = ctypes.c_double
     lib.sk_server_create.argtypes = [ctypes.POINTER(ServerDesc), ctypes.POINTER(VP)]
     lib.sk_server_add_array.argtypes = [VP, ctypes.POINTER(PlanDesc), ctypes.POINTER(I32)]
@@ -139,7 +141,7 @@ def load_library():
     for name in ("sk_plan_create", "sk_plan_destroy", "sk_plan_device_bytes", "sk_compute", "sk_flags",
                  "sk_state_reset", "sk_state_size", "sk_state_export", "sk_state_import",
                  "sk_digitised_expectation", "sk_plan_set_pass_a_tile", "sk_plan_get_pass_a_tile",
-                 "sk_profile_enable", "sk_profile_read", "sk_plan_set_pass_a_variant", "sk_read_probe", "sk_plan_set_segments", "sk_plan_set_pass_b_depth", "sk_plan_set_pass_a_blocks",
+                 "sk_profile_enable", "sk_profile_read", "sk_plan_set_pass_a_variant", "sk_read_probe", "sk_plan_set_segments", "sk_plan_set_pass_b_depth", "sk_plan_set_pass_a_blocks", "sk_plan_set_fused", "sk_plan_get_last_fused",
                  "sk_plan_get_last_segments"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -290,6 +292,16 @@ class Plan:
     def set_pass_b_depth(self, depth: int):
         """Blocks a pass B partial wavefront loads together (0: library choice, 2, 4, 8)."""
         _check(self._lib.sk_plan_set_pass_b_depth(self.handle, int(depth)))
+
+    def set_fused(self, mode: int):
+        """Single-launch path: 0 never (default), 1 whenever the shape allows."""
+        _check(self._lib.sk_plan_set_fused(self.handle, int(mode)))
+
+    def last_fused(self) -> bool:
+        """Whether the last call ran the single-launch path."""
+        k = ctypes.c_int32()
+        _check(self._lib.sk_plan_get_last_fused(self.handle, ctypes.byref(k)))
+        return bool(k.value)
 
     def last_segments(self) -> int:
         """Segments (pass A launches) of the last call."""

@@ -49,6 +49,11 @@ struct sk_plan_s {
   int64_t* part_r2;
   int32_t* part_n;
   int32_t* hist[2];        // [F][hist_cap][N], ping-pong
+  int32_t* seg_sum = nullptr;   // single-launch path: [n_cu][F*N] segment sums
+  int32_t* seg_pre = nullptr;   //   [n_cu][F*N] exclusive prefixes over segments
+  int32_t* hist_suf = nullptr;  //   [hist_cap][F*N] history suffix sums
+  int fused_mode = 0;      // 1: single launch wherever the shape allows
+  int last_fused = 0;      // whether the last call ran the single-launch path
   int32_t cur;             // index of the live history buffer
   size_t bytes;
   int pass_a_lpr;          // 0 = heuristic
@@ -124,6 +129,9 @@ static void free_plan_memory(sk_plan_s* p) {
   if (p->part_n) (void)hipFree(p->part_n);
   if (p->hist[0]) (void)hipFree(p->hist[0]);
   if (p->hist[1]) (void)hipFree(p->hist[1]);
+  if (p->seg_sum) (void)hipFree(p->seg_sum);
+  if (p->seg_pre) (void)hipFree(p->seg_pre);
+  if (p->hist_suf) (void)hipFree(p->hist_suf);
 }
 
 #define SK_ALLOC(ptr, nbytes)                                                     \
@@ -288,6 +296,46 @@ int sk_plan_set_pass_b_depth(sk_plan_t p, int32_t depth) {
   clear_error();
   if (!p || (depth != 0 && depth != 2 && depth != 4 && depth != 8)) { set_error("depth must be 0, 2, 4 or 8"); return SK_ERR_INVALID_ARG; }
   p->pass_b_depth = depth;
+  return SK_OK;
+}
+
+int sk_plan_set_fused(sk_plan_t p, int32_t mode) {
+  clear_error();
+  if (!p || mode < 0 || mode > 1) { set_error("mode must be 0 or 1"); return SK_ERR_INVALID_ARG; }
+  p->fused_mode = mode;
+  const int64_t F = p->d.n_channels, N = p->d.n_inputs;
+  // Scratch of the single-launch path, allocated the first time it is
+  // switched on for a shape it serves: wide rows covered by one 512-lane
+  // workgroup, whole channels per wavefront, at most 4 blocks per workgroup
+  // in one round of the CUs, a window of at least 2 blocks.
+  if (mode == 1 && !p->seg_sum && p->d.norm_window_blocks >= 2 && N % 1024 == 0 && (F * N) / 16 <= 512 &&
+      p->n_blocks <= 4 * (int64_t)p->n_cu) {
+    const size_t seg = (size_t)p->n_cu * F * N * sizeof(int32_t);
+    const size_t suf = (size_t)p->hist_cap * F * N * sizeof(int32_t);
+    int32_t *a = nullptr, *b = nullptr, *c = nullptr;
+    hipError_t e = hipMalloc((void**)&a, seg);
+    if (e == hipSuccess) e = hipMalloc((void**)&b, seg);
+    if (e == hipSuccess) e = hipMalloc((void**)&c, suf);
+    if (e != hipSuccess) {
+      if (a) (void)hipFree(a);
+      if (b) (void)hipFree(b);
+      if (c) (void)hipFree(c);
+      p->fused_mode = 0;
+      set_error("hipMalloc for the single-launch path failed: %s", hipGetErrorString(e));
+      return SK_ERR_NOMEM;
+    }
+    p->seg_sum = a;
+    p->seg_pre = b;
+    p->hist_suf = c;
+    p->bytes += 2 * seg + suf;
+  }
+  return SK_OK;
+}
+
+int sk_plan_get_last_fused(sk_plan_t p, int32_t* fused) {
+  clear_error();
+  if (!p || !fused) { set_error("NULL argument"); return SK_ERR_INVALID_ARG; }
+  *fused = p->last_fused;
   return SK_OK;
 }
 
@@ -464,7 +512,34 @@ int sk_compute(sk_plan_t p, const uint8_t* d_packed, const uint8_t* d_mask, cons
   const bool rec = p->prof_n < p->prof_max;
   if (rec) SK_HIP_TRY(hipEventRecord(p->prof[3 * p->prof_n], s));
   int rc = SK_OK;
-  if (K <= 1) {
+
+  // Single launch when it is switched on and the shape allows it. Off by
+  // default: the two grid-wide barriers it needs cost more than the launches
+  // and the S1/S2 re-read that it saves.
+  const int fq = (int)((B + p->n_cu - 1) / p->n_cu);
+  bool fused = p->fused_mode != 0 && K <= 1 && p->seg_sum && c.vec == 16 && d.norm_window_blocks >= 2 &&
+               fq >= 1 && fq <= 4;
+  if (fused) {
+    const int grid = (int)((B + fq - 1) / fq);
+    if (grid > fused_max_workgroups()) fused = false;
+  }
+  p->last_fused = fused ? 1 : 0;
+  if (fused) {
+    FusedArgs fa;
+    memset(&fa, 0, sizeof fa);
+    fa.a = t;
+    fa.a.s2 = outs->s2;           // S2 in memory only when requested
+    fa.b = a;
+    fa.b.chunk0 = 0;
+    fa.b.fin_b0 = 0;
+    fa.b.fin_nb = (int32_t)B;
+    fa.segsum = p->seg_sum;
+    fa.segpre = p->seg_pre;
+    fa.hsuf = p->hist_suf;
+    rc = launch_fused(fa, fq, s);
+    if (rc) return rc;
+    if (rec) SK_HIP_TRY(hipEventRecord(p->prof[3 * p->prof_n + 1], s));
+  } else if (K <= 1) {
     rc = launch_pass_a(t, c, s);
     if (rc) return rc;
     if (rec) SK_HIP_TRY(hipEventRecord(p->prof[3 * p->prof_n + 1], s));

@@ -122,6 +122,19 @@ int launch_pass_b(const PassBArgs& a, hipStream_t s);
 int launch_pass_b_range(PassBArgs a, int32_t c_begin, int32_t c_end, int32_t b_begin, int32_t b_end,
                         bool with_hist_copy, hipStream_t s);
 
+// ---------------------------------------------------------------- single launch
+// One cooperative kernel for wide rows filling one round of CUs (see
+// sk_fused.hip): pass A, the window scans and pass B of a call.
+struct FusedArgs {
+  PassATask a;          // x, s1 (always written), s2 (null: not stored), geometry
+  PassBArgs b;          // window, history, outputs, flag parameters
+  int32_t* segsum;      // [segments][F*N] S1 sums of each workgroup's blocks
+  int32_t* segpre;      // [segments][F*N] exclusive prefix over segments
+  int32_t* hsuf;        // [hist_cap][F*N] suffix sums of the history rows
+};
+int launch_fused(const FusedArgs& fa, int blocks_per_workgroup, hipStream_t s);
+int fused_max_workgroups();
+
 double pearson3_quantile(double mean, double sd, double skew, double p);
 
 struct FlagArgs {
