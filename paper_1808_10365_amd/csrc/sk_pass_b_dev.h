@@ -82,7 +82,28 @@ __device__ __forceinline__ void chunk_sum_body(const PassBArgs& a, int c, int f,
   s.store(a.chunk_sum + ((int64_t)f * a.n_chunks + c) * a.n_inputs + i0);
 }
 
-// Sum of S1 over sequence positions [lo, hi) for V inputs at i0.
+// Adds S1 of sequence positions [from, to) for V inputs at i0 into out,
+// eight rows loaded together (independent loads in flight, the last group
+// predicated).
+template <int V>
+__device__ __forceinline__ void add_rows(const PassBArgs& a, int f, int64_t from, int64_t to, int i0, int32_t* out) {
+  for (int64_t e = from; e < to; e += 8) {
+    IVec<V> x[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+#pragma unroll
+      for (int k = 0; k < V; ++k) x[u].v[k] = 0;
+      if (e + u < to) x[u].load(seq_row(a, f, e + u) + i0);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int k = 0; k < V; ++k) out[k] += x[u].v[k];
+  }
+}
+
+// Sum of S1 over sequence positions [lo, hi) for V inputs at i0: the chunk
+// sums of the chunks wholly inside, plus the rows at either edge.
 template <int V>
 __device__ void window_sum(const PassBArgs& a, int f, int64_t lo, int64_t hi, int i0, int32_t* out) {
 #pragma unroll
@@ -91,7 +112,6 @@ __device__ void window_sum(const PassBArgs& a, int f, int64_t lo, int64_t hi, in
   const int64_t R = a.chunk;
   const int64_t cs = (lo + R - 1) / R;   // first chunk fully inside
   const int64_t ce = hi / R;             // one past the last chunk fully inside
-  int64_t edge_hi = hi;
   if (cs < ce) {
 #pragma unroll 8
     for (int64_t c = cs; c < ce; ++c) {
@@ -100,19 +120,10 @@ __device__ void window_sum(const PassBArgs& a, int f, int64_t lo, int64_t hi, in
 #pragma unroll
       for (int k = 0; k < V; ++k) out[k] += t.v[k];
     }
-    for (int64_t e = ce * R; e < hi; ++e) {
-      IVec<V> x;
-      x.load(seq_row(a, f, e) + i0);
-#pragma unroll
-      for (int k = 0; k < V; ++k) out[k] += x.v[k];
-    }
-    edge_hi = cs * R;
-  }
-  for (int64_t e = lo; e < edge_hi; ++e) {
-    IVec<V> x;
-    x.load(seq_row(a, f, e) + i0);
-#pragma unroll
-    for (int k = 0; k < V; ++k) out[k] += x.v[k];
+    add_rows<V>(a, f, lo, cs * R, i0, out);
+    add_rows<V>(a, f, ce * R, hi, i0, out);
+  } else {
+    add_rows<V>(a, f, lo, hi, i0, out);
   }
 }
 
