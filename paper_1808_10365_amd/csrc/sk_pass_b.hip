@@ -41,6 +41,12 @@ __global__ __launch_bounds__(256) void partial_kernel_4(PassBArgs a) {
 __global__ __launch_bounds__(256) void chunk_sum_kernel_8(PassBArgs a) { chunk_sum_body<8>(a, a.chunk0 + blockIdx.x, blockIdx.y, blockIdx.z); }
 __global__ __launch_bounds__(256) void partial_kernel_8(PassBArgs a) { partial_body<8>(a, a.chunk0 + blockIdx.x, blockIdx.y, blockIdx.z); }
 __global__ __launch_bounds__(256) void finalize_kernel(PassBArgs a) { finalize_body(a, blockIdx.x); }
+// Partial sums and estimator together: one workgroup per (chunk, channel),
+// one wavefront per input group.
+template <int V, int D>
+__global__ __launch_bounds__(64 * MAX_FIN_GROUPS) void partial_finish_kernel(PassBArgs a) {
+  partial_body<V, D, true>(a, a.chunk0 + blockIdx.x, blockIdx.y, 0);
+}
 __global__ __launch_bounds__(256) void hist_copy_kernel(PassBArgs a) { hist_copy_body(a, blockIdx.x, blockIdx.y, blockIdx.z); }
 
 template <int V>
@@ -65,6 +71,23 @@ static int launch_v(const PassBArgs& a0, int32_t c_begin, int32_t c_end, int32_t
       hist_copy_kernel<<<dim3(n_old, F, (a.n_inputs + 255) / 256), dim3(256), 0, s>>>(a);
       SK_HIP_TRY(hipGetLastError());
     }
+  }
+  // A whole call whose channels fit one workgroup of at most 4 wavefronts:
+  // partial sums and estimator in one launch, no per-group partials in
+  // memory. Wider channels keep the separate finalize launch: their 8-wave
+  // workgroups, tied by the barriers, retire later than independent 4-wave
+  // ones, which costs what the launch saves (CHIME M = 256: 40.6 us against
+  // 34.8 + 4.6).
+  const bool whole = c_begin == 0 && c_end == a.n_chunks && b_begin == 0 && b_end == a.n_blocks;
+  if (whole && nc > 0 && a.n_groups <= MAX_FIN_GROUPS) {
+    const dim3 grid(nc, F), wg(64 * a.n_groups);
+    if (V == 8) partial_finish_kernel<8, 4><<<grid, wg, 0, s>>>(a);
+    else if (V == 4 && a.depth == 8) partial_finish_kernel<4, 8><<<grid, wg, 0, s>>>(a);
+    else if (V == 4 && a.depth == 2) partial_finish_kernel<4, 2><<<grid, wg, 0, s>>>(a);
+    else if (V == 4) partial_finish_kernel<4, 4><<<grid, wg, 0, s>>>(a);
+    else partial_finish_kernel<1, 4><<<grid, wg, 0, s>>>(a);
+    SK_HIP_TRY(hipGetLastError());
+    return SK_OK;
   }
   if (nc > 0) {
     if (V == 8) partial_kernel_8<<<dim3(nc, F, (a.n_groups + 3) / 4), dim3(256), 0, s>>>(a);

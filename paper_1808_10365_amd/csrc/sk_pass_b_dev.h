@@ -203,9 +203,79 @@ __device__ __forceinline__ double recip_pos(double p) {
 
 // RI: integer type of the per-wavefront R1/R2 sums: int32_t when a
 // wavefront's sums provably fit (64 V M 2^14 < 2^31), else int64_t.
-template <int V, typename RI, int U>
+// Estimator and flags from the combined sums (Eq. avgSK, final; Sec. 3.2).
+// Contraction is off so the rounding steps are the plain ones.
+__device__ __forceinline__ void finish(const PassBArgs& a, int f, int b, double A, double Bq, int64_t R1, int64_t R2,
+                       int32_t n) {
+#pragma clang fp contract(off)
+  const int64_t K = (int64_t)n * a.block_len;
+  const double Kd = (double)K, Md = (double)a.block_len;
+  bool invalid = K < 2;
+  double V = 0.0;
+  if (a.window == 0) {
+    invalid = invalid || R1 == 0;
+    if (!invalid) {
+      // Eq. (2) over all K samples, numerator K R2 - R1^2 formed exactly.
+      const __int128 num = (__int128)K * (__int128)R2 - (__int128)R1 * (__int128)R1;
+      const __int128 den = (__int128)R1 * (__int128)R1;
+      const double nd = (double)(int64_t)(num >> 64) * 18446744073709551616.0 + (double)(uint64_t)num;
+      const double dd = (double)(int64_t)(den >> 64) * 18446744073709551616.0 + (double)(uint64_t)den;
+      V = (Kd + 1.0) / (Kd - 1.0) * (nd / dd);
+    }
+  } else {
+    invalid = invalid || A == 0.0;
+    if (!invalid) {
+      if (a.estimator == SK_EST_TILDE)
+        V = (Md + 1.0) / (Md - 1.0) * (Md * Bq / (double)n - 1.0);
+      else
+        V = (Kd + 1.0) / (Kd - 1.0) * (Kd * Bq / (A * A) - 1.0);
+    }
+  }
+  uint8_t fl;
+  double sig = __builtin_nan("");
+  if (invalid) {
+    V = __builtin_nan("");
+    fl = SK_FLAG_INVALID;
+  } else {
+    double e0 = 1.0;
+    if (a.estimator == SK_EST_HAT && a.window == 1) e0 = ((Kd + 1.0) * (Md - 1.0)) / ((Kd - 1.0) * (Md + 1.0));
+    const double E = e0 + a.expect_offset;
+    const double s = a.sigma_override > 0.0 ? a.sigma_override : sqrt(4.0 / Kd);
+    double lo = E - a.k_sigma * s, hi = E + a.k_sigma * s;
+    if (a.thresholds) {
+      lo = a.thresholds[2 * n];
+      hi = a.thresholds[2 * n + 1];
+    }
+    fl = (V < lo ? SK_FLAG_LOW : 0) | (V > hi ? SK_FLAG_HIGH : 0);
+    sig = (V - E) / s;
+  }
+  const int64_t o = (int64_t)f * a.n_blocks + b;
+  if (a.significance) a.significance[o] = (float)sig;
+  if (a.r1) a.r1[o] = R1;
+  if (a.r2) a.r2[o] = R2;
+  if (a.v) a.v[o] = (float)V;
+  if (a.flags) a.flags[o] = fl;
+  if (a.n_eff) a.n_eff[o] = n;
+}
+
+// FIN: the workgroup holds every input group of the channel (one wavefront
+// per group, z = 0, at most MAX_FIN_GROUPS) and finishes its blocks itself.
+// The wavefront sums of up to FIN_SLOTS blocks wait in LDS; then, after one
+// barrier, they are added in group order (the order finalize_body uses, so
+// every output is the same bit for bit) and the blocks are finished.
+constexpr int MAX_FIN_GROUPS = 4;
+constexpr int FIN_SLOTS = 32;
+
+template <int V, typename RI, int U, bool FIN = false>
 __device__ __forceinline__ void partial_body_t(const PassBArgs& a, int c, int f, int z) {
   // U: blocks whose rows are loaded together.
+  static_assert(!FIN || U <= FIN_SLOTS, "a batch must fit the slots");
+  __shared__ double fin_a[FIN ? FIN_SLOTS : 1][FIN ? MAX_FIN_GROUPS : 1];
+  __shared__ double fin_q[FIN ? FIN_SLOTS : 1][FIN ? MAX_FIN_GROUPS : 1];
+  __shared__ int64_t fin_r1[FIN ? FIN_SLOTS : 1][FIN ? MAX_FIN_GROUPS : 1];
+  __shared__ int64_t fin_r2[FIN ? FIN_SLOTS : 1][FIN ? MAX_FIN_GROUPS : 1];
+  __shared__ int32_t fin_n[FIN ? FIN_SLOTS : 1][FIN ? MAX_FIN_GROUPS : 1];
+  int pend = 0;                                                // blocks waiting in LDS
   const int lane = threadIdx.x & 63;
   const int g = z * 4 + (threadIdx.x >> 6);                   // input group of 64*V
   const int N = a.n_inputs, L = a.window, H = a.hist_len;
@@ -289,7 +359,15 @@ __device__ __forceinline__ void partial_body_t(const PassBArgs& a, int c, int f,
       r1 = wave_sum_to_last(r1);
       r2 = wave_sum_to_last(r2);
       n = wave_sum_to_last(n);
-      if (lane == 63) {
+      if constexpr (FIN) {
+        if (lane == 63) {
+          fin_a[pend + u][g] = pa;
+          fin_q[pend + u][g] = pq;
+          fin_r1[pend + u][g] = (int64_t)r1;
+          fin_r2[pend + u][g] = (int64_t)r2;
+          fin_n[pend + u][g] = n;
+        }
+      } else if (lane == 63) {
         const int64_t o = ((int64_t)f * a.n_groups + g) * a.n_blocks + (e - H);
         a.part_a[o] = pa;
         a.part_q[o] = pq;
@@ -298,72 +376,45 @@ __device__ __forceinline__ void partial_body_t(const PassBArgs& a, int c, int f,
         a.part_n[o] = n;
       }
     }
+    if constexpr (FIN) {
+      const int nb = e1 - eb < U ? (int)(e1 - eb) : U;
+      pend += nb;
+      if (eb + U >= e1 || pend + U > FIN_SLOTS) {
+        // Slot j holds block e = eb + nb - pend + j. It is finished by lane
+        // j / W of wavefront j % W (W wavefronts), spreading the work; the
+        // second barrier keeps the slots until every finisher is done.
+        __syncthreads();
+        const int nw = (int)(blockDim.x >> 6);
+        const int j = (threadIdx.x & 63) * nw + (threadIdx.x >> 6);
+        if (j < pend) {
+          double A = 0.0, Bq = 0.0;
+          int64_t R1 = 0, R2 = 0;
+          int32_t nn = 0;
+          for (int gg = 0; gg < a.n_groups; ++gg) {
+            A += fin_a[j][gg];
+            Bq += fin_q[j][gg];
+            R1 += fin_r1[j][gg];
+            R2 += fin_r2[j][gg];
+            nn += fin_n[j][gg];
+          }
+          finish(a, f, (int)(eb + nb - pend + j - H), A, Bq, R1, R2, nn);
+        }
+        __syncthreads();
+        pend = 0;
+      }
+    }
   }
 }
 
-template <int V, int U = 4>
+template <int V, int U = 4, bool FIN = false>
 __device__ __forceinline__ void partial_body(const PassBArgs& a, int c, int f, int z) {
   // S2 of one input is at most M * 128^2 = M * 2^14 (Eq. singlesums).
   if ((int64_t)64 * V * a.block_len * 16384 < ((int64_t)1 << 31))
-    partial_body_t<V, int32_t, U>(a, c, f, z);
+    partial_body_t<V, int32_t, U, FIN>(a, c, f, z);
   else
-    partial_body_t<V, int64_t, U>(a, c, f, z);
+    partial_body_t<V, int64_t, U, FIN>(a, c, f, z);
 }
 
-// Estimator and flags from the combined sums (Eq. avgSK, final; Sec. 3.2).
-// Contraction is off so the rounding steps are the plain ones.
-__device__ __forceinline__ void finish(const PassBArgs& a, int f, int b, double A, double Bq, int64_t R1, int64_t R2,
-                       int32_t n) {
-#pragma clang fp contract(off)
-  const int64_t K = (int64_t)n * a.block_len;
-  const double Kd = (double)K, Md = (double)a.block_len;
-  bool invalid = K < 2;
-  double V = 0.0;
-  if (a.window == 0) {
-    invalid = invalid || R1 == 0;
-    if (!invalid) {
-      // Eq. (2) over all K samples, numerator K R2 - R1^2 formed exactly.
-      const __int128 num = (__int128)K * (__int128)R2 - (__int128)R1 * (__int128)R1;
-      const __int128 den = (__int128)R1 * (__int128)R1;
-      const double nd = (double)(int64_t)(num >> 64) * 18446744073709551616.0 + (double)(uint64_t)num;
-      const double dd = (double)(int64_t)(den >> 64) * 18446744073709551616.0 + (double)(uint64_t)den;
-      V = (Kd + 1.0) / (Kd - 1.0) * (nd / dd);
-    }
-  } else {
-    invalid = invalid || A == 0.0;
-    if (!invalid) {
-      if (a.estimator == SK_EST_TILDE)
-        V = (Md + 1.0) / (Md - 1.0) * (Md * Bq / (double)n - 1.0);
-      else
-        V = (Kd + 1.0) / (Kd - 1.0) * (Kd * Bq / (A * A) - 1.0);
-    }
-  }
-  uint8_t fl;
-  double sig = __builtin_nan("");
-  if (invalid) {
-    V = __builtin_nan("");
-    fl = SK_FLAG_INVALID;
-  } else {
-    double e0 = 1.0;
-    if (a.estimator == SK_EST_HAT && a.window == 1) e0 = ((Kd + 1.0) * (Md - 1.0)) / ((Kd - 1.0) * (Md + 1.0));
-    const double E = e0 + a.expect_offset;
-    const double s = a.sigma_override > 0.0 ? a.sigma_override : sqrt(4.0 / Kd);
-    double lo = E - a.k_sigma * s, hi = E + a.k_sigma * s;
-    if (a.thresholds) {
-      lo = a.thresholds[2 * n];
-      hi = a.thresholds[2 * n + 1];
-    }
-    fl = (V < lo ? SK_FLAG_LOW : 0) | (V > hi ? SK_FLAG_HIGH : 0);
-    sig = (V - E) / s;
-  }
-  const int64_t o = (int64_t)f * a.n_blocks + b;
-  if (a.significance) a.significance[o] = (float)sig;
-  if (a.r1) a.r1[o] = R1;
-  if (a.r2) a.r2[o] = R2;
-  if (a.v) a.v[o] = (float)V;
-  if (a.flags) a.flags[o] = fl;
-  if (a.n_eff) a.n_eff[o] = n;
-}
 
 __device__ __forceinline__ void finalize_body(const PassBArgs& a, int64_t blk) {
   const int64_t j = blk * 256 + threadIdx.x;
