@@ -54,6 +54,7 @@ struct sk_plan_s {
   int32_t* hist_suf = nullptr;  //   [hist_cap][F*N] history suffix sums
   int fused_mode = 0;      // 1: single launch wherever the shape allows
   int last_fused = 0;      // whether the last call ran the single-launch path
+  int fused_max_wg = 0;    // co-resident workgroups of the single-launch kernel
   int32_t cur;             // index of the live history buffer
   size_t bytes;
   int pass_a_lpr;          // 0 = heuristic
@@ -302,6 +303,13 @@ int sk_plan_set_pass_b_depth(sk_plan_t p, int32_t depth) {
 int sk_plan_set_fused(sk_plan_t p, int32_t mode) {
   clear_error();
   if (!p || mode < 0 || mode > 1) { set_error("mode must be 0 or 1"); return SK_ERR_INVALID_ARG; }
+  if (mode == 1) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != p->device) {
+      set_error("plan was created on device %d, current device is %d", p->device, dev);
+      return SK_ERR_INVALID_ARG;
+    }
+  }
   p->fused_mode = mode;
   const int64_t F = p->d.n_channels, N = p->d.n_inputs;
   // Scratch of the single-launch path, allocated the first time it is
@@ -329,6 +337,7 @@ int sk_plan_set_fused(sk_plan_t p, int32_t mode) {
     p->hist_suf = c;
     p->bytes += 2 * seg + suf;
   }
+  if (mode == 1 && p->fused_max_wg == 0) p->fused_max_wg = fused_max_workgroups();
   return SK_OK;
 }
 
@@ -521,7 +530,7 @@ int sk_compute(sk_plan_t p, const uint8_t* d_packed, const uint8_t* d_mask, cons
                fq >= 1 && fq <= 4;
   if (fused) {
     const int grid = (int)((B + fq - 1) / fq);
-    if (grid > fused_max_workgroups()) fused = false;
+    if (grid > p->fused_max_wg) fused = false;
   }
   p->last_fused = fused ? 1 : 0;
   if (fused) {
