@@ -184,8 +184,8 @@ void orc_flags(const double* V, const int32_t* n_eff, int64_t n, int64_t M, int6
 /* Array combine, estimator and flags for every (f, b).
  * Eq. normedSum1: A = sum_i S1_i / P_i;  Eq. normedSum2: Bq = sum_i S2_i / P_i^2
  * (both up to the common factors M*count and (M*count)^2, which cancel).
- * Eq. avgSK line 1: V = (K+1)/(K-1) * (K * Bq / A^2 - 1), K = N_eff * M.
- * Eq. final line 2 (L = 1 only): V = (M+1)/(M-1) * (M * Bq / N_eff - 1).
+ * Eq. avgSK, first form: V = (K+1)/(K-1) * (K * Bq / A^2 - 1), K = N_eff * M.
+ * Eq. final, second form (L = 1 only): V = (M+1)/(M-1) * (M * Bq / N_eff - 1).
  * L = 0: Eq. (2) over all K samples: V = (K+1)/(K-1) * (K R2 - R1^2) / R1^2,
  * with the numerator formed exactly in 128-bit integers.
  * R1, R2 are the raw integer sums over the included inputs. */
