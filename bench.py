@@ -233,10 +233,20 @@ def batched_same_workload(w, xd, args):
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / steps
         lpr = batch.tiles(0)[0]
+        pa_ms = batch.time_pass_a()
         batch.close()
     gbs = w.nbytes / (ms * 1e-3) / 1e9
+    pa_gbs = pass_a_bytes([w]) / (pa_ms * 1e-3) / 1e9
     return {"ms_per_call": round(ms, 4), "GBps": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+            "pass_a": {"ms": round(pa_ms, 4), "GBps": round(pa_gbs, 1), "frac": round(pa_gbs / HBM_PEAK_GBS, 4),
+                       "note": "persistent pass A kernel alone, best of 3; algorithmic bytes (input + S1/S2)"},
             "lanes_per_row": lpr, "note": "one-problem batch of this workload, one graph launch per call"}
+
+
+def pass_a_bytes(ws):
+    """Algorithmic bytes of pass A: every input byte read once, 8 bytes of
+    S1/S2 written per (channel, block, input)."""
+    return sum(w.nbytes + 8 * w.n_channels * (w.n_samples // w.block_len) * w.n_inputs for w in ws)
 
 
 def batched_bench(args, dev):
@@ -273,12 +283,16 @@ def batched_bench(args, dev):
         e1.record(stream)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / args.batched_steps
+        pa_ms = batch.time_pass_a()
         batch.close()
     del xs
     torch.cuda.empty_cache()
     gbs = total / (ms * 1e-3) / 1e9
+    pa_gbs = pass_a_bytes(ws) / (pa_ms * 1e-3) / 1e9
     return {"problems": len(ws), "input_bytes": total, "ms_per_call": round(ms, 4), "GBps": round(gbs, 1),
             "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+            "pass_a": {"ms": round(pa_ms, 4), "GBps": round(pa_gbs, 1), "frac": round(pa_gbs / HBM_PEAK_GBS, 4),
+                       "note": "persistent pass A kernel alone, best of 3; algorithmic bytes (input + S1/S2)"},
             "shapes": "N in {64,256,1024,2048}, M in {64,256,1024}, F in {1,4,8}, T = M * U{1..2^17/M}, "
                       "L = 2^16/M; one graph launch per call"}
 

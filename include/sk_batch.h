@@ -62,6 +62,15 @@ int sk_batch_get_tiles(sk_batch_t batch, int32_t j, int32_t* lanes_per_row, int3
  * Synchronises the device. */
 int sk_batch_get_state(sk_batch_t batch, int32_t j, int32_t* hist_len);
 
+/* Profiling: runs pass A of the whole batch alone (the persistent kernel,
+ * with the batch's tuned rows per load) 4 times on `stream`, the first as a
+ * warm-up, and returns the best time in milliseconds. Synchronises `stream`.
+ * It rewrites every problem's S1/S2 from the current inputs (the values a
+ * call would write) and leaves the normaliser state alone. It resets the
+ * work-queue counter with hipMemsetAsync, so it must not run under graph
+ * capture or overlap a call of the same batch. */
+int sk_batch_time_pass_a(sk_batch_t batch, void* stream, float* ms);
+
 int sk_batch_destroy(sk_batch_t batch);
 
 #ifdef __cplusplus

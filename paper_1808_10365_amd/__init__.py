@@ -106,6 +106,7 @@ def load_library():
     lib.sk_batch_compute.argtypes = [VP, VP, VP]
     lib.sk_batch_state_reset.argtypes = [VP, VP]
     lib.sk_batch_get_tiles.argtypes = [VP, I32, ctypes.POINTER(I32), ctypes.POINTER(I32)]
+    lib.sk_batch_time_pass_a.argtypes = [VP, VP, ctypes.POINTER(ctypes.c_float)]
     lib.sk_batch_destroy.argtypes = [VP]
     lib.sk_batch_get_state.argtypes = [VP, I32, ctypes.POINTER(I32)]
     lib.sk_read_probe.argtypes = [VP, I64, I32, VP, VP]
@@ -136,7 +137,7 @@ def load_library():
     for name in ("sk_server_create", "sk_server_add_array", "sk_stream_submit", "sk_stream_poll",
                  "sk_server_drain", "sk_server_get_stats", "sk_server_destroy"):
         getattr(lib, name).restype = ctypes.c_int
-    for name in ("sk_batch_create", "sk_batch_compute", "sk_batch_state_reset", "sk_batch_get_tiles", "sk_batch_destroy", "sk_batch_get_state"):
+    for name in ("sk_batch_create", "sk_batch_compute", "sk_batch_state_reset", "sk_batch_get_tiles", "sk_batch_destroy", "sk_batch_get_state", "sk_batch_time_pass_a"):
         getattr(lib, name).restype = ctypes.c_int
     for name in ("sk_plan_create", "sk_plan_destroy", "sk_plan_device_bytes", "sk_compute", "sk_flags",
                  "sk_state_reset", "sk_state_size", "sk_state_export", "sk_state_import",
@@ -429,6 +430,14 @@ class Batch:
         lpr, grid = ctypes.c_int32(), ctypes.c_int32()
         _check(self._lib.sk_batch_get_tiles(self.handle, j, ctypes.byref(lpr), ctypes.byref(grid)))
         return lpr.value, grid.value
+
+    def time_pass_a(self, stream=None) -> float:
+        """Best of three runs of batched pass A alone, in milliseconds (profiling)."""
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream()
+        ms = ctypes.c_float()
+        _check(self._lib.sk_batch_time_pass_a(self.handle, ctypes.c_void_p(s.cuda_stream), ctypes.byref(ms)))
+        return float(ms.value)
 
     def close(self):
         if getattr(self, "handle", None):

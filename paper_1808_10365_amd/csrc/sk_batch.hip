@@ -591,6 +591,21 @@ int sk_batch_get_tiles(sk_batch_t b, int32_t j, int32_t* lpr, int32_t* grid) {
   return SK_OK;
 }
 
+int sk_batch_time_pass_a(sk_batch_t b, void* stream, float* ms) {
+  clear_error();
+  if (!b || !ms) { set_error("bad arguments"); return SK_ERR_INVALID_ARG; }
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != b->device) {
+    set_error("batch was created on device %d, current device is %d", b->device, dev);
+    return SK_ERR_INVALID_ARG;
+  }
+  const float t = time_pass_a_batch(b, b->rows_a, (hipStream_t)stream);
+  SK_HIP_TRY(hipGetLastError());
+  if (!(t < 1e29f)) { set_error("pass A timing failed"); return SK_ERR_DEVICE; }
+  *ms = t;
+  return SK_OK;
+}
+
 int sk_batch_get_state(sk_batch_t b, int32_t j, int32_t* hist_len) {
   clear_error();
   if (!b || j < 0 || j >= b->n || !hist_len) { set_error("bad arguments"); return SK_ERR_INVALID_ARG; }

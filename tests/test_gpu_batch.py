@@ -127,3 +127,37 @@ def test_batch_rejects_unsupported():
     x = torch.zeros((64, 1, 20), dtype=torch.uint8, device=DEV)
     with pytest.raises(sk.SKError):
         sk.Batch([dict(n_inputs=20, n_channels=1, n_samples=64, block_len=16)], [x])
+
+
+def test_batch_time_pass_a_leaves_calls_intact(tmp_path):
+    # Timing pass A alone between two calls rewrites S1/S2 from the inputs
+    # only: the second call still continues the first call's history, and both
+    # calls match the oracle over the concatenated stream.
+    probs = _problems(13, 5)
+    xs = [synth.generate(w, nthreads=2) for w, _ in probs]
+    first = [torch.from_numpy(np.ascontiguousarray(x[:kw["n_samples"]])).to(DEV) for x, (_, kw) in zip(xs, probs)]
+    second = [torch.from_numpy(np.ascontiguousarray(x[kw["n_samples"]:])).to(DEV) for x, (_, kw) in zip(xs, probs)]
+    batch = sk.Batch([kw for _, kw in probs], first, autotune=False, use_graph=True,
+                     tune_cache=str(tmp_path / "tune.json"))
+    res = []
+    for call, inputs in enumerate((first, second)):
+        outs = batch.compute(inputs)
+        torch.cuda.synchronize()
+        res.append([{k: getattr(o, k).cpu().numpy().copy() for k in sk.ALL_OUTPUTS} for o in outs])
+        if call == 0:
+            ms = batch.time_pass_a()
+            print("batched pass A alone:", ms, "ms", flush=True)
+            assert 0.0 < ms < 1000.0
+            h = [batch.hist_len(j) for j in range(len(probs))]
+            expect = [min(max(kw["norm_window"] - 1, 0), kw["n_samples"] // kw["block_len"]) for _, kw in probs]
+            assert h == expect
+    for j, (w, kw) in enumerate(probs):
+        M, L, est = kw["block_len"], kw["norm_window"], kw["estimator"]
+        ref = oracle.sk(xs[j], M, L, est, 4.0, -0.05, 0.0)
+
+        class G:
+            pass
+        g = G()
+        for k in sk.ALL_OUTPUTS:
+            setattr(g, k, torch.from_numpy(np.concatenate([res[0][j][k], res[1][j][k]], axis=1)))
+        check_result(g, ref, M, L, est, 4.0, -0.05, 0.0, what=f"timed batch problem {j} {kw}")
