@@ -79,7 +79,7 @@ def workload(name):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("sk_pass_a.hip", "sk_internal.h"):
+    for f in ("sk_pass_a.hip", "sk_pass_a_dev.h", "sk_internal.h"):
         with open(os.path.join(ROOT, "paper_1808_10365_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
