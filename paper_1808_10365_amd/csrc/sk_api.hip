@@ -242,7 +242,8 @@ static PassAConfig plan_pass_a_config(const sk_plan_s* p, const uint8_t* d_packe
   t->blocks_per_task = 1;
   t->block_len = p->d.block_len;
   t->n_blocks = (int32_t)B;
-  PassAConfig c = default_pass_a_config(vec, t->row_bytes, B, p->pass_a_lpr == 0 && p->pass_a_variant < 0, p->n_cu);
+  PassAConfig c = default_pass_a_config(vec, t->row_bytes, B, p->d.block_len, p->pass_a_lpr == 0 && p->pass_a_variant < 0,
+                                        p->n_cu);
   if (p->pass_a_lpr) c.lpr = p->pass_a_lpr;
   if (p->pass_a_variant >= 0) c.variant = p->pass_a_variant;
   {

@@ -74,7 +74,8 @@ bool pass_a_deferred(int vec, int variant);
 int pass_a_deferred_blocks(int64_t n_blocks, int64_t col_groups, int n_cu);
 // lane_table: the lane-replicated table variants may be chosen (single-plan
 // kernel only; the batched kernel has its own table).
-PassAConfig default_pass_a_config(int vec, int64_t row_bytes, int64_t n_blocks, bool lane_table, int n_cu);
+PassAConfig default_pass_a_config(int vec, int64_t row_bytes, int64_t n_blocks, int block_len, bool lane_table,
+                                  int n_cu);
 
 // ---------------------------------------------------------------- pass B
 // Normaliser window, array combine, estimator and flags (Eq. discreteMean,

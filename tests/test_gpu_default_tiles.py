@@ -35,7 +35,9 @@ SHAPES = [
     (48, 5, 4, 4096, 16),        # 15 groups padded to 16 lanes, 16 blocks side by side
     (48, 5, 4, 2000, 16),        # the same rows with too few tasks: row phases of 16 lanes
     (16, 1, 256, 16, None),      # tiny: row phases
-    (256, 4, 256, 192, None),    # serving N=256 frame shape: row phases
+    (256, 4, 256, 192, 16),      # serving N=256 frame shape: 16 lanes, 16 row phases, 768 workgroups
+    (1024, 4, 8, 16, 32),        # 256 groups, 16 blocks: row phases stop at the block's 8 rows
+    (2048, 4, 4, 8, 64),         # 512 groups, 8 blocks of 4 rows: 64 lanes (4 phases)
 ]
 
 
