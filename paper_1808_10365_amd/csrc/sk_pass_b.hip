@@ -9,7 +9,8 @@
 // 1/P_i (Eq. normedSum1, normedSum2).
 //
 // Kernels:
-//   chunk_sum_kernel   (L >= 2) sum of S1 over each chunk of R consecutive e.
+//   chunk_sum_kernel   (L > 16) sum of S1 over each chunk of R consecutive e;
+//                      shorter windows are summed from their rows.
 //   partial_kernel     one wavefront per (chunk, channel, 64*V inputs): the
 //                      window start of the chunk from chunk sums plus fewer
 //                      than R edge reads, then per block the sliding update
@@ -60,7 +61,7 @@ static int launch_v(const PassBArgs& a0, int32_t c_begin, int32_t c_end, int32_t
   a.fin_nb = b_end - b_begin;
   const int zc = (a.n_inputs + 256 * V - 1) / (256 * V);
   if (a.window >= 2) {
-    if (nc > 0) {
+    if (nc > 0 && a.window > SHORT_WINDOW) {
       if (V == 8) chunk_sum_kernel_8<<<dim3(nc, F, zc), dim3(256), 0, s>>>(a);
       else if (V == 4) chunk_sum_kernel_4<<<dim3(nc, F, zc), dim3(256), 0, s>>>(a);
       else chunk_sum_kernel_1<<<dim3(nc, F, zc), dim3(256), 0, s>>>(a);

@@ -102,6 +102,10 @@ __device__ __forceinline__ void add_rows(const PassBArgs& a, int f, int64_t from
   }
 }
 
+// Windows of at most SHORT_WINDOW blocks are summed from their rows (a
+// batch or two of loads); the chunk sums, and their launch, serve longer ones.
+constexpr int SHORT_WINDOW = 16;
+
 // Sum of S1 over sequence positions [lo, hi) for V inputs at i0: the chunk
 // sums of the chunks wholly inside, plus the rows at either edge.
 template <int V>
@@ -112,7 +116,7 @@ __device__ void window_sum(const PassBArgs& a, int f, int64_t lo, int64_t hi, in
   const int64_t R = a.chunk;
   const int64_t cs = (lo + R - 1) / R;   // first chunk fully inside
   const int64_t ce = hi / R;             // one past the last chunk fully inside
-  if (cs < ce) {
+  if (a.window > SHORT_WINDOW && cs < ce) {
 #pragma unroll 8
     for (int64_t c = cs; c < ce; ++c) {
       IVec<V> t;
