@@ -24,3 +24,13 @@ def test_split_oracle_equals_whole_run(L, n_tasks):
     for (f, b0, b1, h), (v, fl) in zip(tasks, parts):
         np.testing.assert_array_equal(v, whole.V[f, b0:b1])
         np.testing.assert_array_equal(fl, whole.flags[f, b0:b1])
+
+
+def test_pass_a_algorithmic_bytes():
+    # Input bytes plus 8 bytes of S1/S2 per (channel, block, input): the CHIME
+    # M = 256 call is 2 GiB + 64 MiB, the figure the roofline divides by.
+    import synth
+    w = synth.chime(seed=3, block_len=256)
+    assert bench.pass_a_bytes([w]) == (1 << 31) + (1 << 26)
+    small = synth.Workload("pab", 48, 3, 64 * 5, 64, 1, np.full(48, 2.0), [])
+    assert bench.pass_a_bytes([w, small]) == (1 << 31) + (1 << 26) + 48 * 3 * 320 + 8 * 3 * 5 * 48
