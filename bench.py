@@ -54,6 +54,8 @@ def parse():
                     help="offered loads as fractions of the measured saturated frame rate")
     ap.add_argument("--no-ceiling", action="store_true", help="skip the read-only stream ceiling")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched (32 problems) measurement")
+    ap.add_argument("--no-next-rows", action="store_true",
+                    help="skip the SK_i / false-alarm / diagnostic / Monte-Carlo measurements")
     ap.add_argument("--batched-steps", type=int, default=10)
     ap.add_argument("--cpu-threads", type=int, default=0,
                     help="threads for the split oracle run (0: the CPUs this process may use, at most 16)")
@@ -247,6 +249,66 @@ def pass_a_bytes(ws):
     """Algorithmic bytes of pass A: every input byte read once, 8 bytes of
     S1/S2 written per (channel, block, input)."""
     return sum(w.nbytes + 8 * w.n_channels * (w.n_samples // w.block_len) * w.n_inputs for w in ws)
+
+
+def next_rows_bench(w, xd, L, delta, sig, dev, steps):
+    """The rows beyond the core path on this workload, timed with HIP events
+    on the current stream: the call with per-input SK_i and significance
+    exported, the call with false-alarm thresholds, the per-channel
+    diagnostic on a call's V, and the Monte-Carlo threshold calibration."""
+    import torch
+    import paper_1808_10365_amd as sk
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, n):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(n):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n
+
+    F, B, N = w.n_channels, w.n_samples // w.block_len, w.n_inputs
+    plan = sk.Plan(N, F, w.n_samples, w.block_len, norm_window=L, k_sigma=5.0, expect_offset=delta,
+                   sigma_override=sig)
+    base_out = plan.alloc_outputs(dev)
+    base = timed(lambda: plan.compute_into(xd, base_out), steps)
+    ext_out = plan.alloc_outputs(dev, tuple(sk.DEFAULT_OUTPUTS) + ("sk_i", "significance"))
+    ext = timed(lambda: plan.compute_into(xd, ext_out), steps)
+    plan.set_false_alarm(1e-6)
+    fap = timed(lambda: plan.compute_into(xd, base_out), steps)
+    plan.set_false_alarm(0.0)
+    base2 = timed(lambda: plan.compute_into(xd, base_out), steps)
+    diag = timed(lambda: sk.channel_stats(base_out.v, w.block_len), 50)
+    plan.close()
+    n_mc, m_mc, sims = 16, 256, 1 << 18
+    sk.calibrate_mc(n_mc, m_mc, 2.5, 1024, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sk.calibrate_mc(n_mc, m_mc, 2.5, sims, 7)
+    torch.cuda.synchronize()
+    mc_s = time.perf_counter() - t0
+    extra = 4 * F * B * N + 4 * F * B
+    return {
+        "plain_call": {"ms_per_call": [round(base, 4), round(base2, 4)],
+                       "note": "the plain call without per-phase events, before and after the two below"},
+        "sk_i_and_significance": {"ms_per_call": round(ext, 4),
+                                  "extra_output_bytes": extra,
+                                  "GBps": round(w.nbytes / (ext * 1e-3) / 1e9, 1)},
+        "false_alarm_thresholds": {"ms_per_call": round(fap, 4), "fap": 1e-6,
+                                   "GBps": round(w.nbytes / (fap * 1e-3) / 1e9, 1)},
+        "channel_stats": {"us_per_call": round(diag * 1e3, 2), "values": F * B},
+        "monte_carlo": {"simulated_estimates": sims, "n_inputs": n_mc, "block_len": m_mc,
+                        "seconds": round(mc_s, 4),
+                        "samples_per_s": round(sims * n_mc * m_mc / mc_s, 1),
+                        "note": "wall time of one synchronous call, counter-based generator on the GPU"},
+        "note": "per-call times on this workload with HIP events; same plan settings as the main run",
+    }
 
 
 def batched_bench(args, dev):
@@ -536,6 +598,9 @@ def main():
     if not args.no_batched and x.nbytes % 16 == 0 and w.n_inputs % 16 == 0:
         print("# batched form on this workload", file=sys.stderr, flush=True)
         res["batched_same_workload"] = batched_same_workload(w, xd[0], args)
+    if not args.no_next_rows:
+        print("# SK_i, false-alarm thresholds, diagnostic, Monte-Carlo", file=sys.stderr, flush=True)
+        res["next_rows"] = next_rows_bench(w, xd[0], L, delta, sig, dev, max(10, args.steps // 2))
     del xd
     torch.cuda.empty_cache()
     if not args.no_serving:
