@@ -4,7 +4,8 @@
 Each case draws N (multiples of 16 and 4 and neither), F, M, the blocks per
 call, the window L, the estimator, a mask or none, quantised-Gaussian or
 uniform random bytes, and 1..3 consecutive calls on one plan (stream mode).
-The cases are fixed by their seeds, so a failure names a reproducible shape."""
+A second test draws every tuning control at random on the same shapes. The
+cases are fixed by their seeds, so a failure names a reproducible shape."""
 from types import SimpleNamespace
 
 import numpy as np
@@ -69,3 +70,52 @@ def test_random_shape(case):
     got = SimpleNamespace(**{name: torch.cat([getattr(o, name) for o in outs], dim=1) for name in sk.ALL_OUTPUTS})
     ref = oracle.sk(x, M, L, est, 5.0, 0.0, 0.0, mask)
     check_result(got, ref, M, L, est, 5.0, 0.0, 0.0, what=f"random case {case} {c}")
+
+
+def draw_knobs(case):
+    r = np.random.default_rng(77000 + case)
+    return dict(seg=int(r.choice([0, 1, 2, 3, 4])), chunk=int(r.choice([0, 1, 2, 4, 8, 16, 32, 64])),
+                vec=int(r.choice([0, 1, 4, 8])), depth=int(r.choice([0, 2, 4, 8])),
+                variant=int(r.integers(-1, 18)), lpr=int(r.choice([0, 1, 4, 16, 64, 256, 512, 1024])),
+                grid=int(r.choice([0, 0, 64, 300])), ablocks=int(r.choice([0, 0, 2, 4])))
+
+
+@pytest.mark.parametrize("case", range(40))
+def test_random_shape_and_tuning(case):
+    # The same seeded shapes with every tuning control drawn at random:
+    # block segments, pass B chunk / lane width / load depth, pass A variant,
+    # lanes per row, persistent grid and blocks per task.
+    c, kn = draw(case), draw_knobs(case)
+    N, F, M, B, L, est, calls = c["N"], c["F"], c["M"], c["B"], c["L"], c["est"], c["calls"]
+    T = M * B
+    print(f"case {case}: {c} {kn}", flush=True)
+    rng = np.random.default_rng(c["seed"])
+    if c["uniform"]:
+        x = rng.integers(0, 256, size=(calls * T, F, N), dtype=np.uint8)
+    else:
+        w = synth.Workload(f"knob{case}", N, F, calls * T, M, c["seed"], rng.uniform(1.5, 3.5, N), [])
+        x = synth.generate(w, nthreads=4)
+    mask = (rng.random((F, N)) > 0.1).astype(np.uint8) if c["use_mask"] else None
+    plan = sk.Plan(N, F, T, M, norm_window=L, estimator=est, k_sigma=5.0)
+    if kn["seg"]:
+        plan.set_segments(kn["seg"])
+    if kn["chunk"] or kn["vec"]:
+        plan.set_pass_b_tile(kn["chunk"], kn["vec"])
+    if kn["depth"]:
+        plan.set_pass_b_depth(kn["depth"])
+    if kn["lpr"]:
+        plan.set_pass_a_tile(kn["lpr"])
+    if kn["variant"] >= 0 or kn["grid"]:
+        plan.set_pass_a_variant(kn["variant"], kn["grid"])
+    if kn["ablocks"]:
+        plan.set_pass_a_blocks(kn["ablocks"])
+    md = None if mask is None else torch.from_numpy(mask).to(DEV)
+    outs = []
+    for k in range(calls):
+        xd = torch.from_numpy(np.ascontiguousarray(x[k * T:(k + 1) * T])).to(DEV)
+        outs.append(plan.compute(xd, mask=md, want=sk.ALL_OUTPUTS))
+    torch.cuda.synchronize()
+    plan.close()
+    got = SimpleNamespace(**{name: torch.cat([getattr(o, name) for o in outs], dim=1) for name in sk.ALL_OUTPUTS})
+    ref = oracle.sk(x, M, L, est, 5.0, 0.0, 0.0, mask)
+    check_result(got, ref, M, L, est, 5.0, 0.0, 0.0, what=f"random case {case} with tuning {kn}")
