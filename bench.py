@@ -54,6 +54,8 @@ def parse():
                     help="offered loads as fractions of the measured saturated frame rate")
     ap.add_argument("--no-ceiling", action="store_true", help="skip the read-only stream ceiling")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched (32 problems) measurement")
+    ap.add_argument("--profile-stride", type=int, default=4,
+                    help="record pass A / pass B events on every n-th timed call (1: every call)")
     ap.add_argument("--no-next-rows", action="store_true",
                     help="skip the SK_i / false-alarm / diagnostic / Monte-Carlo measurements")
     ap.add_argument("--batched-steps", type=int, default=10)
@@ -494,8 +496,14 @@ def main():
 
     lib = sk.load_library()
     import ctypes
-    rc = lib.sk_profile_enable(plan.handle, ctypes.c_int32(args.steps))
+    # Per-phase events (pass A / pass B durations) on every stride-th call of
+    # the timed loop: each recorded call carries a few microseconds of event
+    # overhead between its kernels.
+    stride = max(1, args.profile_stride)
+    n_rec = (args.steps + stride - 1) // stride
+    rc = lib.sk_profile_enable(plan.handle, ctypes.c_int32(n_rec))
     assert rc == 0
+    assert lib.sk_profile_set_stride(plan.handle, ctypes.c_int32(stride)) == 0
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -505,10 +513,10 @@ def main():
     ev1.record(stream)
     torch.cuda.synchronize()
     total_ms = ev0.elapsed_time(ev1)
-    ms_a = (ctypes.c_float * args.steps)()
-    ms_b = (ctypes.c_float * args.steps)()
+    ms_a = (ctypes.c_float * n_rec)()
+    ms_b = (ctypes.c_float * n_rec)()
     n = ctypes.c_int32()
-    assert lib.sk_profile_read(plan.handle, ms_a, ms_b, args.steps, ctypes.byref(n)) == 0
+    assert lib.sk_profile_read(plan.handle, ms_a, ms_b, n_rec, ctypes.byref(n)) == 0
     ms_a = np.array(ms_a[:n.value], dtype=np.float64)
     ms_b = np.array(ms_b[:n.value], dtype=np.float64)
     lib.sk_profile_enable(plan.handle, 0)
@@ -574,9 +582,10 @@ def main():
         "samples_per_s": round(in_bytes / (ms_step * 1e-3), 1),
         "frame_latency_ms": {"p50": round(float(np.percentile(step_ms, 50)), 4),
                              "p99": round(float(np.percentile(step_ms, 99)), 4),
-                             "note": "device time of one sk_compute (pass A + pass B), HIP events"},
+                             "note": "device time of one sk_compute (pass A + pass B), HIP events on the recorded calls"},
         "pass_ms": {"pass_a_avg": round(float(ms_a.mean()), 4), "pass_b_avg": round(float(ms_b.mean()), 4),
                     "pass_a_launches": launches, "single_launch": fused,
+                    "recorded_calls": int(n.value), "record_stride": stride,
                     "note": ("single launch: pass A time is the whole cooperative kernel (pass A, window scans "
                              "and pass B); pass B time is what follows it" if fused else
                              "pass A: all of a call's pass A launches; pass B: what is left after them "

@@ -21,6 +21,12 @@ extern "C" {
  * on this plan (0 turns recording off and frees the events). Host-side only. */
 int sk_profile_enable(sk_plan_t plan, int32_t max_records);
 
+/* Record only every stride-th call from now on (1, the default after
+ * sk_profile_enable: every call). The events sit between dependent kernels
+ * and cost a few microseconds per recorded call; a stride samples the phase
+ * durations of a long run of calls while the others run unperturbed. */
+int sk_profile_set_stride(sk_plan_t plan, int32_t stride);
+
 /* Wait for the recorded calls and return their phase durations in
  * milliseconds (ms_pass_a[j], ms_pass_b[j], j < *n, n <= cap); then start a
  * new recording. */

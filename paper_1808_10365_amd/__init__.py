@@ -101,6 +101,7 @@ def load_library():
     lib.sk_plan_set_pass_b_tile.argtypes = [VP, I32, I32]
     lib.sk_plan_set_pass_b_tile.restype = ctypes.c_int
     lib.sk_profile_enable.argtypes = [VP, I32]
+    lib.sk_profile_set_stride.argtypes = [VP, I32]
     lib.sk_profile_read.argtypes = [VP, VP, VP, I32, ctypes.POINTER(I32)]
     lib.sk_batch_create.argtypes = [ctypes.POINTER(PlanDesc), I32, ctypes.POINTER(BatchOpts), VP, ctypes.POINTER(Outputs), ctypes.POINTER(VP)]
     lib.sk_batch_compute.argtypes = [VP, VP, VP]
@@ -142,7 +143,7 @@ def load_library():
     for name in ("sk_plan_create", "sk_plan_destroy", "sk_plan_device_bytes", "sk_compute", "sk_flags",
                  "sk_state_reset", "sk_state_size", "sk_state_export", "sk_state_import",
                  "sk_digitised_expectation", "sk_plan_set_pass_a_tile", "sk_plan_get_pass_a_tile",
-                 "sk_profile_enable", "sk_profile_read", "sk_plan_set_pass_a_variant", "sk_read_probe", "sk_plan_set_segments", "sk_plan_set_pass_b_depth", "sk_plan_set_pass_a_blocks", "sk_plan_set_fused", "sk_plan_get_last_fused",
+                 "sk_profile_enable", "sk_profile_set_stride", "sk_profile_read", "sk_plan_set_pass_a_variant", "sk_read_probe", "sk_plan_set_segments", "sk_plan_set_pass_b_depth", "sk_plan_set_pass_a_blocks", "sk_plan_set_fused", "sk_plan_get_last_fused",
                  "sk_plan_get_last_segments"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib

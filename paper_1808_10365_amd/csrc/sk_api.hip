@@ -72,6 +72,7 @@ struct sk_plan_s {
   double* thresholds;             // [N + 1][2] false-alarm thresholds by N_eff, or null
   double fap;
   int32_t prof_max, prof_n;
+  int32_t prof_stride = 1, prof_calls = 0;   // record every prof_stride-th call
 };
 
 static const uint32_t kStateMagic = 0x534B5354u;  // "SKST"
@@ -398,6 +399,16 @@ int sk_profile_enable(sk_plan_t p, int32_t max_records) {
   for (auto& e : p->prof) SK_HIP_TRY(hipEventCreate(&e));
   p->prof_max = max_records;
   p->prof_n = 0;
+  p->prof_stride = 1;
+  p->prof_calls = 0;
+  return SK_OK;
+}
+
+int sk_profile_set_stride(sk_plan_t p, int32_t stride) {
+  clear_error();
+  if (!p || stride < 1) { set_error("stride must be at least 1"); return SK_ERR_INVALID_ARG; }
+  p->prof_stride = stride;
+  p->prof_calls = 0;
   return SK_OK;
 }
 
@@ -519,7 +530,7 @@ int sk_compute(sk_plan_t p, const uint8_t* d_packed, const uint8_t* d_mask, cons
   }
 
   p->last_segments = K < 1 ? 1 : K;
-  const bool rec = p->prof_n < p->prof_max;
+  const bool rec = p->prof_n < p->prof_max && (p->prof_calls++ % p->prof_stride) == 0;
   if (rec) SK_HIP_TRY(hipEventRecord(p->prof[3 * p->prof_n], s));
   int rc = SK_OK;
 
