@@ -38,16 +38,11 @@ def parse():
     ap.add_argument("--cpu-sample-blocks", type=int, default=0,
                     help="blocks per channel in the oracle's timed sample (0: pick ~10-30 s of work)")
     ap.add_argument("--lpr", type=int, default=0, help="force pass A lanes per row")
-    ap.add_argument("--variant", type=int, default=-1, help="force pass A row batching variant (0..17; -1 = library choice)")
+    ap.add_argument("--variant", type=int, default=-1, help="force pass A variant (0..4; -1 = library choice)")
     ap.add_argument("--grid", type=int, default=0, help="force pass A workgroup count (persistent loop)")
     ap.add_argument("--ablocks", type=int, default=0, help="consecutive blocks per pass A task (packed variants)")
-    ap.add_argument("--fused", type=int, default=0,
-                    help="single-launch path: 0 never (default), 1 whenever the shape allows")
-    ap.add_argument("--segments", type=int, default=0,
-                    help="block segments per call (0 = library choice, 1 = pass B after pass A)")
-    ap.add_argument("--chunk", type=int, default=0, help="force pass B chunk length (blocks)")
-    ap.add_argument("--bvec", type=int, default=0, help="force pass B inputs per lane (1, 4 or 8)")
-    ap.add_argument("--bdepth", type=int, default=0, help="force pass B blocks loaded together (2, 4, 8)")
+    ap.add_argument("--chunk", type=int, default=0, help="force pass B blocks per combine workgroup (1, 2, 4)")
+    ap.add_argument("--bvec", type=int, default=0, help="force pass B inputs per lane (1 or 4)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
     ap.add_argument("--serving-frames", type=int, default=10000)
     ap.add_argument("--serving-loads", default="0.3,0.6,0.9",
@@ -474,14 +469,8 @@ def main():
         plan.set_pass_a_variant(args.variant, args.grid)
     if args.chunk or args.bvec:
         plan.set_pass_b_tile(args.chunk, args.bvec)
-    if args.fused:
-        plan.set_fused(args.fused)
-    if args.segments:
-        plan.set_segments(args.segments)
     if args.ablocks:
         plan.set_pass_a_blocks(args.ablocks)
-    if args.bdepth:
-        plan.set_pass_b_depth(args.bdepth)
     # Inputs resident in HBM. Inputs smaller than the 256 MB last-level cache
     # rotate over enough copies that repeats cannot be served from it.
     nbuf = max(1, int(np.ceil(1.0e9 / x.nbytes))) if x.nbytes < 1 << 30 else 1
@@ -544,13 +533,8 @@ def main():
     fbn = w.n_channels * B * w.n_inputs
     # Pass A algorithmic bytes per launch: every input byte once, 8 B of
     # per-input sums (S1, S2 int32) per (channel, block, input).
-    # A call runs pass A as `launches` kernels over consecutive block ranges
-    # of (near) equal size; per launch: the call's bytes and pass A time over
-    # the launch count.
-    launches = max(1, plan.last_segments())
-    fused = plan.last_fused()
-    pass_a_bytes = (in_bytes + 8 * fbn) / launches
-    a_avg = float(ms_a.mean()) / launches
+    pass_a_bytes = in_bytes + 8 * fbn
+    a_avg = float(ms_a.mean())
     achieved = pass_a_bytes / (a_avg * 1e-3) / 1e9
     traffic = traffic_from_profile(args.workload, pass_a_bytes)
     step_ms = ms_a + ms_b
@@ -584,20 +568,18 @@ def main():
                              "p99": round(float(np.percentile(step_ms, 99)), 4),
                              "note": "device time of one sk_compute (pass A + pass B), HIP events on the recorded calls"},
         "pass_ms": {"pass_a_avg": round(float(ms_a.mean()), 4), "pass_b_avg": round(float(ms_b.mean()), 4),
-                    "pass_a_launches": launches, "single_launch": fused,
                     "recorded_calls": int(n.value), "record_stride": stride,
-                    "note": ("single launch: pass A time is the whole cooperative kernel (pass A, window scans "
-                             "and pass B); pass B time is what follows it" if fused else
-                             "pass A: all of a call's pass A launches; pass B: what is left after them "
-                             "(pass B of earlier segments overlaps pass A on a second stream)")},
+                    "note": "pass A: the per-input sums kernel; pass B: the scan and combine kernels after it"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
-                     "kernel": ("fused_kernel (pass A, window scans and pass B in one cooperative launch)"
-                                if fused else "pass_a kernel (per-input block sums)"),
-                     "algorithmic_bytes_per_launch": round(pass_a_bytes), "launches_per_step": launches},
+                     "kernel": "pass_a kernel (per-input block sums)",
+                     "algorithmic_bytes_per_launch": round(pass_a_bytes), "launches_per_step": 1},
         "flagged_fraction": round(flagged, 5),
     }
+    # Every handle is closed before main returns, so no device memory is
+    # released from a finaliser at interpreter exit.
+    plan.close()
     if not args.no_ceiling and x.nbytes % 16 == 0:
         print("# read-only stream ceiling", file=sys.stderr, flush=True)
         c = read_ceiling(xd[0], dev)

@@ -65,9 +65,12 @@ int sk_server_add_array(sk_server_t server, const sk_plan_desc* desc, int32_t* a
  * memory, valid until the ticket completes; 1: host memory (pinned for an
  * asynchronous copy), copied into a staging buffer the server allocates
  * within its budget. outs: device buffers for this frame's results.
+ * ready_stream (a hipStream_t, or NULL): work enqueued on it before this call
+ * (writing the frame, or still using the output buffers) completes before
+ * the frame's work starts; NULL means the frame and outputs are ready now.
  * SK_ERR_AGAIN when the queue is full. */
 int sk_stream_submit(sk_server_t server, int32_t array_id, const uint8_t* frame, int32_t frame_on_host,
-                     const sk_outputs* outs, uint64_t tag, sk_ticket_t* ticket);
+                     const sk_outputs* outs, uint64_t tag, void* ready_stream, sk_ticket_t* ticket);
 
 /* SK_OK and *result once the ticket completed (the ticket is then
  * released); SK_ERR_AGAIN before that; SK_ERR_INVALID_ARG for unknown tickets. */

@@ -13,6 +13,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import sys
 from dataclasses import dataclass
 from typing import Dict, Optional, Sequence
 
@@ -111,16 +112,12 @@ def load_library():
     lib.sk_batch_destroy.argtypes = [VP]
     lib.sk_batch_get_state.argtypes = [VP, I32, ctypes.POINTER(I32)]
     lib.sk_read_probe.argtypes = [VP, I64, I32, VP, VP]
-    lib.sk_plan_set_segments.argtypes = [VP, I32]
-    lib.sk_plan_set_pass_b_depth.argtypes = [VP, I32]
     lib.sk_plan_set_pass_a_blocks.argtypes = [VP, I32]
-    lib.sk_plan_get_last_segments.argtypes = [VP, ctypes.POINTER(I32)]
-    lib.sk_plan_set_fused.argtypes = [VP, I32]
-    lib.sk_plan_get_last_fused.argtypes = [VP, ctypes.POINTER(I32)]
     lib.sk_server_now.restype = ctypes.c_double
     lib.sk_server_create.argtypes = [ctypes.POINTER(ServerDesc), ctypes.POINTER(VP)]
     lib.sk_server_add_array.argtypes = [VP, ctypes.POINTER(PlanDesc), ctypes.POINTER(I32)]
-    lib.sk_stream_submit.argtypes = [VP, I32, VP, I32, ctypes.POINTER(Outputs), ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)]
+    lib.sk_stream_submit.argtypes = [VP, I32, VP, I32, ctypes.POINTER(Outputs), ctypes.c_uint64, VP,
+                                     ctypes.POINTER(ctypes.c_uint64)]
     lib.sk_stream_poll.argtypes = [VP, ctypes.c_uint64, ctypes.POINTER(ServerResult)]
     lib.sk_server_drain.argtypes = [VP]
     lib.sk_server_get_stats.argtypes = [VP, ctypes.POINTER(ServerStats)]
@@ -143,8 +140,8 @@ def load_library():
     for name in ("sk_plan_create", "sk_plan_destroy", "sk_plan_device_bytes", "sk_compute", "sk_flags",
                  "sk_state_reset", "sk_state_size", "sk_state_export", "sk_state_import",
                  "sk_digitised_expectation", "sk_plan_set_pass_a_tile", "sk_plan_get_pass_a_tile",
-                 "sk_profile_enable", "sk_profile_set_stride", "sk_profile_read", "sk_plan_set_pass_a_variant", "sk_read_probe", "sk_plan_set_segments", "sk_plan_set_pass_b_depth", "sk_plan_set_pass_a_blocks", "sk_plan_set_fused", "sk_plan_get_last_fused",
-                 "sk_plan_get_last_segments"):
+                 "sk_profile_enable", "sk_profile_set_stride", "sk_profile_read", "sk_plan_set_pass_a_variant", "sk_read_probe",
+                 "sk_plan_set_pass_a_blocks"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -163,6 +160,38 @@ def _ptr(t: Optional[torch.Tensor]):
 def _stream_handle(stream: Optional[torch.cuda.Stream]):
     s = stream if stream is not None else torch.cuda.current_stream()
     return ctypes.c_void_p(s.cuda_stream)
+
+
+def _device_tensor(t, name: str, dtype, shape, device_index: int):
+    """Raise ValueError unless t is a contiguous tensor on GPU `device_index`
+    with this dtype and exact shape: the library receives raw pointers and
+    trusts their extent."""
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name} must be a torch tensor")
+    if not t.is_cuda or t.device.index != device_index:
+        raise ValueError(f"{name} must live on cuda:{device_index}, got {t.device}")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def _output_specs(F: int, B: int, N: int):
+    return {"s1": ((F, B, N), torch.int32), "s2": ((F, B, N), torch.int32), "r1": ((F, B), torch.int64),
+            "r2": ((F, B), torch.int64), "v": ((F, B), torch.float32), "flags": ((F, B), torch.uint8),
+            "n_eff": ((F, B), torch.int32), "sk_i": ((F, B, N), torch.float32),
+            "significance": ((F, B), torch.float32)}
+
+
+def _check_outputs(out, F: int, B: int, N: int, device_index: int):
+    specs = _output_specs(F, B, N)
+    for k in ALL_OUTPUTS:
+        t = getattr(out, k)
+        if t is not None:
+            _device_tensor(t, f"output {k}", specs[k][1], specs[k][0], device_index)
 
 
 def digitised_expectation(sigma: Sequence[float], block_len: int, clip: int = 7):
@@ -198,14 +227,18 @@ def read_probe(x: torch.Tensor, workgroups: int, sink: torch.Tensor,
     """Launch the read-only stream probe over the bytes of ``x`` (16-byte
     aligned, size a multiple of 16) on ``stream``; ``sink`` is a device int32
     tensor of at least workgroups * 256 elements."""
-    assert x.is_contiguous() and sink.dtype == torch.int32 and sink.numel() >= workgroups * 256
+    if not (x.is_cuda and x.is_contiguous()) or not (sink.is_cuda and sink.is_contiguous()):
+        raise ValueError("x and sink must be contiguous device tensors")
+    if sink.dtype != torch.int32 or sink.numel() < workgroups * 256:
+        raise ValueError("sink must be int32 with at least workgroups * 256 elements")
     _check(load_library().sk_read_probe(_ptr(x), x.numel() * x.element_size(), int(workgroups), _ptr(sink),
                                         _stream_handle(stream)))
 
 
 def channel_stats(v: torch.Tensor, block_len: int, stream: Optional[torch.cuda.Stream] = None):
     """App. A diagnostic per channel of v [F][B]: (mean, var, n_eff, count) device tensors."""
-    assert v.dtype == torch.float32 and v.dim() == 2
+    if not isinstance(v, torch.Tensor) or not v.is_cuda or v.dtype != torch.float32 or v.dim() != 2:
+        raise ValueError("v must be a float32 device tensor [F][B]")
     v = v.contiguous()
     F, B = v.shape
     mean = torch.empty(F, dtype=torch.float64, device=v.device)
@@ -243,6 +276,7 @@ class Plan:
         self._lib = load_library()
         self.desc = PlanDesc(n_inputs, n_channels, n_samples, block_len, norm_window, estimator,
                              k_sigma, expect_offset, sigma_override)
+        self.device_index = torch.cuda.current_device()
         h = ctypes.c_void_p()
         _check(self._lib.sk_plan_create(ctypes.byref(self.desc), ctypes.byref(h)))
         self.handle = h
@@ -257,6 +291,10 @@ class Plan:
             self.handle = None
 
     def __del__(self):
+        # At interpreter shutdown the HIP runtime may already be gone: leave
+        # the memory to the process exit instead of calling into it.
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -271,6 +309,8 @@ class Plan:
         _check(self._lib.sk_plan_set_pass_a_tile(self.handle, int(lanes_per_row)))
 
     def set_pass_b_tile(self, chunk: int = 0, inputs_per_lane: int = 0):
+        """Pass B blocks per combine workgroup (1, 2, 4; 0: library choice) and
+        inputs per lane (1, 4; 0: library choice)."""
         _check(self._lib.sk_plan_set_pass_b_tile(self.handle, int(chunk), int(inputs_per_lane)))
 
     def set_false_alarm(self, fap: float):
@@ -282,38 +322,14 @@ class Plan:
         _check(self._lib.sk_plan_get_thresholds(self.handle, int(n_eff), ctypes.byref(lo), ctypes.byref(hi)))
         return lo.value, hi.value
 
-    def set_segments(self, segments: int):
-        """Block segments per call (0: library choice, 1: none); pass B of each
-        segment overlaps pass A of the next on a plan-owned stream."""
-        _check(self._lib.sk_plan_set_segments(self.handle, int(segments)))
-
     def set_pass_a_blocks(self, blocks: int):
         """Consecutive blocks per pass A task with the packed-table variants (0: library choice)."""
         _check(self._lib.sk_plan_set_pass_a_blocks(self.handle, int(blocks)))
 
-    def set_pass_b_depth(self, depth: int):
-        """Blocks a pass B partial wavefront loads together (0: library choice, 2, 4, 8)."""
-        _check(self._lib.sk_plan_set_pass_b_depth(self.handle, int(depth)))
-
-    def set_fused(self, mode: int):
-        """Single-launch path: 0 never (default), 1 whenever the shape allows."""
-        _check(self._lib.sk_plan_set_fused(self.handle, int(mode)))
-
-    def last_fused(self) -> bool:
-        """Whether the last call ran the single-launch path."""
-        k = ctypes.c_int32()
-        _check(self._lib.sk_plan_get_last_fused(self.handle, ctypes.byref(k)))
-        return bool(k.value)
-
-    def last_segments(self) -> int:
-        """Segments (pass A launches) of the last call."""
-        k = ctypes.c_int32()
-        _check(self._lib.sk_plan_get_last_segments(self.handle, ctypes.byref(k)))
-        return k.value
-
     def set_pass_a_variant(self, variant: int, grid: int = 0):
-        """Row batching variant of pass A (-1: library choice, 0..17) and workgroup
-        count (0: one per task)."""
+        """Pass A variant (-1: library choice; 0 shared table, 1/2 packed lane
+        table with 8/16 rows per load, 3 blocks side by side, 4 deferred stores)
+        and workgroup count (0: one per task)."""
         _check(self._lib.sk_plan_set_pass_a_variant(self.handle, int(variant), int(grid)))
 
     def alloc_outputs(self, device, want: Sequence[str] = DEFAULT_OUTPUTS) -> Result:
@@ -334,10 +350,11 @@ class Plan:
     def compute_into(self, packed: torch.Tensor, out: Result, mask: Optional[torch.Tensor] = None,
                      stream: Optional[torch.cuda.Stream] = None) -> Result:
         T, F, N = self.desc.n_samples, self.desc.n_channels, self.desc.n_inputs
-        if packed.dtype != torch.uint8 or tuple(packed.shape) != (T, F, N) or not packed.is_contiguous() or not packed.is_cuda:
-            raise ValueError(f"packed must be a contiguous CUDA uint8 tensor of shape {(T, F, N)}")
-        if mask is not None and (mask.dtype != torch.uint8 or tuple(mask.shape) != (F, N) or not mask.is_contiguous()):
-            raise ValueError(f"mask must be a contiguous uint8 tensor of shape {(F, N)}")
+        dev = self.device_index
+        _device_tensor(packed, "packed", torch.uint8, (T, F, N), dev)
+        if mask is not None:
+            _device_tensor(mask, "mask", torch.uint8, (F, N), dev)
+        _check_outputs(out, F, self.n_blocks, N, dev)
         o = Outputs(*[_ptr(getattr(out, k)) for k in ALL_OUTPUTS])
         _check(self._lib.sk_compute(self.handle, _ptr(packed), _ptr(mask), ctypes.byref(o), _stream_handle(stream)))
         return out
@@ -348,9 +365,10 @@ class Plan:
         return self.compute_into(packed, out, mask, stream)
 
     def flags(self, v: torch.Tensor, n_eff: torch.Tensor, stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
-        assert v.dtype == torch.float32 and n_eff.dtype == torch.int32 and v.shape == n_eff.shape
         v = v.contiguous()
         n_eff = n_eff.contiguous()
+        _device_tensor(v, "v", torch.float32, tuple(v.shape), self.device_index)
+        _device_tensor(n_eff, "n_eff", torch.int32, tuple(v.shape), self.device_index)
         out = torch.empty(v.shape, dtype=torch.uint8, device=v.device)
         _check(self._lib.sk_flags(self.handle, _ptr(v), _ptr(n_eff), _ptr(out), v.numel(), _stream_handle(stream)))
         return out
@@ -380,6 +398,9 @@ class Batch:
                  tune_cache: Optional[str] = None):
         self._lib = load_library()
         n = len(plans)
+        if n < 1 or len(inputs) != n:
+            raise ValueError("one input tensor per problem, at least one problem")
+        self.device_index = torch.cuda.current_device()
         self.descs = (PlanDesc * n)()
         self.outputs = []
         outs = (Outputs * n)()
@@ -389,8 +410,7 @@ class Batch:
                          kw.get("expect_offset", 0.0), kw.get("sigma_override", 0.0))
             self.descs[j] = d
             T, F, N, M = d.n_samples, d.n_channels, d.n_inputs, d.block_len
-            if x.dtype != torch.uint8 or tuple(x.shape) != (T, F, N) or not x.is_contiguous():
-                raise ValueError(f"input {j} must be a contiguous uint8 tensor of shape {(T, F, N)}")
+            _device_tensor(x, f"input {j}", torch.uint8, (T, F, N), self.device_index)
             B = T // M
             r = Result(torch.empty((F, B, N), dtype=torch.int32, device=x.device),
                        torch.empty((F, B, N), dtype=torch.int32, device=x.device),
@@ -414,6 +434,12 @@ class Batch:
     def compute(self, inputs=None, stream: Optional[torch.cuda.Stream] = None):
         ptrs = None
         if inputs is not None:
+            if len(inputs) != self.n:
+                raise ValueError(f"expected {self.n} inputs, got {len(inputs)}")
+            for j, x in enumerate(inputs):
+                d = self.descs[j]
+                _device_tensor(x, f"input {j}", torch.uint8, (d.n_samples, d.n_channels, d.n_inputs),
+                               self.device_index)
             self._inputs = list(inputs)
             ptrs = (ctypes.c_void_p * self.n)(*[x.data_ptr() for x in inputs])
         _check(self._lib.sk_batch_compute(self.handle, ptrs, _stream_handle(stream)))
@@ -446,6 +472,8 @@ class Batch:
             self.handle = None
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -457,6 +485,7 @@ class Server:
 
     def __init__(self, hbm_budget_bytes: int, max_inflight: int = 8, n_streams: int = 4, queue_capacity: int = 1024):
         self._lib = load_library()
+        self.device_index = torch.cuda.current_device()
         d = ServerDesc(int(hbm_budget_bytes), int(max_inflight), int(n_streams), int(queue_capacity))
         h = ctypes.c_void_p()
         _check(self._lib.sk_server_create(ctypes.byref(d), ctypes.byref(h)))
@@ -483,12 +512,28 @@ class Server:
         return Result(**{k: (torch.empty(shapes[k][0], dtype=shapes[k][1], device=device) if k in want else None)
                          for k in ALL_OUTPUTS})
 
-    def submit(self, array_id: int, frame: torch.Tensor, out: Result, tag: int = 0) -> Optional[int]:
-        """Returns the ticket, or None when the queue is full."""
+    def submit(self, array_id: int, frame: torch.Tensor, out: Result, tag: int = 0,
+               stream: Optional[torch.cuda.Stream] = None) -> Optional[int]:
+        """Returns the ticket, or None when the queue is full. The frame's work
+        waits for what is already enqueued on ``stream`` (default: the current
+        stream), so frames and output buffers written there need no sync."""
+        if not 0 <= array_id < len(self.arrays):
+            raise ValueError(f"unknown array {array_id}")
+        d = self.arrays[array_id]
+        T, F, N = d.n_samples, d.n_channels, d.n_inputs
+        if frame.is_cuda:
+            _device_tensor(frame, "frame", torch.uint8, (T, F, N), self.device_index)
+        else:
+            if frame.dtype != torch.uint8 or tuple(frame.shape) != (T, F, N) or not frame.is_contiguous():
+                raise ValueError(f"host frame must be a contiguous uint8 tensor of shape {(T, F, N)}")
+            if not frame.is_pinned():
+                raise ValueError("host frames must be in pinned memory (asynchronous copy)")
+        _check_outputs(out, F, d.n_samples // d.block_len, N, self.device_index)
         o = Outputs(*[_ptr(getattr(out, k)) for k in ALL_OUTPUTS])
         t = ctypes.c_uint64()
         rc = self._lib.sk_stream_submit(self.handle, array_id, ctypes.c_void_p(frame.data_ptr()),
-                                        0 if frame.is_cuda else 1, ctypes.byref(o), tag, ctypes.byref(t))
+                                        0 if frame.is_cuda else 1, ctypes.byref(o), tag,
+                                        _stream_handle(stream), ctypes.byref(t))
         if rc == SK_ERR_AGAIN:
             return None
         _check(rc)
@@ -522,6 +567,8 @@ class Server:
             self._keep.clear()
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:

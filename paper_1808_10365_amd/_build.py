@@ -9,7 +9,7 @@ ROOT = os.path.dirname(_HERE)
 CSRC = os.path.join(_HERE, "csrc")
 LIB = os.path.join(_HERE, "libsk.so")
 
-SOURCES = ["sk_pass_a.hip", "sk_pass_b.hip", "sk_api.hip", "sk_batch.hip", "sk_server.hip", "sk_diag.hip", "sk_mc.hip", "sk_probe.hip", "sk_fused.hip", "sk_calib.cpp", "sk_fap.cpp"]
+SOURCES = ["sk_pass_a.hip", "sk_pass_b.hip", "sk_api.hip", "sk_batch.hip", "sk_server.hip", "sk_diag.hip", "sk_mc.hip", "sk_probe.hip", "sk_calib.cpp", "sk_fap.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -37,37 +37,21 @@ struct sk_plan_s {
   int64_t n_blocks;        // B = T / M
   int32_t hist_cap;        // max(L - 1, 0)
   int32_t hist_len;        // history blocks currently held (<= hist_cap)
-  int32_t chunk;           // R
-  int32_t n_chunks_max;    // chunks of the sequence when the history is full
+  int32_t chunk;           // R of pass B
   int32_t s1_s2_owned;
-  int32_t* s1;             // [F][B][N] scratch
+  int32_t* s1;             // [F][B][N] scratch (when the caller does not take the sums)
   int32_t* s2;
-  int32_t* chunk_sum;      // [F][n_chunks_max][N]
-  double* part_a;          // [F][n_groups_max][B] per-group partial sums of pass B
-  double* part_q;
-  int64_t* part_r1;
-  int64_t* part_r2;
-  int32_t* part_n;
-  int32_t* hist[2];        // [F][hist_cap][N], ping-pong
-  int32_t* seg_sum = nullptr;   // single-launch path: [n_cu][F*N] segment sums
-  int32_t* seg_pre = nullptr;   //   [n_cu][F*N] exclusive prefixes over segments
-  int32_t* hist_suf = nullptr;  //   [hist_cap][F*N] history suffix sums
-  int fused_mode = 0;      // 1: single launch wherever the shape allows
-  int last_fused = 0;      // whether the last call ran the single-launch path
-  int fused_max_wg = 0;    // co-resident workgroups of the single-launch kernel
+  uint32_t* pc;            // [F][ceil(B / R) + 1][N] prefix sums of pass B
+  size_t pc_bytes;
+  int32_t* hs[2];          // [F][hist_cap][N] history suffix sums, ping-pong
   int32_t cur;             // index of the live history buffer
   size_t bytes;
   int pass_a_lpr;          // 0 = heuristic
-  int pass_a_variant = -1; // row batching variant of pass A; -1 = heuristic
+  int pass_a_variant = -1; // pass A variant; -1 = heuristic
   int pass_a_grid;         // 0 = one workgroup per task
-  int pass_b_vec;          // 0 = library choice, else 1 or 4 inputs per lane
-  int segments = 0;        // block segments per call (0 = library choice, 1 = none)
-  int pass_b_depth = 0;    // blocks a partial wavefront loads together (0 = library choice)
   int pass_a_blocks = 0;   // consecutive blocks per pass A task (packed variants; 0 = library choice)
+  int pass_b_vec;          // 0 = library choice, else 1 or 4 inputs per lane
   int n_cu = 256;          // compute units of the plan's device
-  int last_segments = 0;   // segments the last call used
-  hipStream_t side = nullptr;          // pass B of segmented calls
-  std::vector<hipEvent_t> seg_ev;      // pass A segment k done (on the caller's stream); last: join
   std::vector<hipEvent_t> prof;   // 3 events per recorded call
   double* thresholds;             // [N + 1][2] false-alarm thresholds by N_eff, or null
   double fap;
@@ -100,12 +84,6 @@ int validate_desc(const sk_plan_desc* d) {
 }
 }  // namespace sk
 
-static int32_t pow2_floor(int64_t v) {
-  int32_t r = 1;
-  while ((int64_t)r * 2 <= v && r < (1 << 30)) r *= 2;
-  return r;
-}
-
 static void free_profile(sk_plan_s* p) {
   for (hipEvent_t e : p->prof) (void)hipEventDestroy(e);
   p->prof.clear();
@@ -114,26 +92,14 @@ static void free_profile(sk_plan_s* p) {
 
 static void free_plan_memory(sk_plan_s* p) {
   free_profile(p);
-  for (hipEvent_t e : p->seg_ev) (void)hipEventDestroy(e);
-  p->seg_ev.clear();
-  if (p->side) (void)hipStreamDestroy(p->side);
-  p->side = nullptr;
   if (p->thresholds) (void)hipFree(p->thresholds);
   if (p->s1_s2_owned) {
     if (p->s1) (void)hipFree(p->s1);
     if (p->s2) (void)hipFree(p->s2);
   }
-  if (p->chunk_sum) (void)hipFree(p->chunk_sum);
-  if (p->part_a) (void)hipFree(p->part_a);
-  if (p->part_q) (void)hipFree(p->part_q);
-  if (p->part_r1) (void)hipFree(p->part_r1);
-  if (p->part_r2) (void)hipFree(p->part_r2);
-  if (p->part_n) (void)hipFree(p->part_n);
-  if (p->hist[0]) (void)hipFree(p->hist[0]);
-  if (p->hist[1]) (void)hipFree(p->hist[1]);
-  if (p->seg_sum) (void)hipFree(p->seg_sum);
-  if (p->seg_pre) (void)hipFree(p->seg_pre);
-  if (p->hist_suf) (void)hipFree(p->hist_suf);
+  if (p->pc) (void)hipFree(p->pc);
+  if (p->hs[0]) (void)hipFree(p->hs[0]);
+  if (p->hs[1]) (void)hipFree(p->hs[1]);
 }
 
 #define SK_ALLOC(ptr, nbytes)                                                     \
@@ -175,36 +141,16 @@ int sk_plan_create(const sk_plan_desc* desc, sk_plan_t* out) {
   const int L = desc->norm_window_blocks;
   p->hist_cap = L >= 2 ? L - 1 : 0;
   p->hist_len = 0;
-  // Chunk length R: a wavefront of the partial kernel reads about L/R chunk
-  // sums to start its window and 3R rows in its main loop, so R near
-  // sqrt(L) keeps the start-up cost small; R shrinks while there are too few
-  // wavefronts to fill the device.
-  const int64_t seq = p->hist_cap + p->n_blocks;
-  const int64_t groups = (N + 63) / 64;   // upper bound (1 input per lane)
-  int32_t R = 1, R_min = 1;
-  if (L >= 2) {
-    while (R < 64 && (int64_t)R * R * 2 < L) R *= 2;          // L/R <= 2R
-    while (R_min < R && (int64_t)R_min * R_min * 8 < L) R_min *= 2;   // L/R <= 8R
-  } else {
-    R = 16;
-  }
-  while (R > R_min && ((seq + R - 1) / R) * F * ((N + 255) / 256) < 2048) R /= 2;
-  p->chunk = R;
-  p->n_chunks_max = (int32_t)((seq + R - 1) / R);
+  p->chunk = pass_b_chunk((int32_t)N, (int32_t)F, p->n_blocks, L);
   p->s1_s2_owned = 1;
   const size_t fbn = (size_t)F * p->n_blocks * N;
   SK_ALLOC(p->s1, fbn * sizeof(int32_t));
   SK_ALLOC(p->s2, fbn * sizeof(int32_t));
-  const size_t fgb = (size_t)F * groups * p->n_blocks;
-  SK_ALLOC(p->part_a, fgb * sizeof(double));
-  SK_ALLOC(p->part_q, fgb * sizeof(double));
-  SK_ALLOC(p->part_r1, fgb * sizeof(int64_t));
-  SK_ALLOC(p->part_r2, fgb * sizeof(int64_t));
-  SK_ALLOC(p->part_n, fgb * sizeof(int32_t));
   if (L >= 2) {
-    SK_ALLOC(p->chunk_sum, (size_t)F * p->n_chunks_max * N * sizeof(int32_t));
-    SK_ALLOC(p->hist[0], (size_t)F * p->hist_cap * N * sizeof(int32_t));
-    SK_ALLOC(p->hist[1], (size_t)F * p->hist_cap * N * sizeof(int32_t));
+    p->pc_bytes = pass_b_prefix_bytes((int32_t)N, (int32_t)F, p->n_blocks, p->chunk);
+    SK_ALLOC(p->pc, p->pc_bytes);
+    SK_ALLOC(p->hs[0], (size_t)F * p->hist_cap * N * sizeof(int32_t));
+    SK_ALLOC(p->hs[1], (size_t)F * p->hist_cap * N * sizeof(int32_t));
   }
   p->cur = 0;
   *out = p;
@@ -253,9 +199,8 @@ static PassAConfig plan_pass_a_config(const sk_plan_s* p, const uint8_t* d_packe
     if (c.lpr < lo) c.lpr = lo;
     if (c.lpr > hi) c.lpr = hi;
   }
-  const int gpl = pass_a_groups_per_lane(vec, c.variant);
   t->col_groups = (int32_t)(t->row_bytes / vec);
-  t->chunks = (t->col_groups + c.lpr * gpl - 1) / (c.lpr * gpl);
+  t->chunks = (t->col_groups + c.lpr - 1) / c.lpr;
   if (pass_a_packed(vec, c.variant) && p->pass_a_blocks > 1) t->blocks_per_task = p->pass_a_blocks;
   if (pass_a_deferred(vec, c.variant)) {
     c.lpr = 512;
@@ -275,16 +220,9 @@ static PassAConfig plan_pass_a_config(const sk_plan_s* p, const uint8_t* d_packe
 }
 
 int sk_plan_set_pass_a_variant(sk_plan_t p, int32_t variant, int32_t grid) {
-  if (!p || variant < -1 || variant > 17 || grid < 0) { set_error("bad variant"); return SK_ERR_INVALID_ARG; }
+  if (!p || variant < -1 || variant > 4 || grid < 0) { set_error("pass A variant must be -1..4 and grid >= 0"); return SK_ERR_INVALID_ARG; }
   p->pass_a_variant = variant;
   p->pass_a_grid = grid;
-  return SK_OK;
-}
-
-int sk_plan_set_segments(sk_plan_t p, int32_t segments) {
-  clear_error();
-  if (!p || segments < 0 || segments > 64) { set_error("segments must be in 0..64"); return SK_ERR_INVALID_ARG; }
-  p->segments = segments;
   return SK_OK;
 }
 
@@ -295,87 +233,27 @@ int sk_plan_set_pass_a_blocks(sk_plan_t p, int32_t blocks) {
   return SK_OK;
 }
 
-int sk_plan_set_pass_b_depth(sk_plan_t p, int32_t depth) {
-  clear_error();
-  if (!p || (depth != 0 && depth != 2 && depth != 4 && depth != 8)) { set_error("depth must be 0, 2, 4 or 8"); return SK_ERR_INVALID_ARG; }
-  p->pass_b_depth = depth;
-  return SK_OK;
-}
-
-int sk_plan_set_fused(sk_plan_t p, int32_t mode) {
-  clear_error();
-  if (!p || mode < 0 || mode > 1) { set_error("mode must be 0 or 1"); return SK_ERR_INVALID_ARG; }
-  if (mode == 1) {
-    int dev = -1;
-    if (hipGetDevice(&dev) != hipSuccess || dev != p->device) {
-      set_error("plan was created on device %d, current device is %d", p->device, dev);
-      return SK_ERR_INVALID_ARG;
-    }
-  }
-  p->fused_mode = mode;
-  const int64_t F = p->d.n_channels, N = p->d.n_inputs;
-  // Scratch of the single-launch path, allocated the first time it is
-  // switched on for a shape it serves: wide rows covered by one 512-lane
-  // workgroup, whole channels per wavefront, at most 4 blocks per workgroup
-  // in one round of the CUs, a window of at least 2 blocks.
-  if (mode == 1 && !p->seg_sum && p->d.norm_window_blocks >= 2 && N % 1024 == 0 && (F * N) / 16 <= 512 &&
-      p->n_blocks <= 4 * (int64_t)p->n_cu) {
-    const size_t seg = (size_t)p->n_cu * F * N * sizeof(int32_t);
-    const size_t suf = (size_t)p->hist_cap * F * N * sizeof(int32_t);
-    int32_t *a = nullptr, *b = nullptr, *c = nullptr;
-    hipError_t e = hipMalloc((void**)&a, seg);
-    if (e == hipSuccess) e = hipMalloc((void**)&b, seg);
-    if (e == hipSuccess) e = hipMalloc((void**)&c, suf);
-    if (e != hipSuccess) {
-      if (a) (void)hipFree(a);
-      if (b) (void)hipFree(b);
-      if (c) (void)hipFree(c);
-      p->fused_mode = 0;
-      set_error("hipMalloc for the single-launch path failed: %s", hipGetErrorString(e));
-      return SK_ERR_NOMEM;
-    }
-    p->seg_sum = a;
-    p->seg_pre = b;
-    p->hist_suf = c;
-    p->bytes += 2 * seg + suf;
-  }
-  if (mode == 1 && p->fused_max_wg == 0) p->fused_max_wg = fused_max_workgroups();
-  return SK_OK;
-}
-
-int sk_plan_get_last_fused(sk_plan_t p, int32_t* fused) {
-  clear_error();
-  if (!p || !fused) { set_error("NULL argument"); return SK_ERR_INVALID_ARG; }
-  *fused = p->last_fused;
-  return SK_OK;
-}
-
-int sk_plan_get_last_segments(sk_plan_t p, int32_t* segments) {
-  clear_error();
-  if (!p || !segments) { set_error("NULL argument"); return SK_ERR_INVALID_ARG; }
-  *segments = p->last_segments;
-  return SK_OK;
-}
-
 int sk_plan_set_pass_b_tile(sk_plan_t p, int32_t chunk, int32_t vec) {
   clear_error();
-  if (!p || chunk < 0 || chunk > 1024 || (chunk & (chunk - 1)) || (vec != 0 && vec != 1 && vec != 4 && vec != 8)) {
-    set_error("bad pass B tile");
+  if (!p || (chunk != 0 && chunk != 1 && chunk != 2 && chunk != 4) || (vec != 0 && vec != 1 && vec != 4)) {
+    set_error("pass B tile: chunk must be 0, 1, 2 or 4 and inputs per lane 0, 1 or 4");
     return SK_ERR_INVALID_ARG;
   }
-  if (chunk > 0 && chunk != p->chunk) {
-    const int64_t seq = p->hist_cap + p->n_blocks;
-    const int32_t n_max = (int32_t)((seq + chunk - 1) / chunk);
-    if (p->d.norm_window_blocks >= 2 && n_max > p->n_chunks_max) {
-      int32_t* cs = nullptr;
+  const int32_t R = chunk ? chunk
+                          : pass_b_chunk(p->d.n_inputs, p->d.n_channels, p->n_blocks, p->d.norm_window_blocks);
+  if (p->d.norm_window_blocks >= 2) {
+    const size_t need = pass_b_prefix_bytes(p->d.n_inputs, p->d.n_channels, p->n_blocks, R);
+    if (need > p->pc_bytes) {
+      uint32_t* pc = nullptr;
       SK_HIP_TRY(hipDeviceSynchronize());
-      SK_HIP_TRY(hipMalloc((void**)&cs, (size_t)p->d.n_channels * n_max * p->d.n_inputs * sizeof(int32_t)));
-      if (p->chunk_sum) (void)hipFree(p->chunk_sum);
-      p->chunk_sum = cs;
-      p->n_chunks_max = n_max;
+      SK_HIP_TRY(hipMalloc((void**)&pc, need));
+      if (p->pc) (void)hipFree(p->pc);
+      p->bytes += need - p->pc_bytes;
+      p->pc = pc;
+      p->pc_bytes = need;
     }
-    p->chunk = chunk;
   }
+  p->chunk = R;
   p->pass_b_vec = vec;
   return SK_OK;
 }
@@ -426,6 +304,68 @@ int sk_profile_read(sk_plan_t p, float* ms_a, float* ms_b, int32_t cap, int32_t*
   return SK_OK;
 }
 
+}  // extern "C"
+
+namespace sk {
+
+// Buffers of one call beyond the caller's input and outputs.
+struct CallBuffers {
+  int32_t* s1;           // [F][B][N] (the caller's output or scratch)
+  int32_t* s2;
+  uint32_t* pc;          // pass B prefix sums (L >= 2)
+  const int32_t* hs;     // history suffix sums of this call (L >= 2; hist_len slots valid)
+  int32_t* hs_next;      // the next call's
+  int32_t hist_len;
+};
+
+// Pass B arguments of one call.
+static PassBArgs make_pass_b_args(const sk_plan_desc& d, int64_t B, int32_t hist_cap, int32_t chunk, int32_t vec_pref,
+                                  const uint8_t* mask, const sk_outputs* outs, const CallBuffers& cb,
+                                  const double* thresholds) {
+  PassBArgs a;
+  memset(&a, 0, sizeof a);
+  const int64_t N = d.n_inputs;
+  a.s1 = cb.s1;
+  a.s2 = cb.s2;
+  a.cs = nullptr;
+  a.hs = cb.hs;
+  a.hs_next = cb.hs_next;
+  a.pc = cb.pc;
+  a.mask = mask;
+  a.r1 = outs->r1;
+  a.r2 = outs->r2;
+  a.v = outs->v;
+  a.flags = outs->flags;
+  a.n_eff = outs->n_eff;
+  a.sk_i = outs->sk_i;
+  a.significance = outs->significance;
+  a.thresholds = thresholds;
+  a.n_inputs = (int32_t)N;
+  a.n_channels = d.n_channels;
+  a.n_blocks = (int32_t)B;
+  a.block_len = d.block_len;
+  a.window = d.norm_window_blocks;
+  a.hist_len = cb.hist_len;
+  a.hist_cap = hist_cap;
+  const int64_t total = cb.hist_len + B;
+  a.hist_next_len = (int32_t)(total < hist_cap ? total : hist_cap);
+  a.chunk = chunk;
+  a.n_chunks = (int32_t)((B + chunk - 1) / chunk);
+  // Four inputs per lane need 16-byte aligned rows of the sums.
+  a.vec = pass_b_vec((int32_t)N);
+  if (((uintptr_t)cb.s1 | (uintptr_t)cb.s2 | (uintptr_t)outs->sk_i) % 16 != 0) a.vec = 1;
+  if (vec_pref == 1) a.vec = 1;
+  a.estimator = d.estimator;
+  a.k_sigma = d.k_sigma;
+  a.expect_offset = d.expect_offset;
+  a.sigma_override = d.sigma_override;
+  return a;
+}
+
+}  // namespace sk
+
+extern "C" {
+
 int sk_compute(sk_plan_t p, const uint8_t* d_packed, const uint8_t* d_mask, const sk_outputs* outs,
                void* stream) {
   clear_error();
@@ -435,180 +375,37 @@ int sk_compute(sk_plan_t p, const uint8_t* d_packed, const uint8_t* d_mask, cons
   SK_HIP_TRY(hipGetDevice(&dev));
   if (dev != p->device) { set_error("plan was created on device %d, current device is %d", p->device, dev); return SK_ERR_INVALID_ARG; }
   hipStream_t s = (hipStream_t)stream;
-  const sk_plan_desc& d = p->d;
-  const int64_t N = d.n_inputs, F = d.n_channels, B = p->n_blocks;
+  const int64_t B = p->n_blocks;
   if (B == 0) return SK_OK;
 
-  int32_t* s1 = outs->s1 ? outs->s1 : p->s1;
-  int32_t* s2 = outs->s2 ? outs->s2 : p->s2;
+  CallBuffers cb;
+  cb.s1 = outs->s1 ? outs->s1 : p->s1;
+  cb.s2 = outs->s2 ? outs->s2 : p->s2;
+  cb.pc = p->pc;
+  cb.hs = p->hs[p->cur];
+  cb.hs_next = p->hs[1 - p->cur];
+  cb.hist_len = p->hist_len;
 
   PassATask t;
   PassAConfig c = plan_pass_a_config(p, d_packed, &t);
   t.x = d_packed;
-  t.s1 = s1;
-  t.s2 = s2;
+  t.s1 = cb.s1;
+  t.s2 = cb.s2;
+  PassBArgs a = make_pass_b_args(p->d, B, p->hist_cap, p->chunk, p->pass_b_vec, d_mask, outs, cb, p->thresholds);
 
-  PassBArgs a;
-  memset(&a, 0, sizeof a);
-  a.s1 = s1;
-  a.s2 = s2;
-  a.hist = p->hist[p->cur];
-  a.hist_next = p->hist[1 - p->cur];
-  a.chunk_sum = p->chunk_sum;
-  a.part_a = p->part_a;
-  a.part_q = p->part_q;
-  a.part_r1 = p->part_r1;
-  a.part_r2 = p->part_r2;
-  a.part_n = p->part_n;
-  a.mask = d_mask;
-  a.r1 = outs->r1;
-  a.r2 = outs->r2;
-  a.v = outs->v;
-  a.flags = outs->flags;
-  a.n_eff = outs->n_eff;
-  a.sk_i = outs->sk_i;
-  a.significance = outs->significance;
-  a.thresholds = p->thresholds;
-  a.n_inputs = (int32_t)N;
-  a.n_channels = (int32_t)F;
-  a.n_blocks = (int32_t)B;
-  a.block_len = d.block_len;
-  a.window = d.norm_window_blocks;
-  a.hist_len = p->hist_len;
-  a.hist_cap = p->hist_cap;
-  {
-    const int64_t total = p->hist_len + B;
-    a.hist_next_len = (int32_t)(total < p->hist_cap ? total : p->hist_cap);
-  }
-  a.chunk = p->chunk;
-  a.n_chunks = (int32_t)((p->hist_len + B + p->chunk - 1) / p->chunk);
-  // Four inputs per lane need 16-byte aligned rows of the sums.
-  a.vec = pass_b_vec((int32_t)N);
-  if (((uintptr_t)s1 | (uintptr_t)s2 | (uintptr_t)outs->sk_i) % 16 != 0) a.vec = 1;
-  if (p->pass_b_vec == 1) a.vec = 1;
-  if (p->pass_b_vec == 8 && a.vec == 4 && N % 8 == 0 && ((uintptr_t)s1 | (uintptr_t)s2 | (uintptr_t)outs->sk_i) % 32 == 0)
-    a.vec = 8;
-  a.n_groups = (int32_t)((N + 64 * a.vec - 1) / (64 * a.vec));
-  a.depth = p->pass_b_depth ? p->pass_b_depth : 4;
-  a.estimator = d.estimator;
-  a.k_sigma = d.k_sigma;
-  a.expect_offset = d.expect_offset;
-  a.sigma_override = d.sigma_override;
-
-  // Segments: pass B of blocks [b_k, b_k+1) needs S1 of those blocks and of
-  // earlier ones only, so it can run on a second stream while pass A streams
-  // the next segment. Boundaries sit on chunk boundaries of the sequence
-  // (history + this call), so each segment's chunk sums read finished rows.
-  int K = p->segments;
-  // Library choice: one segment. Measured on MI355X (CHIME shapes), every
-  // extra pass A launch adds a drain of its last workgroups (each streams
-  // about 1 MiB, tens of microseconds) while pass B, latency-bound, takes
-  // nearly as long for a quarter of the blocks as for all of them.
-  if (K == 0) K = 1;
-  if (K > a.n_chunks) K = a.n_chunks;
-  if (K > 1 && !p->side) {
-    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    SK_HIP_TRY(hipStreamIsCapturing(s, &cs));
-    if (cs != hipStreamCaptureStatusNone) {
-      K = 1;   // no stream creation under capture; later calls segment
-    } else {
-      SK_HIP_TRY(hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking));
-    }
-  }
-  if (K > 1 && (int)p->seg_ev.size() < K + 1) {
-    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    SK_HIP_TRY(hipStreamIsCapturing(s, &cs));
-    if (cs != hipStreamCaptureStatusNone) {
-      K = 1;
-    } else {
-      while ((int)p->seg_ev.size() < K + 1) {
-        hipEvent_t e;
-        SK_HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-        p->seg_ev.push_back(e);
-      }
-    }
-  }
-
-  p->last_segments = K < 1 ? 1 : K;
   const bool rec = p->prof_n < p->prof_max && (p->prof_calls++ % p->prof_stride) == 0;
   if (rec) SK_HIP_TRY(hipEventRecord(p->prof[3 * p->prof_n], s));
-  int rc = SK_OK;
-
-  // Single launch when it is switched on and the shape allows it. Off by
-  // default: the two grid-wide barriers it needs cost more than the launches
-  // and the S1/S2 re-read that it saves.
-  const int fq = (int)((B + p->n_cu - 1) / p->n_cu);
-  bool fused = p->fused_mode != 0 && K <= 1 && p->seg_sum && c.vec == 16 && d.norm_window_blocks >= 2 &&
-               fq >= 1 && fq <= 4;
-  if (fused) {
-    const int grid = (int)((B + fq - 1) / fq);
-    if (grid > p->fused_max_wg) fused = false;
-  }
-  p->last_fused = fused ? 1 : 0;
-  if (fused) {
-    FusedArgs fa;
-    memset(&fa, 0, sizeof fa);
-    fa.a = t;
-    fa.a.s2 = outs->s2;           // S2 in memory only when requested
-    fa.b = a;
-    fa.b.chunk0 = 0;
-    fa.b.fin_b0 = 0;
-    fa.b.fin_nb = (int32_t)B;
-    fa.segsum = p->seg_sum;
-    fa.segpre = p->seg_pre;
-    fa.hsuf = p->hist_suf;
-    rc = launch_fused(fa, fq, s);
-    if (rc) return rc;
-    if (rec) SK_HIP_TRY(hipEventRecord(p->prof[3 * p->prof_n + 1], s));
-  } else if (K <= 1) {
-    rc = launch_pass_a(t, c, s);
-    if (rc) return rc;
-    if (rec) SK_HIP_TRY(hipEventRecord(p->prof[3 * p->prof_n + 1], s));
-    rc = launch_pass_b(a, s);
-    if (rc) return rc;
-  } else {
-    const int64_t H = p->hist_len, R = p->chunk;
-    int32_t c_prev = 0;
-    int32_t b_prev = 0;
-    for (int k = 0; k < K; ++k) {
-      int32_t c_next = a.n_chunks;
-      if (k + 1 < K) {
-        const int64_t target = H + (int64_t)B * (k + 1) / K;     // sequence position
-        int64_t cn = (target + R / 2) / R;
-        if (cn < c_prev) cn = c_prev;
-        if (cn > a.n_chunks) cn = a.n_chunks;
-        c_next = (int32_t)cn;
-      }
-      int64_t bn = (int64_t)c_next * R - H;
-      if (k + 1 == K || bn > B) bn = B;
-      if (bn < b_prev) bn = b_prev;
-      const int32_t b_next = (int32_t)bn;
-      if (b_next > b_prev) {
-        PassATask ts = t;
-        ts.block0 = b_prev;
-        ts.block_end = b_next;
-        ts.n_tasks = (int64_t)((b_next - b_prev + t.blocks_per_task - 1) / t.blocks_per_task) * t.chunks;
-        rc = launch_pass_a(ts, c, s);
-        if (rc) return rc;
-      }
-      SK_HIP_TRY(hipEventRecord(p->seg_ev[k], s));
-      SK_HIP_TRY(hipStreamWaitEvent(p->side, p->seg_ev[k], 0));
-      rc = launch_pass_b_range(a, c_prev, c_next, b_prev, b_next, k == 0, p->side);
-      if (rc) return rc;
-      c_prev = c_next;
-      b_prev = b_next;
-    }
-    if (rec) SK_HIP_TRY(hipEventRecord(p->prof[3 * p->prof_n + 1], s));
-    SK_HIP_TRY(hipEventRecord(p->seg_ev[K], p->side));
-    SK_HIP_TRY(hipStreamWaitEvent(s, p->seg_ev[K], 0));
-  }
+  int rc = launch_pass_a(t, c, s);
+  if (rc) return rc;
+  if (rec) SK_HIP_TRY(hipEventRecord(p->prof[3 * p->prof_n + 1], s));
+  rc = launch_pass_b(a, s);
+  if (rc) return rc;
   if (rec) {
     SK_HIP_TRY(hipEventRecord(p->prof[3 * p->prof_n + 2], s));
     p->prof_n += 1;
   }
   if (p->hist_cap > 0) {
-    const int64_t total = p->hist_len + B;
-    p->hist_len = (int32_t)(total < p->hist_cap ? total : p->hist_cap);
+    p->hist_len = a.hist_next_len;
     p->cur = 1 - p->cur;
   }
   return SK_OK;
@@ -706,14 +503,24 @@ int sk_state_export(sk_plan_t p, void* host_buf, size_t cap, void* stream) {
   if (!host_buf || cap < need) { set_error("buffer too small: need %zu", need); return SK_ERR_INVALID_ARG; }
   StateHeader h = {kStateMagic, 1, p->d.n_inputs, p->d.n_channels, p->d.block_len, p->d.norm_window_blocks, p->hist_len, 0};
   memcpy(host_buf, &h, sizeof h);
-  if (p->hist_len > 0) {
+  const int64_t H = p->hist_len, N = p->d.n_inputs, Hc = p->hist_cap;
+  if (H > 0) {
+    // The device keeps suffix sums HS over the history; the blob holds the
+    // blocks themselves (oldest first): block y = HS(y) - HS(y + 1).
     hipStream_t s = (hipStream_t)stream;
-    const size_t row = (size_t)p->hist_len * p->d.n_inputs * sizeof(int32_t);
+    std::vector<int32_t> hs((size_t)H * N);
+    int32_t* rows = (int32_t*)((char*)host_buf + sizeof h);
     for (int f = 0; f < p->d.n_channels; ++f) {
-      const int32_t* src = p->hist[p->cur] + (size_t)f * p->hist_cap * p->d.n_inputs;
-      SK_HIP_TRY(hipMemcpyAsync((char*)host_buf + sizeof h + f * row, src, row, hipMemcpyDeviceToHost, s));
+      const int32_t* src = p->hs[p->cur] + ((size_t)f * Hc + (Hc - H)) * N;
+      SK_HIP_TRY(hipMemcpyAsync(hs.data(), src, hs.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      SK_HIP_TRY(hipStreamSynchronize(s));
+      int32_t* dst = rows + (size_t)f * H * N;
+      for (int64_t y = 0; y < H; ++y)
+        for (int64_t i = 0; i < N; ++i) {
+          const uint32_t next = y + 1 < H ? (uint32_t)hs[(y + 1) * N + i] : 0u;
+          dst[y * N + i] = (int32_t)((uint32_t)hs[y * N + i] - next);
+        }
     }
-    SK_HIP_TRY(hipStreamSynchronize(s));
   }
   return SK_OK;
 }
@@ -728,15 +535,26 @@ int sk_state_import(sk_plan_t p, const void* host_buf, size_t size, void* stream
     set_error("state blob does not match this plan");
     return SK_ERR_STATE;
   }
-  const size_t row = (size_t)h.hist_len * p->d.n_inputs * sizeof(int32_t);
+  const int64_t H = h.hist_len, N = p->d.n_inputs, Hc = p->hist_cap;
+  const size_t row = (size_t)H * N * sizeof(int32_t);
   if (size < sizeof h + row * p->d.n_channels) { set_error("state blob truncated"); return SK_ERR_STATE; }
   hipStream_t s = (hipStream_t)stream;
-  if (h.hist_len > 0) {
+  if (H > 0) {
+    const int32_t* rows = (const int32_t*)((const char*)host_buf + sizeof h);
+    std::vector<int32_t> hs((size_t)H * N);
     for (int f = 0; f < p->d.n_channels; ++f) {
-      int32_t* dst = p->hist[p->cur] + (size_t)f * p->hist_cap * p->d.n_inputs;
-      SK_HIP_TRY(hipMemcpyAsync(dst, (const char*)host_buf + sizeof h + f * row, row, hipMemcpyHostToDevice, s));
+      const int32_t* src = rows + (size_t)f * H * N;
+      for (int64_t i = 0; i < N; ++i) {
+        uint32_t acc = 0;
+        for (int64_t y = H - 1; y >= 0; --y) {
+          acc += (uint32_t)src[y * N + i];
+          hs[y * N + i] = (int32_t)acc;
+        }
+      }
+      int32_t* dst = p->hs[p->cur] + ((size_t)f * Hc + (Hc - H)) * N;
+      SK_HIP_TRY(hipMemcpyAsync(dst, hs.data(), hs.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+      SK_HIP_TRY(hipStreamSynchronize(s));
     }
-    SK_HIP_TRY(hipStreamSynchronize(s));
   }
   p->hist_len = h.hist_len;
   return SK_OK;

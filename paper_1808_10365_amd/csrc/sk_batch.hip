@@ -25,15 +25,10 @@ struct BatchProb {
   PassATask a;                 // pass A task geometry (x, s1, s2, shapes, chunks, n_tasks)
   int32_t lpr;                 // pass A lanes per block row (256: wide rows in chunks; else one
                                // workgroup holds 256 / lpr blocks side by side)
-  int32_t window, hist_cap, chunk, n_chunks_max, n_groups, estimator, pad;
+  int32_t window, hist_cap, chunk, n_chunks, waves, estimator, pad;
   double k_sigma, expect_offset, sigma_override;
-  int32_t* hist[2];
-  int32_t* chunk_sum;
-  double* part_a;
-  double* part_q;
-  int64_t* part_r1;
-  int64_t* part_r2;
-  int32_t* part_n;
+  uint32_t* pc;                // pass B prefix sums
+  int32_t* hs[2];              // history suffix sums, ping-pong
   const uint8_t* mask;
   int64_t* r1;
   int64_t* r2;
@@ -42,8 +37,9 @@ struct BatchProb {
   int32_t* n_eff;
   float* sk_i;
   float* significance;
-  // Task ranges of each kernel over the whole batch.
-  int64_t a_begin, cs_begin, cs_count, hc_begin, hc_count, pt_begin, pt_count, fn_begin, fn_count;
+  // Task ranges of each kernel over the whole batch: pass A tasks, scan
+  // workgroups (channel, 64-input slice), combine workgroups (channel, chunk).
+  int64_t a_begin, sc_begin, sc_count, cb_begin, cb_count;
 };
 
 // Per-problem normaliser state kept on the device between calls.
@@ -56,14 +52,10 @@ __device__ __forceinline__ PassBArgs make_args(const BatchProb& P, const BatchSt
   PassBArgs a;
   a.s1 = P.a.s1;
   a.s2 = P.a.s2;
-  a.hist = P.hist[S.parity];
-  a.hist_next = P.hist[S.parity ^ 1];
-  a.chunk_sum = P.chunk_sum;
-  a.part_a = P.part_a;
-  a.part_q = P.part_q;
-  a.part_r1 = P.part_r1;
-  a.part_r2 = P.part_r2;
-  a.part_n = P.part_n;
+  a.cs = nullptr;
+  a.hs = P.hs[S.parity];
+  a.hs_next = P.hs[S.parity ^ 1];
+  a.pc = P.pc;
   a.mask = P.mask;
   a.r1 = P.r1;
   a.r2 = P.r2;
@@ -83,13 +75,8 @@ __device__ __forceinline__ PassBArgs make_args(const BatchProb& P, const BatchSt
   const int64_t total = (int64_t)S.hist_len + P.a.n_blocks;
   a.hist_next_len = (int32_t)(total < P.hist_cap ? total : P.hist_cap);
   a.chunk = P.chunk;
-  a.n_chunks = (int32_t)((total + P.chunk - 1) / P.chunk);
-  a.n_groups = P.n_groups;
+  a.n_chunks = P.n_chunks;
   a.vec = 4;
-  a.chunk0 = 0;
-  a.fin_b0 = 0;
-  a.fin_nb = P.a.n_blocks;
-  a.depth = 4;
   a.estimator = P.estimator;
   a.k_sigma = P.k_sigma;
   a.expect_offset = P.expect_offset;
@@ -131,59 +118,53 @@ __global__ __launch_bounds__(256) void batch_pass_a_kernel(const BatchProb* __re
   }
 }
 
-__global__ __launch_bounds__(256) void batch_chunk_sum_kernel(const BatchProb* __restrict__ probs,
-                                                              const BatchState* __restrict__ st, int n) {
+// Scan workgroups of the whole batch: (problem, channel, 64-input slice),
+// 16 wavefronts each (the prefix sums are exact integers, so they do not
+// depend on how the chunks are spread over the wavefronts).
+__global__ __launch_bounds__(64 * SCAN_MAX_WAVES) void batch_scan_kernel(const BatchProb* __restrict__ probs,
+                                                                        const BatchState* __restrict__ st, int n) {
+  __shared__ uint32_t lds[SCAN_MAX_WAVES * 64];
   const int64_t task = blockIdx.x;
-  const int p = find_prob<&BatchProb::cs_begin>(probs, n, task);
+  const int p = find_prob<&BatchProb::sc_begin>(probs, n, task);
   const BatchProb& P = probs[p];
-  const int64_t lt = task - P.cs_begin;
-  if (lt >= P.cs_count) return;
+  const int64_t lt = task - P.sc_begin;
+  if (lt >= P.sc_count) return;                       // whole workgroup
   const PassBArgs a = make_args(P, st[p]);
-  const int c = (int)(lt % P.n_chunks_max);
-  const int64_t rest = lt / P.n_chunks_max;
-  const int f = (int)(rest % a.n_channels), z = (int)(rest / a.n_channels);
-  if (c >= a.n_chunks) return;
-  chunk_sum_body<4>(a, c, f, z);
+  const int slices = (a.n_inputs + 63) / 64;
+  const int f = (int)(lt / slices), slice = (int)(lt % slices);
+  const int w = threadIdx.x >> 6, W = blockDim.x >> 6;
+  switch (a.chunk) {
+    case 1: scan_body<1>(a, f, slice, w, W, lds); break;
+    case 2: scan_body<2>(a, f, slice, w, W, lds); break;
+    default: scan_body<4>(a, f, slice, w, W, lds); break;
+  }
 }
 
-__global__ __launch_bounds__(256) void batch_hist_copy_kernel(const BatchProb* __restrict__ probs,
-                                                              const BatchState* __restrict__ st, int n) {
-  const int64_t task = blockIdx.x;
-  const int p = find_prob<&BatchProb::hc_begin>(probs, n, task);
-  const BatchProb& P = probs[p];
-  const int64_t lt = task - P.hc_begin;
-  if (lt >= P.hc_count) return;
-  const PassBArgs a = make_args(P, st[p]);
-  const int zc = (a.n_inputs + 1023) / 1024;
-  const int z = (int)(lt % zc);
-  const int64_t rest = lt / zc;
-  const int f = (int)(rest % a.n_channels), j = (int)(rest / a.n_channels);
-  hist_copy_body_v4(a, j, f, z);
+// Combine workgroups of the whole batch: (problem, channel, chunk), 8
+// wavefronts; a problem uses as many as the single-plan kernel does (the
+// others take no inputs), so results equal the plan's bit for bit.
+template <int R>
+__device__ __forceinline__ void batch_combine_r(const PassBArgs& a, int k, int f, int w, int W, CombineShared& sh) {
+  if (combine_sums_fit_32(a.n_inputs, 4, a.block_len)) combine_body<4, R, int32_t>(a, k, f, w, W, sh);
+  else combine_body<4, R, int64_t>(a, k, f, w, W, sh);
 }
 
-__global__ __launch_bounds__(256) void batch_partial_kernel(const BatchProb* __restrict__ probs,
-                                                            const BatchState* __restrict__ st, int n) {
+__global__ __launch_bounds__(64 * COMBINE_MAX_WAVES) void batch_combine_kernel(const BatchProb* __restrict__ probs,
+                                                                              const BatchState* __restrict__ st, int n) {
+  __shared__ CombineShared sh;
   const int64_t task = blockIdx.x;
-  const int p = find_prob<&BatchProb::pt_begin>(probs, n, task);
+  const int p = find_prob<&BatchProb::cb_begin>(probs, n, task);
   const BatchProb& P = probs[p];
-  const int64_t lt = task - P.pt_begin;
-  if (lt >= P.pt_count) return;
+  const int64_t lt = task - P.cb_begin;
+  if (lt >= P.cb_count) return;                       // whole workgroup
   const PassBArgs a = make_args(P, st[p]);
-  const int c = (int)(lt % P.n_chunks_max);
-  const int64_t rest = lt / P.n_chunks_max;
-  const int f = (int)(rest % a.n_channels), z = (int)(rest / a.n_channels);
-  if (c >= a.n_chunks) return;
-  partial_body<4>(a, c, f, z);
-}
-
-__global__ __launch_bounds__(256) void batch_finalize_kernel(const BatchProb* __restrict__ probs,
-                                                             const BatchState* __restrict__ st, int n) {
-  const int64_t task = blockIdx.x;
-  const int p = find_prob<&BatchProb::fn_begin>(probs, n, task);
-  const BatchProb& P = probs[p];
-  const int64_t lt = task - P.fn_begin;
-  if (lt >= P.fn_count) return;
-  finalize_body(make_args(P, st[p]), lt);
+  const int k = (int)(lt % a.n_chunks), f = (int)(lt / a.n_chunks);
+  const int w = threadIdx.x >> 6;
+  switch (a.chunk) {
+    case 1: batch_combine_r<1>(a, k, f, w, P.waves, sh); break;
+    case 2: batch_combine_r<2>(a, k, f, w, P.waves, sh); break;
+    default: batch_combine_r<4>(a, k, f, w, P.waves, sh); break;
+  }
 }
 
 // Last node: advance every problem's history and rearm the work queue.
@@ -255,7 +236,7 @@ struct sk_batch_s {
   BatchState* d_state = nullptr;
   uint32_t* d_counter = nullptr;
   std::vector<void*> owned;
-  int64_t total_a = 0, total_cs = 0, total_hc = 0, total_pt = 0, total_fn = 0;
+  int64_t total_a = 0, total_sc = 0, total_cb = 0;
   int grid_a = 0;
   int rows_a = 16;                 // pass A rows per load (autotuned: 8 or 16)
   bool use_graph = false;
@@ -293,18 +274,14 @@ static int launch_sequence(sk_batch_s* b, hipStream_t s) {
   else
     batch_pass_a_kernel<16><<<dim3(b->grid_a), dim3(256), 0, s>>>(b->d_probs, b->n, b->total_a, b->d_counter);
   SK_HIP_TRY(hipGetLastError());
-  if (b->total_cs > 0) {
-    batch_chunk_sum_kernel<<<dim3((unsigned)b->total_cs), dim3(256), 0, s>>>(b->d_probs, b->d_state, b->n);
+  if (b->total_sc > 0) {
+    batch_scan_kernel<<<dim3((unsigned)b->total_sc), dim3(64 * SCAN_MAX_WAVES), 0, s>>>(b->d_probs, b->d_state, b->n);
     SK_HIP_TRY(hipGetLastError());
   }
-  if (b->total_hc > 0) {
-    batch_hist_copy_kernel<<<dim3((unsigned)b->total_hc), dim3(256), 0, s>>>(b->d_probs, b->d_state, b->n);
+  if (b->total_cb > 0) {
+    batch_combine_kernel<<<dim3((unsigned)b->total_cb), dim3(64 * COMBINE_MAX_WAVES), 0, s>>>(b->d_probs, b->d_state, b->n);
     SK_HIP_TRY(hipGetLastError());
   }
-  batch_partial_kernel<<<dim3((unsigned)b->total_pt), dim3(256), 0, s>>>(b->d_probs, b->d_state, b->n);
-  SK_HIP_TRY(hipGetLastError());
-  batch_finalize_kernel<<<dim3((unsigned)b->total_fn), dim3(256), 0, s>>>(b->d_probs, b->d_state, b->n);
-  SK_HIP_TRY(hipGetLastError());
   batch_state_kernel<<<dim3(1), dim3(256), 0, s>>>(b->d_probs, b->d_state, b->n, b->d_counter);
   SK_HIP_TRY(hipGetLastError());
   return SK_OK;
@@ -401,18 +378,9 @@ int sk_batch_create(const sk_plan_desc* descs, int32_t n, const sk_batch_opts* o
     P.k_sigma = d.k_sigma;
     P.expect_offset = d.expect_offset;
     P.sigma_override = d.sigma_override;
-    const int64_t seq = P.hist_cap + B;
-    int32_t R = 1, Rmin = 1;
-    if (L >= 2) {
-      while (R < 64 && (int64_t)R * R * 2 < L) R *= 2;
-      while (Rmin < R && (int64_t)Rmin * Rmin * 8 < L) Rmin *= 2;
-    } else {
-      R = 16;
-    }
-    while (R > Rmin && ((seq + R - 1) / R) * F * ((N + 255) / 256) < 512) R /= 2;
-    P.chunk = R;
-    P.n_chunks_max = (int32_t)((seq + R - 1) / R);
-    P.n_groups = (int32_t)((N + 255) / 256);
+    P.chunk = pass_b_chunk((int32_t)N, (int32_t)F, B, L);
+    P.n_chunks = (int32_t)((B + P.chunk - 1) / P.chunk);
+    P.waves = combine_waves((int32_t)N, 4);
     P.mask = nullptr;
     const sk_outputs& o = outs[j];
     const size_t fbn = (size_t)F * B * N;
@@ -422,24 +390,13 @@ int sk_batch_create(const sk_plan_desc* descs, int32_t n, const sk_batch_opts* o
     if (o.s2) P.a.s2 = o.s2; else { rc = batch_alloc(b, &p, fbn * 4); P.a.s2 = (int32_t*)p; }
     if (rc) break;
     if (((uintptr_t)P.a.s1 | (uintptr_t)P.a.s2) % 16) { set_error("problem %d: outputs s1/s2 must be 16-byte aligned", j); rc = SK_ERR_INVALID_ARG; break; }
-    const size_t fgb = (size_t)F * P.n_groups * B;
-    if ((rc = batch_alloc(b, &p, fgb * 8))) break;
-    P.part_a = (double*)p;
-    if ((rc = batch_alloc(b, &p, fgb * 8))) break;
-    P.part_q = (double*)p;
-    if ((rc = batch_alloc(b, &p, fgb * 8))) break;
-    P.part_r1 = (int64_t*)p;
-    if ((rc = batch_alloc(b, &p, fgb * 8))) break;
-    P.part_r2 = (int64_t*)p;
-    if ((rc = batch_alloc(b, &p, fgb * 4))) break;
-    P.part_n = (int32_t*)p;
     if (L >= 2) {
-      if ((rc = batch_alloc(b, &p, (size_t)F * P.n_chunks_max * N * 4))) break;
-      P.chunk_sum = (int32_t*)p;
+      if ((rc = batch_alloc(b, &p, pass_b_prefix_bytes((int32_t)N, (int32_t)F, B, P.chunk)))) break;
+      P.pc = (uint32_t*)p;
       if ((rc = batch_alloc(b, &p, (size_t)F * P.hist_cap * N * 4))) break;
-      P.hist[0] = (int32_t*)p;
+      P.hs[0] = (int32_t*)p;
       if ((rc = batch_alloc(b, &p, (size_t)F * P.hist_cap * N * 4))) break;
-      P.hist[1] = (int32_t*)p;
+      P.hs[1] = (int32_t*)p;
     }
     P.r1 = o.r1;
     P.r2 = o.r2;
@@ -457,7 +414,7 @@ int sk_batch_create(const sk_plan_desc* descs, int32_t n, const sk_batch_opts* o
   s = b->cap_stream;
 
   // Task ranges.
-  int64_t ta = 0, tcs = 0, thc = 0, tpt = 0, tfn = 0;
+  int64_t ta = 0, tsc = 0, tcb = 0;
   for (int q = 0; q < n; ++q) {
     BatchProb& P = b->host[q];
     const int64_t F = P.a.row_bytes / P.a.n_inputs;
@@ -468,31 +425,21 @@ int sk_batch_create(const sk_plan_desc* descs, int32_t n, const sk_batch_opts* o
     P.a.n_tasks = (((int64_t)P.a.n_blocks + P.a.blocks_per_task - 1) / P.a.blocks_per_task) * P.a.chunks;
     P.a_begin = ta;
     ta += P.a.n_tasks;
-    const int zc = (P.a.n_inputs + 1023) / 1024;
-    P.cs_begin = tcs;
-    P.cs_count = P.window >= 2 ? (int64_t)P.n_chunks_max * F * zc : 0;
-    tcs += P.cs_count;
-    P.hc_begin = thc;
-    P.hc_count = (P.window >= 2 && P.a.n_blocks < P.hist_cap)
-                     ? (int64_t)(P.hist_cap - P.a.n_blocks) * F * ((P.a.n_inputs + 1023) / 1024) : 0;
-    thc += P.hc_count;
-    P.pt_begin = tpt;
-    P.pt_count = (int64_t)P.n_chunks_max * F * ((P.n_groups + 3) / 4);
-    tpt += P.pt_count;
-    P.fn_begin = tfn;
-    P.fn_count = (F * P.a.n_blocks + 255) / 256;
-    tfn += P.fn_count;
+    P.sc_begin = tsc;
+    P.sc_count = (P.window >= 2 && P.a.n_blocks > 0) ? F * ((P.a.n_inputs + 63) / 64) : 0;
+    tsc += P.sc_count;
+    P.cb_begin = tcb;
+    P.cb_count = F * P.n_chunks;
+    tcb += P.cb_count;
   }
-  if (ta >= (int64_t)UINT32_MAX || tcs >= (1LL << 31) || tpt >= (1LL << 31) || tfn >= (1LL << 31) || thc >= (1LL << 31)) {
+  if (ta >= (int64_t)UINT32_MAX || tsc >= (1LL << 31) || tcb >= (1LL << 31)) {
     batch_free(b);
     set_error("batch too large");
     return SK_ERR_SHAPE;
   }
   b->total_a = ta;
-  b->total_cs = tcs;
-  b->total_hc = thc;
-  b->total_pt = tpt;
-  b->total_fn = tfn;
+  b->total_sc = tsc;
+  b->total_cb = tcb;
 
   void* p = nullptr;
   if ((rc = batch_alloc(b, &p, sizeof(BatchProb) * n))) { batch_free(b); return rc; }

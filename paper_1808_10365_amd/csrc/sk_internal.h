@@ -51,51 +51,38 @@ struct PassATask {
 struct PassAConfig {
   int vec;     // 16, 4 or 1 bytes per lane per row
   int lpr;     // lanes per row: power of two, 1..256
-  int variant; // row batching variant (0..17, 16-byte path; see pass_a_groups_per_lane)
+  int variant; // 0 shared table; 16-byte path: 1, 2 packed, 3 side by side, 4 deferred stores
   int grid;    // workgroups launched (<= tasks; grid-stride beyond)
 };
 
 int launch_pass_a(const PassATask& t, const PassAConfig& c, hipStream_t s);
 int pick_vec(const uint8_t* x, int32_t n_inputs);
-// Column groups each lane owns in pass A for this vector width and variant.
-int pass_a_groups_per_lane(int vec, int variant);
-// Whether this variant uses the lane-replicated power table (needs >= 256
-// lanes per row: one row phase).
-bool pass_a_lane_table(int vec, int variant);
 // Lanes per row the variant supports; the planner clamps into [lo, hi].
 void pass_a_lane_range(int vec, int variant, int* lo, int* hi);
 // Whether the variant uses the packed lane table (tasks may span several blocks).
 bool pass_a_packed(int vec, int variant);
-// Variant 16: 256-lane tasks, blocks side by side for narrow rows.
+// Variant 3: 256-lane tasks, blocks side by side for narrow rows.
 bool pass_a_side_by_side(int vec, int variant);
 int pass_a_side_by_side_lanes(int64_t col_groups);
-// Variant 17: blocks held per task (stores deferred to the task's end).
+// Variant 4: blocks held per task (stores deferred to the task's end).
 bool pass_a_deferred(int vec, int variant);
 int pass_a_deferred_blocks(int64_t n_blocks, int64_t col_groups, int n_cu);
-// lane_table: the lane-replicated table variants may be chosen (single-plan
-// kernel only; the batched kernel has its own table).
+// lane_table: the packed lane-table variants may be chosen.
 PassAConfig default_pass_a_config(int vec, int64_t row_bytes, int64_t n_blocks, int block_len, bool lane_table,
                                   int n_cu);
 
 // ---------------------------------------------------------------- pass B
 // Normaliser window, array combine, estimator and flags (Eq. discreteMean,
-// normedSum1/2, avgSK, final; Sec. 3.2).
-//
-// Extended block sequence per (channel, input): e = 0..H-1 are the H history
-// blocks (oldest first), e = H..H+B-1 the blocks of this call. Chunks of R
-// consecutive e carry exclusive prefix sums so any window sum is two lookups
-// plus fewer than R reads.
+// normedSum1/2, avgSK, final; Sec. 3.2). Kernels and positions: see
+// sk_pass_b_dev.h. A call runs the scan kernel (L >= 2), then the combine
+// kernel.
 struct PassBArgs {
   const int32_t* s1;      // [F][B][N]
   const int32_t* s2;      // [F][B][N]
-  const int32_t* hist;    // [F][Hcap][N], entries 0..H-1 valid (oldest first)
-  int32_t* hist_next;     // [F][Hcap][N] history for the next call
-  int32_t* chunk_sum;     // [F][n_chunks][N] sums of S1 over chunks of the sequence
-  double* part_a;         // [F][n_groups][B] per-group partial sums
-  double* part_q;
-  int64_t* part_r1;
-  int64_t* part_r2;
-  int32_t* part_n;
+  const int32_t* cs;      // [F][n_chunks][N] S1 summed over each chunk (pass A), or null: from s1
+  const int32_t* hs;      // [F][hist_cap][N] history suffix sums (slots >= hist_cap - hist_len valid)
+  int32_t* hs_next;       // [F][hist_cap][N] the same for the next call
+  uint32_t* pc;           // [F][n_chunks + 1][N] exclusive prefix sums of S1 at chunk boundaries
   const uint8_t* mask;    // [F][N] or null
   int64_t* r1;            // [F][B] or null
   int64_t* r2;
@@ -106,35 +93,19 @@ struct PassBArgs {
   float* significance;    // [F][B] or null
   const double* thresholds;  // [N + 1][2] (lo, hi) by N_eff, or null: E -+ k sigma
   int32_t n_inputs, n_channels, n_blocks, block_len, window, hist_len, hist_cap, hist_next_len;
-  int32_t chunk, n_chunks, n_groups, vec, estimator;
-  // Range of one launch sequence: chunks [chunk0, chunk0 + grid) of the
-  // chunk-sum and partial kernels, blocks [fin_b0, fin_b0 + fin_nb) of the
-  // finalize kernel (a whole call: 0, n_chunks, 0, n_blocks).
-  int32_t chunk0, fin_b0, fin_nb;
-  int32_t depth;          // blocks a partial-kernel wavefront loads together (2, 4 or 8)
+  int32_t chunk;          // R: blocks per combine workgroup and per prefix step (1, 2 or 4)
+  int32_t n_chunks;       // ceil(B / R)
+  int32_t vec;            // inputs per combine lane: 4 (16-byte aligned sums, N % 4 == 0) or 1
+  int32_t estimator;
   double k_sigma, expect_offset, sigma_override;
 };
 
+// Library choice of R for a call of B blocks (F channels, N inputs).
+int pass_b_chunk(int32_t n_inputs, int32_t n_channels, int64_t n_blocks, int32_t window);
 int pass_b_vec(int32_t n_inputs);
+// Device bytes of the prefix buffer: F (ceil(B / R) + 1) N uint32.
+size_t pass_b_prefix_bytes(int32_t n_inputs, int32_t n_channels, int64_t n_blocks, int32_t chunk);
 int launch_pass_b(const PassBArgs& a, hipStream_t s);
-// Pass B kernels for chunks [c_begin, c_end) and blocks [b_begin, b_end) of
-// one call; the history carry (when a call is shorter than the window) runs
-// with the range that has with_hist_copy set.
-int launch_pass_b_range(PassBArgs a, int32_t c_begin, int32_t c_end, int32_t b_begin, int32_t b_end,
-                        bool with_hist_copy, hipStream_t s);
-
-// ---------------------------------------------------------------- single launch
-// One cooperative kernel for wide rows filling one round of CUs (see
-// sk_fused.hip): pass A, the window scans and pass B of a call.
-struct FusedArgs {
-  PassATask a;          // x, s1 (always written), s2 (null: not stored), geometry
-  PassBArgs b;          // window, history, outputs, flag parameters
-  int32_t* segsum;      // [segments][F*N] S1 sums of each workgroup's blocks
-  int32_t* segpre;      // [segments][F*N] exclusive prefix over segments
-  int32_t* hsuf;        // [hist_cap][F*N] suffix sums of the history rows
-};
-int launch_fused(const FusedArgs& fa, int blocks_per_workgroup, hipStream_t s);
-int fused_max_workgroups();
 
 double pearson3_quantile(double mean, double sd, double skew, double p);
 

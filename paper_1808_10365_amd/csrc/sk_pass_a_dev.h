@@ -68,57 +68,12 @@ __device__ __forceinline__ void accumulate_one(const Row<VEC>& r0, const uint16_
   }
 }
 
-// Power table replicated per lane: the entry of code c for lane l is the
-// low 16 bits of the dword at byte (c << 8) | (l % 64) * 4, 64 KiB in all.
-// The 64 lanes of a wavefront always read 64 distinct consecutive dwords
-// (no bank conflicts whatever the codes), and one v_perm_b32 forms the
-// address: byte 1 = the code byte, byte 0 = the lane's offset.
-struct LaneLut {
-  const uint8_t* base;
-  uint32_t laneoff;
-  __device__ __forceinline__ uint32_t at(uint32_t w, int k) const {
-    const uint32_t sel = 0x0C0C0000u | ((uint32_t)(4 + k) << 8);
-    return *reinterpret_cast<const uint16_t*>(base + __builtin_amdgcn_perm(w, laneoff, sel));
-  }
-};
-constexpr int LANE_LUT_DWORDS = 256 * 64;
-
-// Fill a lane-replicated table with WG lanes (16-byte stores).
-template <int WG>
-__device__ __forceinline__ void fill_lane_lut(uint32_t* t, int tid) {
-  for (int k = tid; k < LANE_LUT_DWORDS / 4; k += WG) {
-    const uint32_t p = code_power((uint32_t)(k >> 4));
-    reinterpret_cast<u32x4*>(t)[k] = u32x4{p, p, p, p};
-  }
-}
-
-template <int VEC>
-__device__ __forceinline__ void accumulate_pair(const Row<VEC>& r0, const Row<VEC>& r1,
-                                                const LaneLut& lut, uint32_t* s1, uint32_t* s2) {
-  static_assert(VEC >= 4, "the lane table reads bytes of whole dwords");
-  const u16x2 ones = {1, 1};
-#pragma unroll
-  for (int k = 0; k < VEC; ++k) {
-    const uint32_t pp = lut.at(r0.w[k >> 2], k & 3) | (lut.at(r1.w[k >> 2], k & 3) << 16);
-    const u16x2 P = __builtin_bit_cast(u16x2, pp);
-    s2[k] = __builtin_amdgcn_udot2(P, P, s2[k], false);
-    s1[k] = __builtin_amdgcn_udot2(P, ones, s1[k], false);
-  }
-}
-
-template <int VEC>
-__device__ __forceinline__ void accumulate_one(const Row<VEC>& r0, const LaneLut& lut,
-                                               uint32_t* s1, uint32_t* s2) {
-#pragma unroll
-  for (int k = 0; k < VEC; ++k) {
-    const uint32_t p = lut.at(r0.w[k >> 2], k & 3);
-    s1[k] += p;
-    s2[k] += p * p;
-  }
-}
-
-// Packed lane table: the same per-lane layout as LaneLut, each dword holding
-// p | p^2 << 12 for its code. Over at most 16 rows, sum p <= 2048 stays in
+// Packed power table replicated per lane: the entry of code c for lane l is
+// the dword at byte (c << 8) | (l % 64) * 4, 64 KiB in all, holding
+// p | p^2 << 12 for code c. The 64 lanes of a wavefront always read 64
+// distinct consecutive dwords (no bank conflicts whatever the codes), and
+// one v_perm_b32 forms the address: byte 1 = the code byte, byte 0 = the
+// lane's offset. Over at most 16 rows, sum p <= 2048 stays in
 // the low 12 bits and sum p^2 <= 2^18 in the next 19, so one 32-bit add per
 // sample (v_add3_u32 folds two rows) accumulates both sums; every 16 rows
 // the packed sums are split into S1 and S2.
@@ -132,6 +87,8 @@ struct LanePackedLut {
 };
 constexpr int PACK_ROWS = 16;
 constexpr int PACK_SHIFT = 12;
+
+constexpr int LANE_LUT_DWORDS = 256 * 64;
 
 template <int WG>
 __device__ __forceinline__ void fill_lane_packed_lut(uint32_t* t, int tid) {
@@ -183,41 +140,21 @@ __device__ __forceinline__ void sum_rows_packed(const uint8_t* base, int64_t G, 
   }
 }
 
-// Rows of this lane in batches of U: r = ph, ph + RP, ... (< M). With PF the
-// loads of the next batch are issued before the current batch is reduced, so
-// each wavefront keeps a batch of rows in flight while it computes.
-template <int VEC, int RP, int U, bool PF, typename Lut>
+// Rows of this lane in batches of U: r = ph, ph + RP, ... (< M), the loads
+// of a batch issued together, then reduced in row pairs.
+template <int VEC, int RP, int U>
 __device__ __forceinline__ void sum_rows(const uint8_t* base, int64_t G, int M, int ph,
-                                         const Lut& lut, uint32_t* s1, uint32_t* s2) {
+                                         const uint16_t* lut, uint32_t* s1, uint32_t* s2) {
   const int nrow = ph < M ? (M - ph + RP - 1) / RP : 0;
   const int nb = nrow / U;
   int r = ph;
-  if constexpr (PF) {
-    Row<VEC> cur[U], nxt[U];
-    if (nb > 0) {
+  for (int bt = 0; bt < nb; ++bt) {
+    Row<VEC> q[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) cur[u].load(base + (int64_t)(r + u * RP) * G);
-    }
-    for (int bt = 0; bt < nb; ++bt) {
-      if (bt + 1 < nb) {
+    for (int u = 0; u < U; ++u) q[u].load(base + (int64_t)(r + u * RP) * G);
 #pragma unroll
-        for (int u = 0; u < U; ++u) nxt[u].load(base + (int64_t)(r + (U + u) * RP) * G);
-      }
-#pragma unroll
-      for (int u = 0; u < U / 2; ++u) accumulate_pair<VEC>(cur[2 * u], cur[2 * u + 1], lut, s1, s2);
-#pragma unroll
-      for (int u = 0; u < U; ++u) cur[u] = nxt[u];
-      r += U * RP;
-    }
-  } else {
-    for (int bt = 0; bt < nb; ++bt) {
-      Row<VEC> q[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) q[u].load(base + (int64_t)(r + u * RP) * G);
-#pragma unroll
-      for (int u = 0; u < U / 2; ++u) accumulate_pair<VEC>(q[2 * u], q[2 * u + 1], lut, s1, s2);
-      r += U * RP;
-    }
+    for (int u = 0; u < U / 2; ++u) accumulate_pair<VEC>(q[2 * u], q[2 * u + 1], lut, s1, s2);
+    r += U * RP;
   }
   for (; r + RP < M; r += 2 * RP) {
     Row<VEC> q0, q1;
@@ -229,54 +166,6 @@ __device__ __forceinline__ void sum_rows(const uint8_t* base, int64_t G, int M, 
     Row<VEC> q0;
     q0.load(base + (int64_t)r * G);
     accumulate_one<VEC>(q0, lut, s1, s2);
-  }
-}
-
-// Several column groups per lane: group j starts at base[j] (the same row
-// layout). Each batch issues the loads of U rows of every group before any
-// of them is reduced, so a lane keeps GPL * U rows in flight.
-template <int VEC, int RP, int U, int GPL, typename Lut>
-__device__ __forceinline__ void sum_rows_multi(const uint8_t* const* base, int64_t G, int M, int ph,
-                                               const Lut& lut, uint32_t (*s1)[VEC], uint32_t (*s2)[VEC]) {
-  static_assert(U % 2 == 0, "rows are reduced in pairs");
-  const int nrow = ph < M ? (M - ph + RP - 1) / RP : 0;
-  const int nb = nrow / U;
-  const int64_t step = (int64_t)RP * G;
-  const uint8_t* p[GPL];
-#pragma unroll
-  for (int j = 0; j < GPL; ++j) p[j] = base[j] + (int64_t)ph * G;
-  int r = ph;
-  for (int bt = 0; bt < nb; ++bt) {
-    Row<VEC> q[GPL][U];
-#pragma unroll
-    for (int j = 0; j < GPL; ++j)
-#pragma unroll
-      for (int u = 0; u < U; ++u) q[j][u].load(p[j] + u * step);
-#pragma unroll
-    for (int j = 0; j < GPL; ++j) {
-#pragma unroll
-      for (int u = 0; u < U / 2; ++u) accumulate_pair<VEC>(q[j][2 * u], q[j][2 * u + 1], lut, s1[j], s2[j]);
-      p[j] += U * step;
-    }
-    r += U * RP;
-  }
-  for (; r + RP < M; r += 2 * RP) {
-#pragma unroll
-    for (int j = 0; j < GPL; ++j) {
-      Row<VEC> q0, q1;
-      q0.load(p[j]);
-      q1.load(p[j] + step);
-      accumulate_pair<VEC>(q0, q1, lut, s1[j], s2[j]);
-      p[j] += 2 * step;
-    }
-  }
-  if (r < M) {
-#pragma unroll
-    for (int j = 0; j < GPL; ++j) {
-      Row<VEC> q0;
-      q0.load(p[j]);
-      accumulate_one<VEC>(q0, lut, s1[j], s2[j]);
-    }
   }
 }
 
@@ -322,33 +211,5 @@ __device__ __forceinline__ void pass_a_task_side_by_side(const PassATask& t, int
   }
 }
 
-
-// The same row walk with the row-phase count known only at run time.
-template <int VEC, int U>
-__device__ __forceinline__ void sum_rows_rt(const uint8_t* base, int64_t G, int M, int ph, int rp,
-                                            const uint16_t* lut, uint32_t* s1, uint32_t* s2) {
-  const int nrow = ph < M ? (M - ph + rp - 1) / rp : 0;
-  const int nb = nrow / U;
-  int r = ph;
-  for (int bt = 0; bt < nb; ++bt) {
-    Row<VEC> q[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) q[u].load(base + (int64_t)(r + u * rp) * G);
-#pragma unroll
-    for (int u = 0; u < U / 2; ++u) accumulate_pair<VEC>(q[2 * u], q[2 * u + 1], lut, s1, s2);
-    r += U * rp;
-  }
-  for (; r + rp < M; r += 2 * rp) {
-    Row<VEC> q0, q1;
-    q0.load(base + (int64_t)r * G);
-    q1.load(base + (int64_t)(r + rp) * G);
-    accumulate_pair<VEC>(q0, q1, lut, s1, s2);
-  }
-  if (r < M) {
-    Row<VEC> q0;
-    q0.load(base + (int64_t)r * G);
-    accumulate_one<VEC>(q0, lut, s1, s2);
-  }
-}
 
 }  // namespace sk

@@ -1,6 +1,35 @@
-// Pass B device code shared by the single-plan and batched kernels:
-// window sums, array combine, estimator and flags (Eq. discreteMean,
-// normedSum1/2, avgSK, final; Sec. 3.2).
+// Pass B device code shared by the single-plan and batched kernels: the
+// normaliser window (Eq. discreteMean, running form), the array combine
+// (Eq. normedSum1, normedSum2), the estimator (Eq. avgSK, final) and the
+// flags (Sec. 3.2).
+//
+// Positions. Per (channel f, input i) the blocks of a call are positions
+// b = 0 .. B-1; the history, the last H <= L-1 blocks of earlier calls, sits
+// at positions -H .. -1. The window of block b is [max(b - L + 1, -H), b].
+//
+// State. The history is kept as suffix sums HS(y) = sum of S1 over positions
+// [y, 0), y in [-H, 0) (HS(0) = 0, and HS(y) = HS(-H) for y < -H), one int32
+// per (f, slot, i) with slot = y + L - 1. A history block is the difference
+// of two neighbours, and the window's history part is one value.
+//
+// Kernels.
+//   scan     (L >= 2) exclusive prefix sums of S1 at the chunk boundaries of
+//            the call, PC[k] = sum of S1 over [0, k R) (mod 2^32: every
+//            difference that is used is a window sum < 2^31, so it is exact),
+//            one lane per (f, i), a workgroup's wavefronts over consecutive
+//            chunk ranges joined through LDS. It also carries the older
+//            history into the next call's suffix sums when a call is shorter
+//            than the window.
+//   combine  one workgroup per (f, chunk k of R blocks), one wavefront per
+//            64 V inputs. The window sum before the chunk is at most two
+//            prefix values, R - 1 edge rows and one history value; then the
+//            sliding update P += S1[b] - S1[b - L] over the chunk. Per input
+//            FP64 S1/P and S2/P^2 and the raw int sums, wavefront sums in a
+//            fixed tree, wavefronts joined in LDS in a fixed order, then the
+//            estimator and flags of the chunk's blocks. It also writes the
+//            next call's history suffix sums for its blocks.
+// Every load of a wavefront is issued before any of them is used, so a
+// combine wavefront costs one memory round trip.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -31,160 +60,112 @@ struct IVec<4> {
   }
 };
 
-template <>
-struct IVec<8> {
-  int32_t v[8];
-  __device__ __forceinline__ void load(const int32_t* p) {
-    const int4 q = *reinterpret_cast<const int4*>(p);
-    const int4 r = *reinterpret_cast<const int4*>(p + 4);
-    v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
-    v[4] = r.x; v[5] = r.y; v[6] = r.z; v[7] = r.w;
-  }
-  __device__ __forceinline__ void store(int32_t* p) const {
-    *reinterpret_cast<int4*>(p) = make_int4(v[0], v[1], v[2], v[3]);
-    *reinterpret_cast<int4*>(p + 4) = make_int4(v[4], v[5], v[6], v[7]);
-  }
-};
-
-// Row of S1 for sequence position e (history or this call), channel f.
-__device__ __forceinline__ const int32_t* seq_row(const PassBArgs& a, int f, int64_t e) {
-  if (e < a.hist_len) return a.hist + ((int64_t)f * a.hist_cap + e) * a.n_inputs;
-  return a.s1 + ((int64_t)f * a.n_blocks + (e - a.hist_len)) * a.n_inputs;
-}
-
 template <int V>
-__device__ __forceinline__ void chunk_sum_body(const PassBArgs& a, int c, int f, int z) {
-  const int i0 = (z * 256 + threadIdx.x) * V;
-  if (i0 >= a.n_inputs) return;
-  const int64_t total = (int64_t)a.hist_len + a.n_blocks;
-  const int64_t e0 = (int64_t)c * a.chunk;
-  const int64_t e1 = e0 + a.chunk < total ? e0 + a.chunk : total;
-  IVec<V> s;
+__device__ __forceinline__ void zero(IVec<V>& x) {
 #pragma unroll
-  for (int k = 0; k < V; ++k) s.v[k] = 0;
-  // Rows in groups of 8 loaded together (independent loads in flight).
-  int64_t e = e0;
-  for (; e + 8 <= e1; e += 8) {
-    IVec<V> x[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) x[u].load(seq_row(a, f, e + u) + i0);
-#pragma unroll
-    for (int u = 0; u < 8; ++u)
-#pragma unroll
-      for (int k = 0; k < V; ++k) s.v[k] += x[u].v[k];
-  }
-  for (; e < e1; ++e) {
-    IVec<V> x;
-    x.load(seq_row(a, f, e) + i0);
-#pragma unroll
-    for (int k = 0; k < V; ++k) s.v[k] += x.v[k];
-  }
-  s.store(a.chunk_sum + ((int64_t)f * a.n_chunks + c) * a.n_inputs + i0);
+  for (int k = 0; k < V; ++k) x.v[k] = 0;
 }
 
-// Adds S1 of sequence positions [from, to) for V inputs at i0 into out,
-// eight rows loaded together (independent loads in flight, the last group
-// predicated).
-template <int V>
-__device__ __forceinline__ void add_rows(const PassBArgs& a, int f, int64_t from, int64_t to, int i0, int32_t* out) {
-  for (int64_t e = from; e < to; e += 8) {
-    IVec<V> x[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-#pragma unroll
-      for (int k = 0; k < V; ++k) x[u].v[k] = 0;
-      if (e + u < to) x[u].load(seq_row(a, f, e + u) + i0);
-    }
-#pragma unroll
-    for (int u = 0; u < 8; ++u)
-#pragma unroll
-      for (int k = 0; k < V; ++k) out[k] += x[u].v[k];
-  }
-}
+// ------------------------------------------------------------------ wavefront sums
+//
+// One fixed tree for every value: lanes l and l + 32 first (v_permlane32_swap),
+// then rows 0 + 1 and 2 + 3 of the result (v_permlane16_swap), then within a
+// row of 16 lanes l + 8, l + 4, l + 2, l + 1 (DPP row rotations). Two values
+// share each swap step (a reduce-scatter), so n values cost about n/4 of n
+// separate reductions, and each value is added in the same order whichever
+// values it is reduced with: results do not depend on the tile.
 
-// Windows of at most SHORT_WINDOW blocks are summed from their rows (a
-// batch or two of loads); the chunk sums, and their launch, serve longer ones.
-constexpr int SHORT_WINDOW = 16;
-
-// Sum of S1 over sequence positions [lo, hi) for V inputs at i0: the chunk
-// sums of the chunks wholly inside, plus the rows at either edge.
-template <int V>
-__device__ void window_sum(const PassBArgs& a, int f, int64_t lo, int64_t hi, int i0, int32_t* out) {
-#pragma unroll
-  for (int k = 0; k < V; ++k) out[k] = 0;
-  if (hi <= lo) return;
-  const int64_t R = a.chunk;
-  const int64_t cs = (lo + R - 1) / R;   // first chunk fully inside
-  const int64_t ce = hi / R;             // one past the last chunk fully inside
-  if (a.window > SHORT_WINDOW && cs < ce) {
-#pragma unroll 8
-    for (int64_t c = cs; c < ce; ++c) {
-      IVec<V> t;
-      t.load(a.chunk_sum + ((int64_t)f * a.n_chunks + c) * a.n_inputs + i0);
-#pragma unroll
-      for (int k = 0; k < V; ++k) out[k] += t.v[k];
-    }
-    add_rows<V>(a, f, lo, cs * R, i0, out);
-    add_rows<V>(a, f, ce * R, hi, i0, out);
-  } else {
-    add_rows<V>(a, f, lo, hi, i0, out);
-  }
-}
-
-// Wavefront sums with DPP lane moves (VALU only, no LDS). Butterflies
-// inside each row of 16 lanes (quad_perm xor 1, xor 2, half-row mirror, row
-// mirror), then row_bcast:15 and row_bcast:31 fold the four rows; the total
-// lands in lane 63. The order of additions is fixed.
-// With every row enabled (the butterflies) each lane is written, so a plain
-// DPP move suffices; the broadcast steps enable some rows only, and the
-// others must read 0, so they keep an explicit zero as the old value.
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ uint32_t dpp_mov(uint32_t v) {
-  if constexpr (ROW_MASK == 0xF)
-    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, ROW_MASK, 0xF, false);
-  else
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, 0xF, false);
-}
-
-// 64-bit values move as their two 32-bit halves; the halves are regrouped
-// through a two-lane vector (a register pair, no shifts or adds).
-typedef uint32_t dpp_u32x2 __attribute__((ext_vector_type(2)));
-
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ double dpp_step(double v) {
-  const dpp_u32x2 u = __builtin_bit_cast(dpp_u32x2, v);
-  dpp_u32x2 m;
-  m.x = dpp_mov<CTRL, ROW_MASK>(u.x);
-  m.y = dpp_mov<CTRL, ROW_MASK>(u.y);
-  return v + __builtin_bit_cast(double, m);
-}
-
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ int64_t dpp_step(int64_t v) {
-  const dpp_u32x2 u = __builtin_bit_cast(dpp_u32x2, v);
-  dpp_u32x2 m;
-  m.x = dpp_mov<CTRL, ROW_MASK>(u.x);
-  m.y = dpp_mov<CTRL, ROW_MASK>(u.y);
-  return v + __builtin_bit_cast(int64_t, m);
-}
-
-// 32-bit sums: the zero-old form folds into one v_add_u32 with a DPP source.
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ int32_t dpp_step(int32_t v) {
-  return v + __builtin_amdgcn_update_dpp(0, v, CTRL, ROW_MASK, 0xF, false);
-}
-
-// Sum over the 64 lanes, valid in lane 63.
 template <typename T>
-__device__ __forceinline__ T wave_sum_to_last(T v) {
-  v = dpp_step<0xB1, 0xF>(v);    // quad_perm [1,0,3,2]
-  v = dpp_step<0x4E, 0xF>(v);    // quad_perm [2,3,0,1]
-  v = dpp_step<0x141, 0xF>(v);   // row_half_mirror
-  v = dpp_step<0x140, 0xF>(v);   // row_mirror
-  v = dpp_step<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
-  v = dpp_step<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
+__device__ __forceinline__ void swap_halves(T& x, T& y) {
+  // After the swap, x holds x's lanes 0-31 and y's lanes 0-31 (in lanes
+  // 32-63); y holds x's lanes 32-63 (in lanes 0-31) and y's lanes 32-63.
+  if constexpr (sizeof(T) == 4) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(uint32_t, x), __builtin_bit_cast(uint32_t, y),
+                                                    false, false);
+    x = __builtin_bit_cast(T, (uint32_t)r[0]);
+    y = __builtin_bit_cast(T, (uint32_t)r[1]);
+  } else {
+    typedef uint32_t u2 __attribute__((ext_vector_type(2)));
+    u2 a = __builtin_bit_cast(u2, x), b = __builtin_bit_cast(u2, y);
+    const auto r0 = __builtin_amdgcn_permlane32_swap(a.x, b.x, false, false);
+    const auto r1 = __builtin_amdgcn_permlane32_swap(a.y, b.y, false, false);
+    a.x = r0[0]; b.x = r0[1];
+    a.y = r1[0]; b.y = r1[1];
+    x = __builtin_bit_cast(T, a);
+    y = __builtin_bit_cast(T, b);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void swap_rows(T& x, T& y) {
+  // Rows of 16 lanes: x becomes (x0, y0, x2, y2), y becomes (x1, y1, x3, y3).
+  if constexpr (sizeof(T) == 4) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(uint32_t, x), __builtin_bit_cast(uint32_t, y),
+                                                    false, false);
+    x = __builtin_bit_cast(T, (uint32_t)r[0]);
+    y = __builtin_bit_cast(T, (uint32_t)r[1]);
+  } else {
+    typedef uint32_t u2 __attribute__((ext_vector_type(2)));
+    u2 a = __builtin_bit_cast(u2, x), b = __builtin_bit_cast(u2, y);
+    const auto r0 = __builtin_amdgcn_permlane16_swap(a.x, b.x, false, false);
+    const auto r1 = __builtin_amdgcn_permlane16_swap(a.y, b.y, false, false);
+    a.x = r0[0]; b.x = r0[1];
+    a.y = r1[0]; b.y = r1[1];
+    x = __builtin_bit_cast(T, a);
+    y = __builtin_bit_cast(T, b);
+  }
+}
+
+// Lane l + r (mod 16, within its row) of v, every row enabled.
+template <int R, typename T>
+__device__ __forceinline__ T row_rot(T v) {
+  constexpr int CTRL = 0x120 + R;   // DPP row_ror:R
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+  } else {
+    typedef int i2 __attribute__((ext_vector_type(2)));
+    i2 a = __builtin_bit_cast(i2, v);
+    a.x = __builtin_amdgcn_mov_dpp(a.x, CTRL, 0xF, 0xF, false);
+    a.y = __builtin_amdgcn_mov_dpp(a.y, CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(T, a);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ T row_total(T v) {
+  v = v + row_rot<8>(v);
+  v = v + row_rot<4>(v);
+  v = v + row_rot<2>(v);
+  v = v + row_rot<1>(v);
   return v;
 }
+
+// Sums each of NV values (NV a power of two >= 2) over the wavefront.
+// Value j ends in every lane of the row of out[j / 4] that
+// wave_value_of_row names.
+template <int NV, typename T>
+__device__ __forceinline__ void wave_sums(const T (&v)[NV], T (&out)[(NV + 3) / 4]) {
+  static_assert(NV >= 2 && (NV & (NV - 1)) == 0, "a power of two, at least 2");
+  constexpr int NC = NV / 2;
+  T c[NC];
+#pragma unroll
+  for (int m = 0; m < NC; ++m) {
+    T x = v[2 * m], y = v[2 * m + 1];
+    swap_halves(x, y);
+    c[m] = x + y;
+  }
+#pragma unroll
+  for (int q = 0; q < (NV + 3) / 4; ++q) {
+    T x = c[2 * q], y = 2 * q + 1 < NC ? c[2 * q + 1] : c[2 * q];
+    swap_rows(x, y);
+    out[q] = row_total(x + y);
+  }
+}
+
+// The value a lane of row r holds in out[q] after wave_sums: 4q + 2 (r & 1) + (r >> 1).
+__device__ __forceinline__ int wave_value_of_row(int q, int r) { return 4 * q + 2 * (r & 1) + (r >> 1); }
+
+// ------------------------------------------------------------------ estimator
 
 // Eq. originalSK: (M+1)/(M-1) (M S2 / S1^2 - 1), NaN where S1 = 0.
 __device__ __forceinline__ float per_input_sk(int32_t s1, int32_t s2, int32_t block_len) {
@@ -205,12 +186,10 @@ __device__ __forceinline__ double recip_pos(double p) {
   return __builtin_fma(r, e, r);
 }
 
-// RI: integer type of the per-wavefront R1/R2 sums: int32_t when a
-// wavefront's sums provably fit (64 V M 2^14 < 2^31), else int64_t.
 // Estimator and flags from the combined sums (Eq. avgSK, final; Sec. 3.2).
 // Contraction is off so the rounding steps are the plain ones.
 __device__ __forceinline__ void finish(const PassBArgs& a, int f, int b, double A, double Bq, int64_t R1, int64_t R2,
-                       int32_t n) {
+                                       int32_t n) {
 #pragma clang fp contract(off)
   const int64_t K = (int64_t)n * a.block_len;
   const double Kd = (double)K, Md = (double)a.block_len;
@@ -262,199 +241,327 @@ __device__ __forceinline__ void finish(const PassBArgs& a, int f, int b, double 
   if (a.n_eff) a.n_eff[o] = n;
 }
 
-// FIN: the workgroup holds every input group of the channel (one wavefront
-// per group, z = 0, at most MAX_FIN_GROUPS) and finishes its blocks itself.
-// The wavefront sums of up to FIN_SLOTS blocks wait in LDS; then, after one
-// barrier, they are added in group order (the order finalize_body uses, so
-// every output is the same bit for bit) and the blocks are finished.
-constexpr int MAX_FIN_GROUPS = 4;
-constexpr int FIN_SLOTS = 32;
+// ------------------------------------------------------------------ scan
 
-template <int V, typename RI, int U, bool FIN = false>
-__device__ __forceinline__ void partial_body_t(const PassBArgs& a, int c, int f, int z) {
-  // U: blocks whose rows are loaded together.
-  static_assert(!FIN || U <= FIN_SLOTS, "a batch must fit the slots");
-  __shared__ double fin_a[FIN ? FIN_SLOTS : 1][FIN ? MAX_FIN_GROUPS : 1];
-  __shared__ double fin_q[FIN ? FIN_SLOTS : 1][FIN ? MAX_FIN_GROUPS : 1];
-  __shared__ int64_t fin_r1[FIN ? FIN_SLOTS : 1][FIN ? MAX_FIN_GROUPS : 1];
-  __shared__ int64_t fin_r2[FIN ? FIN_SLOTS : 1][FIN ? MAX_FIN_GROUPS : 1];
-  __shared__ int32_t fin_n[FIN ? FIN_SLOTS : 1][FIN ? MAX_FIN_GROUPS : 1];
-  int pend = 0;                                                // blocks waiting in LDS
+constexpr int SCAN_MAX_WAVES = 16;
+
+// Chunks a scan lane holds per round: 64 rows of S1 in flight at most.
+template <int R>
+constexpr int scan_chunks_per_lane() { return 64 / R; }
+
+// One workgroup of W wavefronts: channel f, inputs [64 slice, 64 slice + 64),
+// one input per lane. Wavefront w takes chunks [k0, k0 + C) of each round of
+// C W chunks (C = 64 / R); the rounds carry the running prefix. S1 of a
+// chunk is the pass A chunk sum when the call has them (a.cs), else the sum
+// of its R rows. lds: W * 64 words.
+template <int R>
+__device__ __forceinline__ void scan_body(const PassBArgs& a, int f, int slice, int w, int W, uint32_t* lds) {
+  constexpr int C = scan_chunks_per_lane<R>();
   const int lane = threadIdx.x & 63;
-  const int g = z * 4 + (threadIdx.x >> 6);                   // input group of 64*V
-  const int N = a.n_inputs, L = a.window, H = a.hist_len;
-  const int i0 = (g * 64 + lane) * V;
-  if (g >= a.n_groups) return;                                 // whole wavefront exits
-  const bool active = i0 < N;
-  const int64_t total = (int64_t)H + a.n_blocks;
-  int64_t e0 = (int64_t)c * a.chunk;
-  if (e0 < H) e0 = H;
-  int64_t e1 = (int64_t)(c + 1) * a.chunk;
-  if (e1 > total) e1 = total;
-  if (e0 >= e1) return;
-  const int64_t hist_from = total - a.hist_next_len;          // first e of the next history
-
-  int32_t P[V];
+  const int i = slice * 64 + lane;
+  const bool active = i < a.n_inputs;
+  const int nk = a.n_chunks, B = a.n_blocks;
+  const int64_t rowN = a.n_inputs;
+  uint32_t* pc = a.pc + (int64_t)f * (nk + 1) * rowN + i;
+  if (w == 0 && active) pc[0] = 0u;
+  uint32_t carry = 0;   // prefix before this round, for this lane's input
+  for (int base = 0; base < nk; base += C * W) {
+    const int k0 = base + w * C;
+    uint32_t cs[C];
+    if (a.cs) {
+      const int32_t* p = a.cs + ((int64_t)f * nk + k0) * rowN + i;
 #pragma unroll
-  for (int k = 0; k < V; ++k) P[k] = 0;
-  uint32_t use_mask = 0;
+      for (int j = 0; j < C; ++j) cs[j] = (active && k0 + j < nk) ? (uint32_t)p[(int64_t)j * rowN] : 0u;
+    } else {
+      uint32_t x[C][R];
+      const int32_t* p = a.s1 + ((int64_t)f * B + (int64_t)k0 * R) * rowN + i;
+#pragma unroll
+      for (int j = 0; j < C; ++j)
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+          x[j][r] = (active && (k0 + j) * R + r < B) ? (uint32_t)p[(int64_t)(j * R + r) * rowN] : 0u;
+#pragma unroll
+      for (int j = 0; j < C; ++j) {
+        uint32_t t = 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) t += x[j][r];
+        cs[j] = t;
+      }
+    }
+#pragma unroll
+    for (int j = 1; j < C; ++j) cs[j] += cs[j - 1];
+    lds[w * 64 + lane] = cs[C - 1];
+    __syncthreads();
+    uint32_t off = carry, all = carry;
+    for (int q = 0; q < W; ++q) {
+      const uint32_t t = lds[q * 64 + lane];
+      if (q < w) off += t;
+      all += t;
+    }
+    carry = all;
+    if (active) {
+#pragma unroll
+      for (int j = 0; j < C; ++j)
+        if (k0 + j < nk) pc[(int64_t)(k0 + j + 1) * rowN] = off + cs[j];
+    }
+    __syncthreads();
+  }
+  // History blocks that stay in the window of the next call (a call shorter
+  // than the window): their suffix sums grow by the whole call, `carry`.
+  // Next-call slot s holds position s - Hc, which is old position s - Hc + B.
+  const int Hc = a.hist_cap;
+  const int from = Hc - a.hist_next_len, to = Hc - B;
   if (active) {
-    if (L >= 2) window_sum<V>(a, f, e0 - L > 0 ? e0 - L : 0, e0, i0, P);
+    for (int s = from + w; s < to; s += W) {
+      const int32_t old = a.hist_len > 0 ? a.hs[((int64_t)f * Hc + s + B) * rowN + i] : 0;
+      a.hs_next[((int64_t)f * Hc + s) * rowN + i] = (int32_t)((uint32_t)old + carry);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ combine
+
+constexpr int COMBINE_MAX_WAVES = 8;
+constexpr int COMBINE_MAX_R = 4;
+
+struct CombineShared {
+  double A[COMBINE_MAX_R][COMBINE_MAX_WAVES];
+  double Q[COMBINE_MAX_R][COMBINE_MAX_WAVES];
+  int64_t R1[COMBINE_MAX_R][COMBINE_MAX_WAVES];
+  int64_t R2[COMBINE_MAX_R][COMBINE_MAX_WAVES];
+  int32_t n[COMBINE_MAX_R][COMBINE_MAX_WAVES];
+};
+
+// HS at position y (< 0) for V inputs at i0 of channel f (0 without history).
+template <int V>
+__device__ __forceinline__ void load_hs(const PassBArgs& a, int f, int y, int i0, IVec<V>& out) {
+  const int H = a.hist_len;
+  if (y >= 0 || H == 0) { zero(out); return; }
+  if (y < -H) y = -H;
+  out.load(a.hs + ((int64_t)f * a.hist_cap + (y + a.hist_cap)) * a.n_inputs + i0);
+}
+
+// Chunk k of channel f, wavefront w of W. R blocks per chunk, V inputs per
+// lane, RI the integer type of a lane's R1/R2 sums.
+template <int V, int R, typename RI>
+__device__ __forceinline__ void combine_body(const PassBArgs& a, int k, int f, int w, int W, CombineShared& sh) {
+  static_assert(R >= 1 && R <= COMBINE_MAX_R && (R & (R - 1)) == 0, "R a power of two <= 4");
+  const int lane = threadIdx.x & 63;
+  const int N = a.n_inputs, L = a.window, H = a.hist_len, B = a.n_blocks;
+  const int b0 = k * R;
+  const int nb = B - b0 < R ? B - b0 : R;
+  const int wa = b0 - L + 1;                          // first position of block b0's window
+  const int n_groups = (N + 64 * V - 1) / (64 * V);
+  // Prefix values the window start needs (L >= 2): PC[k] - PC[kc], kc the
+  // first chunk boundary at or after max(wa, 0); positions [max(wa, 0), kc R)
+  // are edge rows, a subset of the R - 1 old rows [wa, wa + R - 1).
+  const int kc = wa <= 0 ? 0 : (wa + R - 1) / R;
+  const bool use_pc = L >= 2 && kc < k;
+  const int hn = a.hist_next_len;
+  const int tail_from = B - hn;                       // first position of the next history
+  const bool tail = L >= 2 && b0 + nb > tail_from;    // this chunk writes next-history sums
+  const int64_t rowF = (int64_t)f * B;
+
+  double accA[R], accQ[R];
+  RI acc1[R], acc2[R];
+  int cnt[R];
 #pragma unroll
-    for (int k = 0; k < V; ++k)
-      if (a.mask == nullptr || a.mask[(int64_t)f * N + i0 + k] != 0) use_mask |= 1u << k;
+  for (int j = 0; j < R; ++j) {
+    accA[j] = accQ[j] = 0.0;
+    acc1[j] = acc2[j] = 0;
+    cnt[j] = 0;
   }
 
-  for (int64_t eb = e0; eb < e1; eb += U) {
-    IVec<V> x1[U], x2[U], old[U];
+  for (int g = w; g < n_groups; g += W) {
+    const int i0 = (g * 64 + lane) * V;
+    const bool active = i0 < N;
+    IVec<V> x1[R], x2[R], old[R > 1 ? R - 1 : 1], hsv[R], pck, pcl, pct;
+    uint32_t use = 0;
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t e = eb + u;
+    for (int j = 0; j < R; ++j) { zero(x1[j]); zero(x2[j]); zero(hsv[j]); }
 #pragma unroll
-      for (int k = 0; k < V; ++k) x1[u].v[k] = x2[u].v[k] = old[u].v[k] = 0;
-      if (active && e < e1) {
-        const int64_t row = ((int64_t)f * a.n_blocks + (e - H)) * N + i0;
-        x1[u].load(a.s1 + row);
-        x2[u].load(a.s2 + row);
-        if (L >= 2 && e - L >= 0) old[u].load(seq_row(a, f, e - L) + i0);
+    for (int j = 0; j < (R > 1 ? R - 1 : 1); ++j) zero(old[j]);
+    zero(pck); zero(pcl); zero(pct);
+    if (active) {
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        if (j < nb) {
+          const int64_t row = (rowF + b0 + j) * N + i0;
+          x1[j].load(a.s1 + row);
+          x2[j].load(a.s2 + row);
+        }
+      }
+      if (L >= 2) {
+#pragma unroll
+        for (int j = 0; j < R - 1; ++j) {
+          const int y = wa + j;             // rows past the call's end are never used
+          if (y >= 0 && y < B) old[j].load(a.s1 + (rowF + y) * N + i0);
+        }
+        if (wa < 0) {
+#pragma unroll
+          for (int j = 0; j < R; ++j) load_hs<V>(a, f, wa + j, i0, hsv[j]);
+        }
+        const uint32_t* pcf = a.pc + (int64_t)f * (a.n_chunks + 1) * N + i0;
+        if ((use_pc || tail) && k > 0) pck.load(reinterpret_cast<const int32_t*>(pcf + (int64_t)k * N));
+        if (use_pc && kc > 0) pcl.load(reinterpret_cast<const int32_t*>(pcf + (int64_t)kc * N));
+        if (tail) pct.load(reinterpret_cast<const int32_t*>(pcf + (int64_t)a.n_chunks * N));
+      }
+#pragma unroll
+      for (int q = 0; q < V; ++q)
+        if (a.mask == nullptr || a.mask[(int64_t)f * N + i0 + q] != 0) use |= 1u << q;
+    }
+
+    // Window sums, block by block (uint32 arithmetic, exact below 2^31).
+    uint32_t P[V];
+    if (L >= 2) {
+      // History blocks of the old rows: differences of suffix sums.
+#pragma unroll
+      for (int j = 0; j < R - 1; ++j) {
+        if (wa + j < 0) {
+#pragma unroll
+          for (int q = 0; q < V; ++q) old[j].v[q] = hsv[j].v[q] - (wa + j + 1 < 0 ? hsv[j + 1].v[q] : 0);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < V; ++q) {
+        uint32_t s = (uint32_t)hsv[0].v[q];              // history part (0 when wa >= 0)
+        if (use_pc) s += (uint32_t)pck.v[q] - (uint32_t)pcl.v[q];
+        P[q] = s;
+      }
+      // Edge rows [max(wa, 0), kc R) are old rows 0 .. kc R - wa - 1.
+      if (wa > 0) {
+#pragma unroll
+        for (int j = 0; j < R - 1; ++j)
+          if (wa + j < kc * R && wa + j < b0) {
+#pragma unroll
+            for (int q = 0; q < V; ++q) P[q] += (uint32_t)old[j].v[q];
+          }
       }
     }
+    uint32_t pre[V];                                     // prefix of S1 before the current block
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t e = eb + u;
-      if (e >= e1) break;
-      double pa = 0.0, pq = 0.0;
-      RI r1 = 0, r2 = 0;
-      int32_t n = 0;
-      if (active) {
-        if (L >= 2) {
+    for (int q = 0; q < V; ++q) pre[q] = (uint32_t)pck.v[q];
+
 #pragma unroll
-          for (int k = 0; k < V; ++k) P[k] += x1[u].v[k] - old[u].v[k];
-          if (e >= hist_from) x1[u].store(a.hist_next + ((int64_t)f * a.hist_cap + (e - hist_from)) * N + i0);
-        } else {
+    for (int j = 0; j < R; ++j) {
+      if (j >= nb) break;
+      if (L >= 2) {
 #pragma unroll
-          for (int k = 0; k < V; ++k) P[k] = x1[u].v[k];
+        for (int q = 0; q < V; ++q) {
+          if (j > 0) P[q] -= (uint32_t)old[j - 1].v[q];
+          P[q] += (uint32_t)x1[j].v[q];
         }
-        if (a.sk_i) {
-          // Eq. originalSK for every input of this block (masked or not).
-          float ski[V];
+        if (tail && b0 + j >= tail_from && active) {
+          IVec<V> h;
 #pragma unroll
-          for (int k = 0; k < V; ++k) ski[k] = per_input_sk(x1[u].v[k], x2[u].v[k], a.block_len);
-          float* dst = a.sk_i + ((int64_t)f * a.n_blocks + (e - H)) * N + i0;
-#pragma unroll
-          for (int k = 0; k < V; ++k) dst[k] = ski[k];
+          for (int q = 0; q < V; ++q) h.v[q] = (int32_t)((uint32_t)pct.v[q] - pre[q]);
+          h.store(a.hs_next + ((int64_t)f * a.hist_cap + (b0 + j - B + a.hist_cap)) * N + i0);
         }
 #pragma unroll
-        for (int k = 0; k < V; ++k) {
-          if ((use_mask >> k & 1u) && P[k] > 0) {
-            n += 1;
-            r1 += x1[u].v[k];
-            r2 += x2[u].v[k];
-            if (L >= 1) {
-              const double rp = recip_pos((double)P[k]);
-              pa += (double)x1[u].v[k] * rp;
-              pq += (double)x2[u].v[k] * rp * rp;
-            }
+        for (int q = 0; q < V; ++q) pre[q] += (uint32_t)x1[j].v[q];
+      } else {
+#pragma unroll
+        for (int q = 0; q < V; ++q) P[q] = (uint32_t)x1[j].v[q];
+      }
+      if (a.sk_i && active) {
+        float ski[V];
+#pragma unroll
+        for (int q = 0; q < V; ++q) ski[q] = per_input_sk(x1[j].v[q], x2[j].v[q], a.block_len);
+        float* dst = a.sk_i + (rowF + b0 + j) * N + i0;
+#pragma unroll
+        for (int q = 0; q < V; ++q) dst[q] = ski[q];
+      }
+#pragma unroll
+      for (int q = 0; q < V; ++q) {
+        const bool inc = active && (use >> q & 1u) && (int32_t)P[q] > 0;
+        cnt[j] += __builtin_popcountll(__ballot(inc));
+        if (inc) {
+          acc1[j] += (RI)x1[j].v[q];
+          acc2[j] += (RI)x2[j].v[q];
+          if (L >= 1) {
+            const double rp = recip_pos((double)P[q]);
+            accA[j] += (double)x1[j].v[q] * rp;
+            accQ[j] += (double)x2[j].v[q] * rp * rp;
           }
         }
       }
-      pa = wave_sum_to_last(pa);
-      pq = wave_sum_to_last(pq);
-      r1 = wave_sum_to_last(r1);
-      r2 = wave_sum_to_last(r2);
-      n = wave_sum_to_last(n);
-      if constexpr (FIN) {
-        if (lane == 63) {
-          fin_a[pend + u][g] = pa;
-          fin_q[pend + u][g] = pq;
-          fin_r1[pend + u][g] = (int64_t)r1;
-          fin_r2[pend + u][g] = (int64_t)r2;
-          fin_n[pend + u][g] = n;
-        }
-      } else if (lane == 63) {
-        const int64_t o = ((int64_t)f * a.n_groups + g) * a.n_blocks + (e - H);
-        a.part_a[o] = pa;
-        a.part_q[o] = pq;
-        a.part_r1[o] = (int64_t)r1;
-        a.part_r2[o] = (int64_t)r2;
-        a.part_n[o] = n;
-      }
     }
-    if constexpr (FIN) {
-      const int nb = e1 - eb < U ? (int)(e1 - eb) : U;
-      pend += nb;
-      if (eb + U >= e1 || pend + U > FIN_SLOTS) {
-        // Slot j holds block e = eb + nb - pend + j. It is finished by lane
-        // j / W of wavefront j % W (W wavefronts), spreading the work; the
-        // second barrier keeps the slots until every finisher is done.
-        __syncthreads();
-        const int nw = (int)(blockDim.x >> 6);
-        const int j = (threadIdx.x & 63) * nw + (threadIdx.x >> 6);
-        if (j < pend) {
-          double A = 0.0, Bq = 0.0;
-          int64_t R1 = 0, R2 = 0;
-          int32_t nn = 0;
-          for (int gg = 0; gg < a.n_groups; ++gg) {
-            A += fin_a[j][gg];
-            Bq += fin_q[j][gg];
-            R1 += fin_r1[j][gg];
-            R2 += fin_r2[j][gg];
-            nn += fin_n[j][gg];
+  }
+
+  // Wavefront sums: (A, Bq) of each block as 2R doubles, (R1, R2) as 2R ints.
+  {
+    constexpr int NV = 2 * R;
+    double dv[NV];
+    RI iv[NV];
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      dv[2 * j] = accA[j];
+      dv[2 * j + 1] = accQ[j];
+      iv[2 * j] = acc1[j];
+      iv[2 * j + 1] = acc2[j];
+    }
+    double dout[(NV + 3) / 4];
+    RI iout[(NV + 3) / 4];
+    wave_sums<NV>(dv, dout);
+    wave_sums<NV>(iv, iout);
+    const int r = lane >> 4;
+    if ((lane & 15) == 0) {
+#pragma unroll
+      for (int q = 0; q < (NV + 3) / 4; ++q) {
+        const int val = wave_value_of_row(q, r);
+        if (val < NV) {
+          const int j = val >> 1;
+          if (val & 1) {
+            sh.Q[j][w] = dout[q];
+            sh.R2[j][w] = (int64_t)iout[q];
+          } else {
+            sh.A[j][w] = dout[q];
+            sh.R1[j][w] = (int64_t)iout[q];
           }
-          finish(a, f, (int)(eb + nb - pend + j - H), A, Bq, R1, R2, nn);
         }
-        __syncthreads();
-        pend = 0;
       }
     }
+    if (lane == 0) {
+#pragma unroll
+      for (int j = 0; j < R; ++j) sh.n[j][w] = cnt[j];
+    }
+  }
+  __syncthreads();
+  if (w == 0 && lane < nb) {
+    const int j = lane;
+    double A = 0.0, Bq = 0.0;
+    int64_t R1 = 0, R2 = 0;
+    int32_t n = 0;
+    for (int q = 0; q < W; ++q) {
+      A += sh.A[j][q];
+      Bq += sh.Q[j][q];
+      R1 += sh.R1[j][q];
+      R2 += sh.R2[j][q];
+      n += sh.n[j][q];
+    }
+    finish(a, f, b0 + j, A, Bq, R1, R2, n);
   }
 }
 
-template <int V, int U = 4, bool FIN = false>
-__device__ __forceinline__ void partial_body(const PassBArgs& a, int c, int f, int z) {
-  // S2 of one input is at most M * 128^2 = M * 2^14 (Eq. singlesums).
-  if ((int64_t)64 * V * a.block_len * 16384 < ((int64_t)1 << 31))
-    partial_body_t<V, int32_t, U, FIN>(a, c, f, z);
-  else
-    partial_body_t<V, int64_t, U, FIN>(a, c, f, z);
+// Waves of a combine workgroup for N inputs at V per lane.
+__host__ __device__ __forceinline__ int combine_waves(int n_inputs, int vec) {
+  const int g = (n_inputs + 64 * vec - 1) / (64 * vec);
+  return g < COMBINE_MAX_WAVES ? g : COMBINE_MAX_WAVES;
 }
 
-
-__device__ __forceinline__ void finalize_body(const PassBArgs& a, int64_t blk) {
-  const int64_t j = blk * 256 + threadIdx.x;
-  if (j >= (int64_t)a.n_channels * a.fin_nb) return;
-  const int f = (int)(j / a.fin_nb), b = a.fin_b0 + (int)(j % a.fin_nb);
-  double A = 0.0, Bq = 0.0;
-  int64_t R1 = 0, R2 = 0;
-  int32_t n = 0;
-  // Group order is fixed; the loads of 8 groups are issued together.
-#pragma unroll 8
-  for (int g = 0; g < a.n_groups; ++g) {
-    const int64_t o = ((int64_t)f * a.n_groups + g) * a.n_blocks + b;
-    A += a.part_a[o];
-    Bq += a.part_q[o];
-    R1 += a.part_r1[o];
-    R2 += a.part_r2[o];
-    n += a.part_n[o];
-  }
-  finish(a, f, b, A, Bq, R1, R2, n);
+// Waves of a scan workgroup for nk chunks.
+__host__ __device__ __forceinline__ int scan_waves(int n_chunks) {
+  return n_chunks < SCAN_MAX_WAVES ? (n_chunks > 0 ? n_chunks : 1) : SCAN_MAX_WAVES;
 }
 
-__device__ __forceinline__ void hist_copy_body(const PassBArgs& a, int j, int f, int z) {
-  const int i = z * 256 + threadIdx.x;
-  if (i >= a.n_inputs || j >= a.hist_next_len - a.n_blocks) return;
-  const int64_t src = (int64_t)a.hist_len + a.n_blocks - a.hist_next_len + j;   // < hist_len
-  a.hist_next[((int64_t)f * a.hist_cap + j) * a.n_inputs + i] =
-      a.hist[((int64_t)f * a.hist_cap + src) * a.n_inputs + i];
-}
-
-// The same carry with four inputs per thread (N % 4 == 0, 16-byte rows).
-__device__ __forceinline__ void hist_copy_body_v4(const PassBArgs& a, int j, int f, int z) {
-  const int i = (z * 256 + threadIdx.x) * 4;
-  if (i >= a.n_inputs || j >= a.hist_next_len - a.n_blocks) return;
-  const int64_t src = (int64_t)a.hist_len + a.n_blocks - a.hist_next_len + j;   // < hist_len
-  *reinterpret_cast<int4*>(a.hist_next + ((int64_t)f * a.hist_cap + j) * a.n_inputs + i) =
-      *reinterpret_cast<const int4*>(a.hist + ((int64_t)f * a.hist_cap + src) * a.n_inputs + i);
+// Integer type of a lane's R1/R2 sums: 32 bits while a whole wavefront's
+// S2 sums fit (64 V M 2^14 < 2^31, S2 of one input <= M 2^14), over all the
+// groups a wavefront takes.
+__host__ __device__ __forceinline__ bool combine_sums_fit_32(int n_inputs, int vec, int block_len) {
+  const int W = combine_waves(n_inputs, vec);
+  const int64_t groups = (n_inputs + 64 * vec - 1) / (64 * vec);
+  const int64_t per_wave = (groups + W - 1) / W;
+  return per_wave * 64 * vec * (int64_t)block_len * 16384 < ((int64_t)1 << 31);
 }
 
 }  // namespace sk

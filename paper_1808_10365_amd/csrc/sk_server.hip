@@ -34,6 +34,7 @@ struct Frame {
   uint64_t tag = 0;
   size_t bytes = 0;          // footprint while in flight
   uint8_t* staging = nullptr;
+  hipEvent_t ready_ev = nullptr;   // recorded on the submitter's stream: the frame is ready
   hipEvent_t done_ev = nullptr;
   sk_result res{};
 };
@@ -97,6 +98,7 @@ static void reap(sk_server_s* s) {
     s->bytes_inflight -= f->bytes;
     if (f->staging) s->staging_free.emplace(s->arrays[f->array_id].in_bytes, f->staging);
     s->event_free.push_back(f->done_ev);
+    if (f->ready_ev) s->event_free.push_back(f->ready_ev);
     s->stats.completed += 1;
     s->inflight[k] = std::move(s->inflight.back());
     s->inflight.pop_back();
@@ -123,6 +125,7 @@ static void admit(sk_server_s* s) {
     }
     hipStream_t st = s->streams[a.stream];
     int rc = SK_OK;
+    if (f->ready_ev && hipStreamWaitEvent(st, f->ready_ev, 0) != hipSuccess) rc = SK_ERR_DEVICE;
     const uint8_t* x = f->src;
     if (f->on_host) {
       auto fb = s->staging_free.find(a.in_bytes);
@@ -137,7 +140,8 @@ static void admit(sk_server_s* s) {
         ++it;
         continue;
       }
-      if (hipMemcpyAsync(f->staging, f->src, a.in_bytes, hipMemcpyHostToDevice, st) != hipSuccess) rc = SK_ERR_DEVICE;
+      if (rc == SK_OK && hipMemcpyAsync(f->staging, f->src, a.in_bytes, hipMemcpyHostToDevice, st) != hipSuccess)
+        rc = SK_ERR_DEVICE;
       x = f->staging;
     }
     if (rc == SK_OK) rc = sk_compute(a.plan, x, nullptr, &f->outs, st);
@@ -227,8 +231,19 @@ int sk_server_add_array(sk_server_t s, const sk_plan_desc* desc, int32_t* array_
   return SK_OK;
 }
 
+static hipEvent_t take_event(sk_server_s* s) {
+  if (s->event_free.empty()) {
+    hipEvent_t e;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+    return e;
+  }
+  hipEvent_t e = s->event_free.back();
+  s->event_free.pop_back();
+  return e;
+}
+
 int sk_stream_submit(sk_server_t s, int32_t array_id, const uint8_t* frame, int32_t frame_on_host,
-                     const sk_outputs* outs, uint64_t tag, sk_ticket_t* ticket) {
+                     const sk_outputs* outs, uint64_t tag, void* ready_stream, sk_ticket_t* ticket) {
   clear_error();
   if (!s || !frame || !outs || !ticket) { set_error("bad arguments"); return SK_ERR_INVALID_ARG; }
   const double t = now_s();
@@ -250,6 +265,16 @@ int sk_stream_submit(sk_server_t s, int32_t array_id, const uint8_t* frame, int3
   f->res.array_id = array_id;
   f->res.status = SK_OK;
   f->res.t_submit = t;
+  if (ready_stream) {
+    // Work already enqueued on the submitter's stream (the producer of the
+    // frame or of its output buffers) completes before the frame's work runs.
+    f->ready_ev = take_event(s);
+    if (!f->ready_ev || hipEventRecord(f->ready_ev, (hipStream_t)ready_stream) != hipSuccess) {
+      if (f->ready_ev) s->event_free.push_back(f->ready_ev);
+      set_error("event record on the ready stream failed");
+      return SK_ERR_DEVICE;
+    }
+  }
   *ticket = f->ticket;
   a.queued += 1;
   s->queue.push_back(std::move(f));
@@ -304,7 +329,10 @@ int sk_server_destroy(sk_server_t s) {
   for (auto& a : s->arrays) sk_plan_destroy(a.plan);
   for (uint8_t* p : s->staging_all) (void)hipFree(p);
   for (hipEvent_t e : s->event_free) (void)hipEventDestroy(e);
-  for (auto& f : s->inflight) if (f->done_ev) (void)hipEventDestroy(f->done_ev);
+  for (auto& f : s->inflight) {
+    if (f->done_ev) (void)hipEventDestroy(f->done_ev);
+    if (f->ready_ev) (void)hipEventDestroy(f->ready_ev);
+  }
   for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
   delete s;
   return SK_OK;

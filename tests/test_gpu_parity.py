@@ -91,18 +91,19 @@ def test_ragged_random_bytes(shape, L):
     both(x, M, L, what=f"ragged {shape}")
 
 
-@pytest.mark.parametrize("lpr", [1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1024])
-@pytest.mark.parametrize("variant", list(range(18)))
-def test_every_pass_a_tile(lpr, variant):
+PASS_A_TILES = ([(0, lpr) for lpr in (1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1024)]
+                + [(v, lpr) for v in (1, 2) for lpr in (256, 512, 1024)] + [(3, 0), (4, 0)])
+
+
+@pytest.mark.parametrize("variant,lpr", PASS_A_TILES)
+def test_every_pass_a_tile(variant, lpr):
     # M = 48 and M = 100 leave partial batches and odd row counts for every
-    # row-phase count; rows of 96 and 32 column groups leave the second and
-    # later groups of a lane (variants 4..6, 8) partly past the row's end, and
-    # the 512-group row fills them exactly at 256 lanes per row. Variants
-    # 7..11, 14, 15 (lane-replicated table) widen tiles below 256 lanes to
-    # 256; 12 and 13 clamp lanes per row to 64..512 (row phases in 512
-    # lanes). M = 100 and 48 leave packed runs shorter than 16 rows.
-    # Variant 16 sets its own lanes per row (blocks side by side); 17 uses
-    # 512 lanes and holds the sums of several blocks before storing them.
+    # row-phase count of the shared table (variant 0). The packed lane table
+    # (1, 2) takes 256..1024 lanes per row; M = 100 and 48 leave packed runs
+    # shorter than 16 rows, and the 32-group row leaves most lanes of a
+    # 256-lane row idle. Variant 3 sets its own lanes per row (blocks side by
+    # side); 4 uses 512 lanes and holds the sums of several blocks before
+    # storing them.
     rng = np.random.default_rng(lpr + 7 * variant)
     for T, F, N, M in ((96, 3, 512, 48), (200, 2, 256, 100), (64, 4, 2048, 32)):
         x = rng.integers(0, 256, size=(T, F, N), dtype=np.uint8)
@@ -115,7 +116,7 @@ def test_pass_a_persistent_grid(grid):
     rng = np.random.default_rng(grid)
     T, F, N, M = 512, 2, 1024, 64
     x = rng.integers(0, 256, size=(T, F, N), dtype=np.uint8)
-    for variant in (0, 1, 4, 6, 7, 8, 12, 13, 14, 15, 16, 17):
+    for variant in (0, 1, 2, 3, 4):
         both(x, M, 3, what=f"grid={grid} variant={variant}", lpr=64, variant=variant, grid=grid)
 
 
@@ -187,10 +188,10 @@ def test_flags_entry_point():
     assert np.array_equal(fl, ref)
 
 
-@pytest.mark.parametrize("variant", [None, 7, 14, 15, 16, 17])
+@pytest.mark.parametrize("variant", [None, 0, 1, 2, 3, 4])
 def test_largest_block_no_overflow(variant):
     # M = 131071 with every sample at power 128: S2 = M * 2^14 = 2^31 - 2^14.
-    # The packed table (14, 15) holds 16 such rows per run: 2^11 + 2^30.
+    # The packed table (1, 2) holds 16 such rows per run: 2^11 + 2^30.
     T, F, N, M = 131071 * 2, 1, 16, 131071
     x = np.zeros((T, F, N), np.uint8)
     x[:, :, 1::2] = 0xFF
@@ -207,7 +208,7 @@ def test_empty_call():
 
 # ----------------------------------------------------------------------------- stream semantics
 
-@pytest.mark.parametrize("L", [2, 5, 64])
+@pytest.mark.parametrize("L", [2, 3, 5, 17, 64])
 def test_stream_frames_equal_one_shot(L):
     # Any cut of the stream into frames gives the outputs of one long call.
     N, F, M = 48, 3, 32
@@ -324,74 +325,80 @@ def test_false_alarm_thresholds(L, est):
     assert np.array_equal(fl2[clear], f0[clear])
 
 
-@pytest.mark.parametrize("chunk,vec,depth", [(1, 4, 0), (2, 1, 0), (8, 4, 0), (64, 1, 0), (128, 4, 0), (4, 8, 0),
-                                             (16, 8, 0), (32, 8, 0), (16, 4, 2), (16, 4, 8), (8, 4, 8), (32, 4, 2)])
-@pytest.mark.parametrize("N", [96, 1040])
-def test_pass_b_tiles(chunk, vec, depth, N):
-    # Every chunk length and lane width gives the oracle's results, across
-    # calls (history) and with a window longer than the chunk; N = 1040 leaves
-    # a partial group of inputs for every lane width.
-    F, M, L = 3, 32, 9
-    T = 32 * 20
-    x = synth.generate(synth.Workload("pb", N, F, 3 * T, M, 8, np.full(N, 2.2), []), nthreads=2)
-    ref = oracle.sk(x, M, L)
-    p = sk.Plan(N, F, T, M, norm_window=L)
-    p.set_pass_b_tile(chunk, vec)
-    p.set_pass_b_depth(depth)
-    outs = [p.compute(torch.from_numpy(x[k * T:(k + 1) * T].copy()).to(DEV), want=sk.ALL_OUTPUTS)
-            for k in range(3)]
-    torch.cuda.synchronize()
-    cat = {name: torch.cat([getattr(o, name) for o in outs], dim=1) for name in sk.ALL_OUTPUTS}
-    check_result(SimpleNamespace(**cat), ref, M, L, what=f"pass B chunk={chunk} vec={vec} depth={depth} N={N}")
-    p.close()
-
-
-@pytest.mark.parametrize("K", [2, 3, 4, 7, 64])
-@pytest.mark.parametrize("L", [0, 1, 5, 40, 80])
-def test_segmented_calls(K, L):
-    # Pass B of each block segment runs on the plan's second stream while
-    # pass A streams the next segment. Every output equals the unsegmented
-    # plan's bit for bit and the oracle's to the usual bar, over three calls
-    # (L = 80 > B: the history carry runs too; K = 64 exceeds the chunk count).
-    N, F, M = 96, 3, 32
-    T = 32 * 50
-    x = synth.generate(synth.Workload("seg", N, F, 3 * T, M, 21 + L, np.full(N, 2.4), []), nthreads=2)
+@pytest.mark.parametrize("vec", [1, 4])
+@pytest.mark.parametrize("N", [96, 1040, 2112])
+@pytest.mark.parametrize("L", [0, 1, 2, 4, 5, 9, 40])
+def test_pass_b_tiles(vec, N, L):
+    # Every chunk length R gives the oracle's results and the same outputs bit
+    # for bit (the sums follow one fixed order), across calls of 3, 1, 20 and
+    # 2 blocks: the history carry, calls shorter than R and than the window,
+    # and windows shorter and longer than R. N = 1040 leaves a partial group
+    # of inputs for both lane widths; N = 2112 gives wavefronts two input
+    # groups each.
+    F, M = 3, 32
+    cuts = [3, 1, 20, 2]
+    x = synth.generate(synth.Workload("pb", N, F, sum(cuts) * M, M, 8 + L, np.full(N, 2.2), []), nthreads=2)
     ref = oracle.sk(x, M, L)
     res = {}
-    for k in (K, 1):
-        p = sk.Plan(N, F, T, M, norm_window=L)
-        p.set_segments(k)
-        outs = [p.compute(torch.from_numpy(x[c * T:(c + 1) * T].copy()).to(DEV), want=sk.ALL_OUTPUTS)
-                for c in range(3)]
-        torch.cuda.synchronize()
-        if k > 1:
-            assert 2 <= p.last_segments() <= k
-        res[k] = {name: torch.cat([getattr(o, name) for o in outs], dim=1) for name in sk.ALL_OUTPUTS}
-        p.close()
-    check_result(SimpleNamespace(**res[K]), ref, M, L, what=f"segments={K} L={L}")
+    for R in (1, 2, 4):
+        plans = {c: sk.Plan(N, F, c * M, M, norm_window=L) for c in set(cuts)}
+        for p in plans.values():
+            p.set_pass_b_tile(R, vec)
+        outs, t0, state = [], 0, None
+        for c in cuts:
+            p = plans[c]
+            if state is not None:
+                p.import_state(state)
+            outs.append(p.compute(torch.from_numpy(x[t0:t0 + c * M].copy()).to(DEV), want=sk.ALL_OUTPUTS))
+            torch.cuda.synchronize()
+            state = p.export_state()
+            t0 += c * M
+        cat = {name: torch.cat([getattr(o, name) for o in outs], dim=1) for name in sk.ALL_OUTPUTS}
+        check_result(SimpleNamespace(**cat), ref, M, L, what=f"pass B R={R} vec={vec} N={N} L={L}")
+        res[R] = cat
+        for p in plans.values():
+            p.close()
     for name in sk.ALL_OUTPUTS:
-        a, b = res[K][name].cpu().numpy(), res[1][name].cpu().numpy()
+        a, b = res[1][name].cpu().numpy(), res[4][name].cpu().numpy()
+        assert np.array_equal(a, b, equal_nan=a.dtype.kind == "f"), name
+        a = res[2][name].cpu().numpy()
         assert np.array_equal(a, b, equal_nan=a.dtype.kind == "f"), name
 
 
-@pytest.mark.parametrize("variant", [14, 15, 16, 17])
+@pytest.mark.parametrize("R", [1, 2, 4])
+@pytest.mark.parametrize("L", [2, 7, 256])
+def test_pass_b_one_plan_many_calls(R, L):
+    # One plan, five calls of 37 blocks: the device-resident history (suffix
+    # sums) carried from call to call with no export, against one long run.
+    N, F, M = 256, 2, 16
+    T = 37 * M
+    x = synth.generate(synth.Workload("mc", N, F, 5 * T, M, 40 + L, np.full(N, 2.0), []), nthreads=2)
+    ref = oracle.sk(x, M, L)
+    p = sk.Plan(N, F, T, M, norm_window=L)
+    p.set_pass_b_tile(R, 0)
+    outs = [p.compute(torch.from_numpy(x[c * T:(c + 1) * T].copy()).to(DEV), want=sk.ALL_OUTPUTS) for c in range(5)]
+    torch.cuda.synchronize()
+    cat = {name: torch.cat([getattr(o, name) for o in outs], dim=1) for name in sk.ALL_OUTPUTS}
+    check_result(SimpleNamespace(**cat), ref, M, L, what=f"many calls R={R} L={L}")
+    p.close()
+
+
+@pytest.mark.parametrize("variant", [1, 2, 3, 4])
 @pytest.mark.parametrize("Q", [2, 3, 4, 7, 64])
-@pytest.mark.parametrize("segments", [1, 3])
-def test_packed_multi_block_tasks(variant, Q, segments):
+def test_packed_multi_block_tasks(variant, Q):
     # Packed-table pass A tasks walking Q consecutive blocks: B = 37 leaves a
-    # short last task for every Q, and 3 segments cut the tasks again.
-    # Variant 16 ignores Q: its 64-group rows put 4 blocks side by side.
-    # Variant 17 takes Q in 1..4 and sizes its tasks itself otherwise.
-    rng = np.random.default_rng(Q * 10 + variant + segments)
+    # short last task for every Q. Variant 3 ignores Q: its 64-group rows put
+    # 4 blocks side by side. Variant 4 takes Q in 1..4 and sizes its tasks
+    # itself otherwise.
+    rng = np.random.default_rng(Q * 10 + variant)
     T, F, N, M = 48 * 37, 2, 512, 48
     x = rng.integers(0, 256, size=(2 * T, F, N), dtype=np.uint8)
     ref = oracle.sk(x, M, 5)
     p = sk.Plan(N, F, T, M, norm_window=5)
     p.set_pass_a_variant(variant, 0)
     p.set_pass_a_blocks(Q)
-    p.set_segments(segments)
     outs = [p.compute(torch.from_numpy(x[c * T:(c + 1) * T].copy()).to(DEV), want=sk.ALL_OUTPUTS) for c in range(2)]
     torch.cuda.synchronize()
     cat = {name: torch.cat([getattr(o, name) for o in outs], dim=1) for name in sk.ALL_OUTPUTS}
-    check_result(SimpleNamespace(**cat), ref, M, 5, what=f"packed variant={variant} Q={Q} segments={segments}")
+    check_result(SimpleNamespace(**cat), ref, M, 5, what=f"packed variant={variant} Q={Q}")
     p.close()

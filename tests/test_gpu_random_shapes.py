@@ -74,17 +74,16 @@ def test_random_shape(case):
 
 def draw_knobs(case):
     r = np.random.default_rng(77000 + case)
-    return dict(seg=int(r.choice([0, 1, 2, 3, 4])), chunk=int(r.choice([0, 1, 2, 4, 8, 16, 32, 64])),
-                vec=int(r.choice([0, 1, 4, 8])), depth=int(r.choice([0, 2, 4, 8])),
-                variant=int(r.integers(-1, 18)), lpr=int(r.choice([0, 1, 4, 16, 64, 256, 512, 1024])),
+    return dict(chunk=int(r.choice([0, 1, 2, 4])), vec=int(r.choice([0, 1, 4])),
+                variant=int(r.integers(-1, 5)), lpr=int(r.choice([0, 1, 4, 16, 64, 256, 512, 1024])),
                 grid=int(r.choice([0, 0, 64, 300])), ablocks=int(r.choice([0, 0, 2, 4])))
 
 
 @pytest.mark.parametrize("case", range(40))
 def test_random_shape_and_tuning(case):
     # The same seeded shapes with every tuning control drawn at random:
-    # block segments, pass B chunk / lane width / load depth, pass A variant,
-    # lanes per row, persistent grid and blocks per task.
+    # pass B chunk and lane width, pass A variant, lanes per row, persistent
+    # grid and blocks per task.
     c, kn = draw(case), draw_knobs(case)
     N, F, M, B, L, est, calls = c["N"], c["F"], c["M"], c["B"], c["L"], c["est"], c["calls"]
     T = M * B
@@ -97,12 +96,8 @@ def test_random_shape_and_tuning(case):
         x = synth.generate(w, nthreads=4)
     mask = (rng.random((F, N)) > 0.1).astype(np.uint8) if c["use_mask"] else None
     plan = sk.Plan(N, F, T, M, norm_window=L, estimator=est, k_sigma=5.0)
-    if kn["seg"]:
-        plan.set_segments(kn["seg"])
     if kn["chunk"] or kn["vec"]:
         plan.set_pass_b_tile(kn["chunk"], kn["vec"])
-    if kn["depth"]:
-        plan.set_pass_b_depth(kn["depth"])
     if kn["lpr"]:
         plan.set_pass_a_tile(kn["lpr"])
     if kn["variant"] >= 0 or kn["grid"]:

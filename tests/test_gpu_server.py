@@ -137,7 +137,7 @@ def test_queue_capacity_and_errors():
         assert srv.poll(t).status == 0
     with pytest.raises(sk.SKError):
         srv.poll(tickets[0])                 # already collected
-    with pytest.raises(sk.SKError):
+    with pytest.raises(ValueError):
         srv.submit(7, f, srv.alloc_outputs(aid, DEV))   # unknown array
     tiny = sk.Server(hbm_budget_bytes=1024, max_inflight=1, n_streams=1)
     tid = tiny.add_array(**kw)
