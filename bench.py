@@ -154,13 +154,15 @@ def run_split_oracle(x, M, L, delta, sig, tasks, threads):
     return time.perf_counter() - t0, out
 
 
-def cpu_baseline(x, w, L, delta, sig, sample_blocks, threads):
+def cpu_baseline(x, w, L, sample_blocks, threads):
     """The oracle as it stands, on the first blocks of every channel: once on
     one thread, and split over (channel, block range) tasks on `threads`
-    threads (the reported value)."""
+    threads (the reported value). Its flag thresholds come from the oracle's
+    own App. B model."""
     import numpy as np
     import oracle
     M = w.block_len
+    delta, sig = oracle.digitised_expectation(w.sigma, M)
     if sample_blocks <= 0:
         # ~1.2 ns per byte for the oracle on a typical host core: aim at ~15 s.
         per_block = w.n_channels * w.n_inputs * M
@@ -602,7 +604,7 @@ def main():
         res["batched"] = batched_bench(args, dev)
     if not args.no_cpu_baseline:
         print("# timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
-        res["cpu_baseline"] = cpu_baseline(x, w, L, delta, sig, args.cpu_sample_blocks, args.cpu_threads)
+        res["cpu_baseline"] = cpu_baseline(x, w, L, args.cpu_sample_blocks, args.cpu_threads)
     else:
         res["cpu_baseline"] = None
     print(json.dumps(res), flush=True)

@@ -4,7 +4,9 @@ Only the test suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package. The GPU library never imports it, and
 it imports nothing of the GPU library. The arithmetic lives in plain C
 (``sk_oracle.c``: int64 sums, FP64 everything else, sums in input order);
-this module only marshals numpy arrays into it. ``exact.py`` recomputes tiny
+this module marshals numpy arrays into it, and adds only the App. B
+threshold model's few FP64 formulas over the C code's PMF moments
+(``digitised_expectation``). ``exact.py`` recomputes tiny
 cases in exact rationals.
 
 Paper: Taylor et al., arXiv:1808.10365, Sec. 2.1-2.2.1 (estimator),
@@ -224,6 +226,41 @@ def quantised_power_moments(sigma: float, clip: int = 7) -> np.ndarray:
     m = np.empty(4)
     _load().orc_quantised_power_moments(float(sigma), int(clip), _ptr(m))
     return m
+
+
+def digitised_expectation(sigma, M: int, clip: int = 7):
+    """App. B threshold model from the exact round-and-clip PMF
+    (quantised_power_moments): (delta, sigma_V) for inputs of per-component
+    RMS sigma[i] and block length M.
+
+    With q = p / E[p] per input, kappa_i = E[q^2] (2 for chi-squared power):
+      delta = mean_i kappa_i - 2  (the offset of the mean of V from 1; App. B
+              adds it to the expectation of the thresholds);
+      sigma_V from the first-order delta method on V + 1 = K sum q^2 / (sum q)^2,
+              Var V = (M / K^2) sum_i [Var(q^2) - 4 kbar Cov(q, q^2) + 4 kbar^2 Var(q)],
+              times (K + 1) / (K - 1) as in Eq. avgSK; for chi-squared power
+              it reduces to the paper's 4/K (Eq. final).
+    Plain per-input loops in FP64."""
+    sig = np.atleast_1d(np.asarray(sigma, dtype=np.float64))
+    n = sig.size
+    k2 = np.empty(n)
+    k3 = np.empty(n)
+    k4 = np.empty(n)
+    for i in range(n):
+        m = quantised_power_moments(float(sig[i]), clip)
+        mu = m[0]
+        k2[i] = m[1] / mu ** 2
+        k3[i] = m[2] / mu ** 3
+        k4[i] = m[3] / mu ** 4
+    kbar = float(k2.mean())
+    acc = 0.0
+    for i in range(n):
+        var_q = k2[i] - 1.0
+        var_q2 = k4[i] - k2[i] ** 2
+        cov = k3[i] - k2[i]
+        acc += var_q2 - 4.0 * kbar * cov + 4.0 * kbar ** 2 * var_q
+    K = float(n * M)
+    return kbar - 2.0, (K + 1.0) / (K - 1.0) * float(np.sqrt(M / (K * K) * acc))
 
 
 def stream(frames, M: int, L: int, **kw) -> Result:

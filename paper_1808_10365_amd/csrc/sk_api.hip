@@ -43,6 +43,8 @@ struct sk_plan_s {
   int32_t* s2;
   uint32_t* pc;            // [F][ceil(B / R) + 1][N] prefix sums of pass B
   size_t pc_bytes;
+  int32_t* cs;             // [F][ceil(B / R)][N] chunk sums written by pass A (variant 4 with Q == R)
+  size_t cs_bytes;
   int32_t* hs[2];          // [F][hist_cap][N] history suffix sums, ping-pong
   int32_t cur;             // index of the live history buffer
   size_t bytes;
@@ -98,6 +100,7 @@ static void free_plan_memory(sk_plan_s* p) {
     if (p->s2) (void)hipFree(p->s2);
   }
   if (p->pc) (void)hipFree(p->pc);
+  if (p->cs) (void)hipFree(p->cs);
   if (p->hs[0]) (void)hipFree(p->hs[0]);
   if (p->hs[1]) (void)hipFree(p->hs[1]);
 }
@@ -149,6 +152,11 @@ int sk_plan_create(const sk_plan_desc* desc, sk_plan_t* out) {
   if (L >= 2) {
     p->pc_bytes = pass_b_prefix_bytes((int32_t)N, (int32_t)F, p->n_blocks, p->chunk);
     SK_ALLOC(p->pc, p->pc_bytes);
+    // Chunk sums from pass A when its tasks are the plan's pass B chunks.
+    if (p->chunk >= 2) {
+      p->cs_bytes = (size_t)F * (size_t)((p->n_blocks + p->chunk - 1) / p->chunk) * (size_t)N * sizeof(int32_t);
+      SK_ALLOC(p->cs, p->cs_bytes);
+    }
     SK_ALLOC(p->hs[0], (size_t)F * p->hist_cap * N * sizeof(int32_t));
     SK_ALLOC(p->hs[1], (size_t)F * p->hist_cap * N * sizeof(int32_t));
   }
@@ -189,6 +197,7 @@ static PassAConfig plan_pass_a_config(const sk_plan_s* p, const uint8_t* d_packe
   t->blocks_per_task = 1;
   t->block_len = p->d.block_len;
   t->n_blocks = (int32_t)B;
+  t->cs = nullptr;
   PassAConfig c = default_pass_a_config(vec, t->row_bytes, B, p->d.block_len, p->pass_a_lpr == 0 && p->pass_a_variant < 0,
                                         p->n_cu);
   if (p->pass_a_lpr) c.lpr = p->pass_a_lpr;
@@ -391,7 +400,14 @@ int sk_compute(sk_plan_t p, const uint8_t* d_packed, const uint8_t* d_mask, cons
   t.x = d_packed;
   t.s1 = cb.s1;
   t.s2 = cb.s2;
+  t.cs = nullptr;
   PassBArgs a = make_pass_b_args(p->d, B, p->hist_cap, p->chunk, p->pass_b_vec, d_mask, outs, cb, p->thresholds);
+  // Pass A tasks of Q = R consecutive blocks hand the scan its chunk sums.
+  if (a.window >= 2 && p->cs && pass_a_deferred(c.vec, c.variant) && t.blocks_per_task == a.chunk &&
+      (size_t)a.n_channels * a.n_chunks * a.n_inputs * sizeof(int32_t) <= p->cs_bytes) {
+    t.cs = p->cs;
+    a.cs = p->cs;
+  }
 
   const bool rec = p->prof_n < p->prof_max && (p->prof_calls++ % p->prof_stride) == 0;
   if (rec) SK_HIP_TRY(hipEventRecord(p->prof[3 * p->prof_n], s));

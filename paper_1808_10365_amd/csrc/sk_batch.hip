@@ -145,8 +145,8 @@ __global__ __launch_bounds__(64 * SCAN_MAX_WAVES) void batch_scan_kernel(const B
 // others take no inputs), so results equal the plan's bit for bit.
 template <int R>
 __device__ __forceinline__ void batch_combine_r(const PassBArgs& a, int k, int f, int w, int W, CombineShared& sh) {
-  if (combine_sums_fit_32(a.n_inputs, 4, a.block_len)) combine_body<4, R, int32_t>(a, k, f, w, W, sh);
-  else combine_body<4, R, int64_t>(a, k, f, w, W, sh);
+  if (combine_sums_fit_32(a.n_inputs, 4, a.block_len)) combine_body<4, R, int32_t, false>(a, k, f, w, W, sh);
+  else combine_body<4, R, int64_t, false>(a, k, f, w, W, sh);
 }
 
 __global__ __launch_bounds__(64 * COMBINE_MAX_WAVES) void batch_combine_kernel(const BatchProb* __restrict__ probs,

@@ -46,6 +46,8 @@ struct PassATask {
   int32_t block0;       // first block of this launch (tasks cover blocks block0 ..)
   int32_t block_end;    // one past the last block of this launch
   int32_t blocks_per_task;  // consecutive blocks one task walks (packed-table variants; else 1)
+  int32_t* cs;          // variant 4 only, or null: [F][ceil(B / Q)][N] S1 summed over each
+                        // task's Q blocks (the chunk sums of pass B's scan when its R == Q)
 };
 
 struct PassAConfig {

@@ -237,6 +237,24 @@ __global__ __launch_bounds__(512) void pass_a_deferred_kernel(PassATask t) {
 #pragma unroll
     for (int q = 0; q < Q; ++q)
       if (b0 + q < t.block_end) store_group<VEC>(t, b0 + q, g, a1[q], a2[q]);
+    if (t.cs) {
+      // S1 over the task's blocks: the chunk sums pass B's prefix scan reads
+      // instead of the rows (blocks past the end hold zero sums).
+      uint32_t c[VEC];
+#pragma unroll
+      for (int k = 0; k < VEC; ++k) {
+        c[k] = a1[0][k];
+#pragma unroll
+        for (int q = 1; q < Q; ++q) c[k] += a1[q][k];
+      }
+      const int N = t.n_inputs;
+      const int64_t col = (int64_t)g * VEC;
+      const int64_t f = col / N, i = col % N;
+      const int64_t nk = (t.n_blocks + Q - 1) / Q;
+      int32_t* d = t.cs + (f * nk + (b0 - t.block0) / Q) * N + i;
+#pragma unroll
+      for (int k = 0; k < VEC; k += 4) *reinterpret_cast<u32x4*>(d + k) = u32x4{c[k], c[k + 1], c[k + 2], c[k + 3]};
+    }
   }
 }
 

@@ -25,16 +25,19 @@ __global__ __launch_bounds__(64 * SCAN_MAX_WAVES) void scan_kernel(PassBArgs a) 
   scan_body<R>(a, blockIdx.y, blockIdx.x, threadIdx.x >> 6, blockDim.x >> 6, lds);
 }
 
-template <int V, int R, typename RI>
+template <int V, int R, typename RI, bool OFF32>
 __global__ __launch_bounds__(64 * COMBINE_MAX_WAVES) void combine_kernel(PassBArgs a) {
   __shared__ CombineShared sh;
-  combine_body<V, R, RI>(a, blockIdx.x, blockIdx.y, threadIdx.x >> 6, blockDim.x >> 6, sh);
+  combine_body<V, R, RI, OFF32>(a, blockIdx.x, blockIdx.y, threadIdx.x >> 6, blockDim.x >> 6, sh);
 }
 
 template <int V, int R>
 static void launch_combine_r(const PassBArgs& a, bool fit32, dim3 grid, dim3 wg, hipStream_t s) {
-  if (fit32) combine_kernel<V, R, int32_t><<<grid, wg, 0, s>>>(a);
-  else combine_kernel<V, R, int64_t><<<grid, wg, 0, s>>>(a);
+  const bool off32 = combine_offsets_fit_32(a.n_inputs, a.n_blocks, a.n_chunks, a.hist_cap);
+  if (fit32 && off32) combine_kernel<V, R, int32_t, true><<<grid, wg, 0, s>>>(a);
+  else if (fit32) combine_kernel<V, R, int32_t, false><<<grid, wg, 0, s>>>(a);
+  else if (off32) combine_kernel<V, R, int64_t, true><<<grid, wg, 0, s>>>(a);
+  else combine_kernel<V, R, int64_t, false><<<grid, wg, 0, s>>>(a);
 }
 
 template <int V>

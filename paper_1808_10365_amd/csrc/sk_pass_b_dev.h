@@ -175,9 +175,11 @@ __device__ __forceinline__ float per_input_sk(int32_t s1, int32_t s2, int32_t bl
   return (float)((Md + 1.0) / (Md - 1.0) * (Md * (double)s2 / (x * x) - 1.0));
 }
 
-// 1/p for p >= 1: the hardware reciprocal estimate refined by two Newton
-// steps (each squares the relative error), within a few ulps of the
-// correctly rounded quotient. S1/P and S2/P^2 then cost multiplies.
+// 1/p for p >= 1: the hardware reciprocal estimate (relative error about
+// 2^-24 on gfx950) refined by two Newton steps, each squaring the error, to
+// within an ulp of the correctly rounded quotient. One step would leave
+// about 2^-48, enough for the tolerance on V but not for exact results such
+// as V = 0 on constant-modulus input. S1/P and S2/P^2 then cost multiplies.
 __device__ __forceinline__ double recip_pos(double p) {
   double r = __builtin_amdgcn_rcp(p);
   double e = __builtin_fma(-p, r, 1.0);
@@ -332,20 +334,28 @@ struct CombineShared {
   int32_t n[COMBINE_MAX_R][COMBINE_MAX_WAVES];
 };
 
-// HS at position y (< 0) for V inputs at i0 of channel f (0 without history).
-template <int V>
-__device__ __forceinline__ void load_hs(const PassBArgs& a, int f, int y, int i0, IVec<V>& out) {
-  const int H = a.hist_len;
-  if (y >= 0 || H == 0) { zero(out); return; }
-  if (y < -H) y = -H;
-  out.load(a.hs + ((int64_t)f * a.hist_cap + (y + a.hist_cap)) * a.n_inputs + i0);
+// Element `e` of a per-channel array. OFF32: the offset is a 32-bit byte
+// count added to a uniform base, so each load takes one scalar base and a
+// vector offset (fewer scalar registers than a 64-bit address per row).
+template <bool OFF32>
+__device__ __forceinline__ const int32_t* elem_at(const int32_t* base, int64_t e) {
+  if constexpr (OFF32)
+    return reinterpret_cast<const int32_t*>(reinterpret_cast<const char*>(base) + (uint32_t)((uint32_t)e * 4u));
+  else
+    return base + e;
 }
 
 // Chunk k of channel f, wavefront w of W. R blocks per chunk, V inputs per
-// lane, RI the integer type of a lane's R1/R2 sums.
-template <int V, int R, typename RI>
+// lane, RI the integer type of a lane's R1/R2 sums, OFF32 when every
+// per-channel array holds fewer than 2^30 elements.
+//
+// Every lane loads: a lane past the last input reads the last group's
+// inputs (in bounds) and contributes nothing. Loads that a chunk does not
+// need are replaced by zeros in wavefront-uniform branches.
+template <int V, int R, typename RI, bool OFF32>
 __device__ __forceinline__ void combine_body(const PassBArgs& a, int k, int f, int w, int W, CombineShared& sh) {
   static_assert(R >= 1 && R <= COMBINE_MAX_R && (R & (R - 1)) == 0, "R a power of two <= 4");
+  constexpr int RO = R > 1 ? R - 1 : 1;               // old-row slots
   const int lane = threadIdx.x & 63;
   const int N = a.n_inputs, L = a.window, H = a.hist_len, B = a.n_blocks;
   const int b0 = k * R;
@@ -357,10 +367,17 @@ __device__ __forceinline__ void combine_body(const PassBArgs& a, int k, int f, i
   // are edge rows, a subset of the R - 1 old rows [wa, wa + R - 1).
   const int kc = wa <= 0 ? 0 : (wa + R - 1) / R;
   const bool use_pc = L >= 2 && kc < k;
+  const int edges = L >= 2 && wa > 0 ? (kc * R < b0 ? kc * R : b0) - wa : 0;
   const int hn = a.hist_next_len;
   const int tail_from = B - hn;                       // first position of the next history
   const bool tail = L >= 2 && b0 + nb > tail_from;    // this chunk writes next-history sums
+  const bool head = L >= 2 && wa < 0 && H > 0;        // the window reaches into the history
   const int64_t rowF = (int64_t)f * B;
+  // Channel bases (uniform).
+  const int32_t* s1c = a.s1 + rowF * N;
+  const int32_t* s2c = a.s2 + rowF * N;
+  const int32_t* pcc = reinterpret_cast<const int32_t*>(a.pc) + (int64_t)f * (a.n_chunks + 1) * N;
+  const int32_t* hsc = a.hs + (int64_t)f * a.hist_cap * N;
 
   double accA[R], accQ[R];
   RI acc1[R], acc2[R];
@@ -375,75 +392,78 @@ __device__ __forceinline__ void combine_body(const PassBArgs& a, int k, int f, i
   for (int g = w; g < n_groups; g += W) {
     const int i0 = (g * 64 + lane) * V;
     const bool active = i0 < N;
-    IVec<V> x1[R], x2[R], old[R > 1 ? R - 1 : 1], hsv[R], pck, pcl, pct;
-    uint32_t use = 0;
+    const int il = active ? i0 : N - V;               // the input this lane loads
+    IVec<V> x1[R], x2[R], old[RO], hsv[R], pck, pcl, pct;
 #pragma unroll
-    for (int j = 0; j < R; ++j) { zero(x1[j]); zero(x2[j]); zero(hsv[j]); }
-#pragma unroll
-    for (int j = 0; j < (R > 1 ? R - 1 : 1); ++j) zero(old[j]);
-    zero(pck); zero(pcl); zero(pct);
-    if (active) {
-#pragma unroll
-      for (int j = 0; j < R; ++j) {
-        if (j < nb) {
-          const int64_t row = (rowF + b0 + j) * N + i0;
-          x1[j].load(a.s1 + row);
-          x2[j].load(a.s2 + row);
-        }
+    for (int j = 0; j < R; ++j) {
+      if (j < nb) {
+        const int64_t e = (int64_t)(b0 + j) * N + il;
+        x1[j].load(elem_at<OFF32>(s1c, e));
+        x2[j].load(elem_at<OFF32>(s2c, e));
+      } else {
+        zero(x1[j]);
+        zero(x2[j]);
       }
-      if (L >= 2) {
+    }
+    if (L >= 2) {
 #pragma unroll
-        for (int j = 0; j < R - 1; ++j) {
-          const int y = wa + j;             // rows past the call's end are never used
-          if (y >= 0 && y < B) old[j].load(a.s1 + (rowF + y) * N + i0);
-        }
-        if (wa < 0) {
-#pragma unroll
-          for (int j = 0; j < R; ++j) load_hs<V>(a, f, wa + j, i0, hsv[j]);
-        }
-        const uint32_t* pcf = a.pc + (int64_t)f * (a.n_chunks + 1) * N + i0;
-        if ((use_pc || tail) && k > 0) pck.load(reinterpret_cast<const int32_t*>(pcf + (int64_t)k * N));
-        if (use_pc && kc > 0) pcl.load(reinterpret_cast<const int32_t*>(pcf + (int64_t)kc * N));
-        if (tail) pct.load(reinterpret_cast<const int32_t*>(pcf + (int64_t)a.n_chunks * N));
+      for (int j = 0; j < RO; ++j) {
+        const int y = wa + j;               // rows past the call's end are never used
+        if (R > 1 && y >= 0 && y < B) old[j].load(elem_at<OFF32>(s1c, (int64_t)y * N + il));
+        else zero(old[j]);
       }
+      if (head) {
+        // History suffix sums at positions wa .. wa + R - 1 (clamped to -H;
+        // positions >= 0 have none). Old rows in the history are differences.
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+          int y = wa + j;
+          if (y < 0) hsv[j].load(elem_at<OFF32>(hsc, (int64_t)((y < -H ? -H : y) + a.hist_cap) * N + il));
+          else zero(hsv[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < RO; ++j) {
+          if (R > 1 && wa + j < 0) {
+#pragma unroll
+            for (int q = 0; q < V; ++q) old[j].v[q] = hsv[j].v[q] - (wa + j + 1 < 0 ? hsv[j + 1].v[q] : 0);
+          }
+        }
+      } else {
+        zero(hsv[0]);
+      }
+      if ((use_pc || tail) && k > 0) pck.load(elem_at<OFF32>(pcc, (int64_t)k * N + il));
+      else zero(pck);
+      if (use_pc && kc > 0) pcl.load(elem_at<OFF32>(pcc, (int64_t)kc * N + il));
+      else zero(pcl);
+      if (tail) pct.load(elem_at<OFF32>(pcc, (int64_t)a.n_chunks * N + il));
+    }
+    uint32_t use = active ? (1u << V) - 1 : 0u;
+    if (a.mask) {
 #pragma unroll
       for (int q = 0; q < V; ++q)
-        if (a.mask == nullptr || a.mask[(int64_t)f * N + i0 + q] != 0) use |= 1u << q;
+        if (a.mask[(int64_t)f * N + il + q] == 0) use &= ~(1u << q);
     }
 
     // Window sums, block by block (uint32 arithmetic, exact below 2^31).
-    uint32_t P[V];
+    uint32_t P[V], pre[V];
     if (L >= 2) {
-      // History blocks of the old rows: differences of suffix sums.
-#pragma unroll
-      for (int j = 0; j < R - 1; ++j) {
-        if (wa + j < 0) {
-#pragma unroll
-          for (int q = 0; q < V; ++q) old[j].v[q] = hsv[j].v[q] - (wa + j + 1 < 0 ? hsv[j + 1].v[q] : 0);
-        }
-      }
 #pragma unroll
       for (int q = 0; q < V; ++q) {
-        uint32_t s = (uint32_t)hsv[0].v[q];              // history part (0 when wa >= 0)
-        if (use_pc) s += (uint32_t)pck.v[q] - (uint32_t)pcl.v[q];
-        P[q] = s;
+        P[q] = (uint32_t)hsv[0].v[q] + (use_pc ? (uint32_t)pck.v[q] - (uint32_t)pcl.v[q] : 0u);
+        pre[q] = (uint32_t)pck.v[q];                  // S1 of this call before the block
       }
-      // Edge rows [max(wa, 0), kc R) are old rows 0 .. kc R - wa - 1.
-      if (wa > 0) {
 #pragma unroll
-        for (int j = 0; j < R - 1; ++j)
-          if (wa + j < kc * R && wa + j < b0) {
+      for (int j = 0; j < RO; ++j)
+        if (j < edges) {
 #pragma unroll
-            for (int q = 0; q < V; ++q) P[q] += (uint32_t)old[j].v[q];
-          }
-      }
+          for (int q = 0; q < V; ++q) P[q] += (uint32_t)old[j].v[q];
+        }
     }
-    uint32_t pre[V];                                     // prefix of S1 before the current block
-#pragma unroll
-    for (int q = 0; q < V; ++q) pre[q] = (uint32_t)pck.v[q];
-
+    uint32_t inc[R];                                  // bit q: input q of block j is included
+    bool all_in = true;
 #pragma unroll
     for (int j = 0; j < R; ++j) {
+      inc[j] = 0;
       if (j >= nb) break;
       if (L >= 2) {
 #pragma unroll
@@ -451,11 +471,13 @@ __device__ __forceinline__ void combine_body(const PassBArgs& a, int k, int f, i
           if (j > 0) P[q] -= (uint32_t)old[j - 1].v[q];
           P[q] += (uint32_t)x1[j].v[q];
         }
-        if (tail && b0 + j >= tail_from && active) {
-          IVec<V> h;
+        if (tail && b0 + j >= tail_from) {
+          if (active) {
+            IVec<V> h;
 #pragma unroll
-          for (int q = 0; q < V; ++q) h.v[q] = (int32_t)((uint32_t)pct.v[q] - pre[q]);
-          h.store(a.hs_next + ((int64_t)f * a.hist_cap + (b0 + j - B + a.hist_cap)) * N + i0);
+            for (int q = 0; q < V; ++q) h.v[q] = (int32_t)((uint32_t)pct.v[q] - pre[q]);
+            h.store(a.hs_next + ((int64_t)f * a.hist_cap + (b0 + j - B + a.hist_cap)) * N + i0);
+          }
         }
 #pragma unroll
         for (int q = 0; q < V; ++q) pre[q] += (uint32_t)x1[j].v[q];
@@ -473,18 +495,46 @@ __device__ __forceinline__ void combine_body(const PassBArgs& a, int k, int f, i
       }
 #pragma unroll
       for (int q = 0; q < V; ++q) {
-        const bool inc = active && (use >> q & 1u) && (int32_t)P[q] > 0;
-        cnt[j] += __builtin_popcountll(__ballot(inc));
-        if (inc) {
-          acc1[j] += (RI)x1[j].v[q];
-          acc2[j] += (RI)x2[j].v[q];
-          if (L >= 1) {
-            const double rp = recip_pos((double)P[q]);
-            accA[j] += (double)x1[j].v[q] * rp;
-            accQ[j] += (double)x2[j].v[q] * rp * rp;
+        const bool in = (use >> q & 1u) && (int32_t)P[q] > 0;
+        const uint64_t bal = __ballot(in);
+        cnt[j] += __builtin_popcountll(bal);
+        all_in = all_in && bal == ~0ull;
+        inc[j] |= (uint32_t)in << q;
+      }
+      if (L >= 1) {
+        // Reciprocals now, while P holds this block's window.
+#pragma unroll
+        for (int q = 0; q < V; ++q) {
+          const double rp = recip_pos((double)P[q]);
+          if (all_in) {
+            accA[j] = __builtin_fma((double)x1[j].v[q], rp, accA[j]);
+            accQ[j] = __builtin_fma((double)x2[j].v[q] * rp, rp, accQ[j]);
+          } else {
+            const double rs = (inc[j] >> q & 1u) ? rp : 0.0;
+            accA[j] = __builtin_fma((double)x1[j].v[q], rs, accA[j]);
+            accQ[j] = __builtin_fma((double)x2[j].v[q] * rs, rs, accQ[j]);
           }
         }
       }
+    }
+    // Raw integer sums of the included inputs.
+    if (all_in) {
+#pragma unroll
+      for (int j = 0; j < R; ++j)
+#pragma unroll
+        for (int q = 0; q < V; ++q) {
+          acc1[j] += (RI)x1[j].v[q];
+          acc2[j] += (RI)x2[j].v[q];
+        }
+    } else {
+#pragma unroll
+      for (int j = 0; j < R; ++j)
+#pragma unroll
+        for (int q = 0; q < V; ++q) {
+          const bool in = inc[j] >> q & 1u;
+          acc1[j] += in ? (RI)x1[j].v[q] : (RI)0;
+          acc2[j] += in ? (RI)x2[j].v[q] : (RI)0;
+        }
     }
   }
 
@@ -552,6 +602,14 @@ __host__ __device__ __forceinline__ int combine_waves(int n_inputs, int vec) {
 // Waves of a scan workgroup for nk chunks.
 __host__ __device__ __forceinline__ int scan_waves(int n_chunks) {
   return n_chunks < SCAN_MAX_WAVES ? (n_chunks > 0 ? n_chunks : 1) : SCAN_MAX_WAVES;
+}
+
+// Whether every per-channel array of a call (S1, S2, prefix sums, history)
+// holds fewer than 2^30 elements, so 32-bit byte offsets reach all of it.
+__host__ __device__ __forceinline__ bool combine_offsets_fit_32(int n_inputs, int64_t n_blocks, int n_chunks,
+                                                                int hist_cap) {
+  const int64_t lim = (int64_t)1 << 30;
+  return n_blocks * n_inputs < lim && ((int64_t)n_chunks + 1) * n_inputs < lim && (int64_t)hist_cap * n_inputs < lim;
 }
 
 // Integer type of a lane's R1/R2 sums: 32 bits while a whole wavefront's

@@ -266,7 +266,7 @@ def test_state_reset_and_continuation():
 def _workload_parity(w, L, reps=1):
     _say(f"generate {w.name}: N={w.n_inputs} F={w.n_channels} T={w.n_samples} M={w.block_len} L={L}")
     x = synth.generate(w)
-    delta, sig = sk.digitised_expectation(w.sigma, w.block_len)
+    delta, sig = oracle.digitised_expectation(w.sigma, w.block_len)   # thresholds from the oracle's model
     plan = sk.Plan(w.n_inputs, w.n_channels, w.n_samples, w.block_len, norm_window=L, k_sigma=5.0,
                    expect_offset=delta, sigma_override=sig)
     xd = torch.from_numpy(x).to(DEV)
