@@ -120,6 +120,24 @@ int sk_plan_device_bytes(sk_plan_t plan, size_t* bytes);
 int sk_compute(sk_plan_t plan, const uint8_t* d_packed, const uint8_t* d_mask,
                const sk_outputs* outs, void* stream);
 
+/* The call of sk_compute with a fresh normaliser (no history, as on a new
+ * plan's first call) and no plan, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc. It allocates nothing. desc as for sk_plan_create;
+ * outs->s1 and outs->s2 are required (the per-input sums live in the
+ * caller's buffers); the other outputs as for sk_compute. Pass B's prefix
+ * sums use a static device array of sk_noalloc_scratch_bytes() bytes per
+ * GPU (32 MiB, held until the process ends): a call whose window (L >= 2)
+ * needs more, F (ceil(B / R) + 1) N 4 bytes with R the library's chunk
+ * length, returns SK_ERR_SHAPE. False-alarm thresholds are not available
+ * (k sigma flags). Calls that overlap on one GPU share the array and race:
+ * order them on one stream. */
+int sk_compute_noalloc(const sk_plan_desc* desc, const uint8_t* d_packed, const uint8_t* d_mask,
+                       const sk_outputs* outs, void* stream);
+
+/* Bytes of sk_compute_noalloc's static scratch on each GPU. */
+size_t sk_noalloc_scratch_bytes(void);
+
 /* Flags from precomputed values (Sec. 3.2), with the plan's k_sigma,
  * expect_offset, sigma_override, M, L and estimator: flags[j] from v[j]
  * (promoted to FP64) and n_eff[j], j < n. Device pointers. */

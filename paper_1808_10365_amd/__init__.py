@@ -91,6 +91,9 @@ def load_library():
     lib.sk_plan_device_bytes.argtypes = [VP, ctypes.POINTER(SZ)]
     lib.sk_compute.argtypes = [VP, VP, VP, ctypes.POINTER(Outputs), VP]
     lib.sk_flags.argtypes = [VP, VP, VP, VP, I64, VP]
+    lib.sk_compute_noalloc.argtypes = [ctypes.POINTER(PlanDesc), VP, VP, ctypes.POINTER(Outputs), VP]
+    lib.sk_compute_noalloc.restype = ctypes.c_int
+    lib.sk_noalloc_scratch_bytes.restype = ctypes.c_size_t
     lib.sk_state_reset.argtypes = [VP]
     lib.sk_state_size.argtypes = [VP, ctypes.POINTER(SZ)]
     lib.sk_state_export.argtypes = [VP, VP, SZ, VP]
@@ -386,6 +389,36 @@ class Plan:
     def import_state(self, blob: bytes, stream: Optional[torch.cuda.Stream] = None):
         buf = ctypes.create_string_buffer(blob, len(blob))
         _check(self._lib.sk_state_import(self.handle, buf, len(blob), _stream_handle(stream)))
+
+
+def compute_noalloc(packed: torch.Tensor, out: "Result", block_len: int, norm_window: int = 1,
+                    estimator: int = EST_HAT, k_sigma: float = 5.0, expect_offset: float = 0.0,
+                    sigma_override: float = 0.0, mask: Optional[torch.Tensor] = None,
+                    stream: Optional[torch.cuda.Stream] = None) -> "Result":
+    """One call of the whole path with a fresh normaliser and no plan, through
+    the entry point that allocates nothing (sk_compute_noalloc): ``packed`` is
+    [T][F][N] uint8 on the current device, ``out`` holds at least s1 and s2."""
+    if not isinstance(packed, torch.Tensor) or packed.dim() != 3:
+        raise ValueError("packed must be a [T][F][N] tensor")
+    T, F, N = packed.shape
+    dev = torch.cuda.current_device()
+    _device_tensor(packed, "packed", torch.uint8, (T, F, N), dev)
+    if out.s1 is None or out.s2 is None:
+        raise ValueError("compute_noalloc needs the s1 and s2 outputs")
+    if block_len < 1 or T % block_len:
+        raise ValueError(f"T = {T} is not a multiple of block_len = {block_len}")
+    if mask is not None:
+        _device_tensor(mask, "mask", torch.uint8, (F, N), dev)
+    _check_outputs(out, F, T // block_len, N, dev)
+    d = PlanDesc(N, F, T, block_len, norm_window, estimator, k_sigma, expect_offset, sigma_override)
+    o = Outputs(*[_ptr(getattr(out, k)) for k in ALL_OUTPUTS])
+    _check(load_library().sk_compute_noalloc(ctypes.byref(d), _ptr(packed), _ptr(mask), ctypes.byref(o),
+                                              _stream_handle(stream)))
+    return out
+
+
+def noalloc_scratch_bytes() -> int:
+    return int(load_library().sk_noalloc_scratch_bytes())
 
 
 class Batch:

@@ -5,6 +5,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -187,21 +189,28 @@ int sk_plan_set_pass_a_tile(sk_plan_t p, int32_t lpr) {
   return SK_OK;
 }
 
-static PassAConfig plan_pass_a_config(const sk_plan_s* p, const uint8_t* d_packed, PassATask* t) {
-  const int64_t N = p->d.n_inputs, F = p->d.n_channels, B = p->n_blocks;
+namespace {
+// Pass A tuning controls of a plan (library choices when 0 / -1).
+struct PassATuning {
+  int lpr = 0, variant = -1, blocks = 0, grid = 0, n_cu = 256;
+};
+}  // namespace
+
+static PassAConfig pass_a_config(const sk_plan_desc& d, int64_t B, const PassATuning& u, const uint8_t* d_packed,
+                                 PassATask* t) {
+  const int64_t N = d.n_inputs, F = d.n_channels;
   const int vec = pick_vec(d_packed, (int32_t)N);
   t->row_bytes = F * N;
   t->n_inputs = (int32_t)N;
   t->block0 = 0;
   t->block_end = (int32_t)B;
   t->blocks_per_task = 1;
-  t->block_len = p->d.block_len;
+  t->block_len = d.block_len;
   t->n_blocks = (int32_t)B;
   t->cs = nullptr;
-  PassAConfig c = default_pass_a_config(vec, t->row_bytes, B, p->d.block_len, p->pass_a_lpr == 0 && p->pass_a_variant < 0,
-                                        p->n_cu);
-  if (p->pass_a_lpr) c.lpr = p->pass_a_lpr;
-  if (p->pass_a_variant >= 0) c.variant = p->pass_a_variant;
+  PassAConfig c = default_pass_a_config(vec, t->row_bytes, B, d.block_len, u.lpr == 0 && u.variant < 0, u.n_cu);
+  if (u.lpr) c.lpr = u.lpr;
+  if (u.variant >= 0) c.variant = u.variant;
   {
     int lo, hi;
     pass_a_lane_range(vec, c.variant, &lo, &hi);
@@ -210,12 +219,11 @@ static PassAConfig plan_pass_a_config(const sk_plan_s* p, const uint8_t* d_packe
   }
   t->col_groups = (int32_t)(t->row_bytes / vec);
   t->chunks = (t->col_groups + c.lpr - 1) / c.lpr;
-  if (pass_a_packed(vec, c.variant) && p->pass_a_blocks > 1) t->blocks_per_task = p->pass_a_blocks;
+  if (pass_a_packed(vec, c.variant) && u.blocks > 1) t->blocks_per_task = u.blocks;
   if (pass_a_deferred(vec, c.variant)) {
     c.lpr = 512;
     t->chunks = (t->col_groups + 511) / 512;
-    t->blocks_per_task = p->pass_a_blocks >= 1 && p->pass_a_blocks <= 4
-                             ? p->pass_a_blocks : pass_a_deferred_blocks(B, t->col_groups, p->n_cu);
+    t->blocks_per_task = u.blocks >= 1 && u.blocks <= 4 ? u.blocks : pass_a_deferred_blocks(B, t->col_groups, u.n_cu);
   }
   if (pass_a_side_by_side(vec, c.variant)) {
     c.lpr = pass_a_side_by_side_lanes(t->col_groups);
@@ -224,8 +232,18 @@ static PassAConfig plan_pass_a_config(const sk_plan_s* p, const uint8_t* d_packe
   }
   t->n_tasks = ((B + t->blocks_per_task - 1) / t->blocks_per_task) * t->chunks;
   c.grid = (int)(t->n_tasks < (1 << 30) ? t->n_tasks : (1 << 30));
-  if (p->pass_a_grid > 0 && p->pass_a_grid < c.grid) c.grid = p->pass_a_grid;
+  if (u.grid > 0 && u.grid < c.grid) c.grid = u.grid;
   return c;
+}
+
+static PassAConfig plan_pass_a_config(const sk_plan_s* p, const uint8_t* d_packed, PassATask* t) {
+  PassATuning u;
+  u.lpr = p->pass_a_lpr;
+  u.variant = p->pass_a_variant;
+  u.blocks = p->pass_a_blocks;
+  u.grid = p->pass_a_grid;
+  u.n_cu = p->n_cu;
+  return pass_a_config(p->d, p->n_blocks, u, d_packed, t);
 }
 
 int sk_plan_set_pass_a_variant(sk_plan_t p, int32_t variant, int32_t grid) {
@@ -425,6 +443,94 @@ int sk_compute(sk_plan_t p, const uint8_t* d_packed, const uint8_t* d_mask, cons
     p->cur = 1 - p->cur;
   }
   return SK_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ no-allocation call
+//
+// sk_compute_noalloc's scratch: pass B's prefix sums live in this
+// file-scope device array (one copy per GPU, held until the process ends).
+// Host code never passes `scratch` itself to a kernel: its device address is
+// taken once per device with hipGetSymbolAddress and kept below.
+static constexpr size_t kNoallocScratchBytes = (size_t)32 << 20;
+static __device__ __align__(256) uint8_t scratch[kNoallocScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_ptr;   // device -> address of that device's scratch
+}  // namespace
+
+// Address of the current device's scratch (looked up on the first call on
+// each device, with that device current).
+static int noalloc_scratch(int dev, void** ptr) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it != g_scratch_ptr.end()) {
+    *ptr = it->second;
+    return SK_OK;
+  }
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p) {
+    set_error("hipGetSymbolAddress(scratch) failed on device %d: %s", dev, hipGetErrorString(e));
+    return SK_ERR_DEVICE;
+  }
+  g_scratch_ptr[dev] = p;
+  *ptr = p;
+  return SK_OK;
+}
+
+extern "C" {
+
+size_t sk_noalloc_scratch_bytes(void) { return kNoallocScratchBytes; }
+
+int sk_compute_noalloc(const sk_plan_desc* desc, const uint8_t* d_packed, const uint8_t* d_mask,
+                       const sk_outputs* outs, void* stream) {
+  clear_error();
+  int rc = validate_desc(desc);
+  if (rc) return rc;
+  if (!outs || !outs->s1 || !outs->s2) {
+    set_error("sk_compute_noalloc needs the caller's s1 and s2 output buffers");
+    return SK_ERR_INVALID_ARG;
+  }
+  const sk_plan_desc& d = *desc;
+  const int64_t B = d.n_samples / d.block_len;
+  if (B == 0) return SK_OK;
+  if (!d_packed) { set_error("NULL input"); return SK_ERR_INVALID_ARG; }
+  const int L = d.norm_window_blocks;
+  const int32_t R = pass_b_chunk(d.n_inputs, d.n_channels, B, L);
+  const size_t need = L >= 2 ? pass_b_prefix_bytes(d.n_inputs, d.n_channels, B, R) : 0;
+  if (need > kNoallocScratchBytes) {
+    set_error("call needs %zu bytes of scratch; sk_compute_noalloc holds %zu (F (ceil(B / %d) + 1) N int32)", need,
+              kNoallocScratchBytes, R);
+    return SK_ERR_SHAPE;
+  }
+  int dev = -1;
+  SK_HIP_TRY(hipGetDevice(&dev));
+  void* sp = nullptr;
+  rc = noalloc_scratch(dev, &sp);
+  if (rc) return rc;
+  PassATuning u;
+  int ncu = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0) u.n_cu = ncu;
+  hipStream_t s = (hipStream_t)stream;
+  CallBuffers cb;
+  cb.s1 = outs->s1;
+  cb.s2 = outs->s2;
+  cb.pc = (uint32_t*)sp;
+  cb.hs = nullptr;
+  cb.hs_next = nullptr;   // no state: nothing is carried to a next call
+  cb.hist_len = 0;
+  PassATask t;
+  PassAConfig c = pass_a_config(d, B, u, d_packed, &t);
+  t.x = d_packed;
+  t.s1 = cb.s1;
+  t.s2 = cb.s2;
+  PassBArgs a = make_pass_b_args(d, B, L >= 2 ? L - 1 : 0, R, 0, d_mask, outs, cb, nullptr);
+  rc = launch_pass_a(t, c, s);
+  if (rc) return rc;
+  return launch_pass_b(a, s);
 }
 
 int sk_flags(sk_plan_t p, const float* d_v, const int32_t* d_n_eff, uint8_t* d_flags, int64_t n,

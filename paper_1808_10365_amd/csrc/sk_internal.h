@@ -83,7 +83,7 @@ struct PassBArgs {
   const int32_t* s2;      // [F][B][N]
   const int32_t* cs;      // [F][n_chunks][N] S1 summed over each chunk (pass A), or null: from s1
   const int32_t* hs;      // [F][hist_cap][N] history suffix sums (slots >= hist_cap - hist_len valid)
-  int32_t* hs_next;       // [F][hist_cap][N] the same for the next call
+  int32_t* hs_next;       // [F][hist_cap][N] the same for the next call (null: not kept)
   uint32_t* pc;           // [F][n_chunks + 1][N] exclusive prefix sums of S1 at chunk boundaries
   const uint8_t* mask;    // [F][N] or null
   int64_t* r1;            // [F][B] or null

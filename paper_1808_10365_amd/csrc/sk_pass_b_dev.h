@@ -313,7 +313,7 @@ __device__ __forceinline__ void scan_body(const PassBArgs& a, int f, int slice, 
   // Next-call slot s holds position s - Hc, which is old position s - Hc + B.
   const int Hc = a.hist_cap;
   const int from = Hc - a.hist_next_len, to = Hc - B;
-  if (active) {
+  if (active && a.hs_next) {
     for (int s = from + w; s < to; s += W) {
       const int32_t old = a.hist_len > 0 ? a.hs[((int64_t)f * Hc + s + B) * rowN + i] : 0;
       a.hs_next[((int64_t)f * Hc + s) * rowN + i] = (int32_t)((uint32_t)old + carry);
@@ -370,7 +370,7 @@ __device__ __forceinline__ void combine_body(const PassBArgs& a, int k, int f, i
   const int edges = L >= 2 && wa > 0 ? (kc * R < b0 ? kc * R : b0) - wa : 0;
   const int hn = a.hist_next_len;
   const int tail_from = B - hn;                       // first position of the next history
-  const bool tail = L >= 2 && b0 + nb > tail_from;    // this chunk writes next-history sums
+  const bool tail = L >= 2 && a.hs_next && b0 + nb > tail_from;   // this chunk writes next-history sums
   const bool head = L >= 2 && wa < 0 && H > 0;        // the window reaches into the history
   const int64_t rowF = (int64_t)f * B;
   // Channel bases (uniform).
