@@ -331,7 +331,14 @@ def batched_bench(args, dev):
     print(f"# batched: {len(ws)} problems, {total / 1e9:.2f} GB generated in {time.perf_counter() - t0:.1f} s",
           file=sys.stderr, flush=True)
     with tempfile.TemporaryDirectory() as td:
+        t0 = time.perf_counter()
         batch = sk.Batch(plans, xs, autotune=True, use_graph=True, tune_cache=os.path.join(td, "tune.json"))
+        tune_s = time.perf_counter() - t0
+        picks = {}
+        for j, w in enumerate(ws):
+            t = batch.tuning(j)
+            picks[f"N={w.n_inputs} M={w.block_len} F={w.n_channels}"] = \
+                f"rows={t['rows']} blocks={t['blocks']} chunk={t['chunk']}"
         for _ in range(3):
             batch.compute()
         torch.cuda.synchronize()
@@ -354,6 +361,8 @@ def batched_bench(args, dev):
             "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
             "pass_a": {"ms": round(pa_ms, 4), "GBps": round(pa_gbs, 1), "frac": round(pa_gbs / HBM_PEAK_GBS, 4),
                        "note": "persistent pass A kernel alone, best of 3; algorithmic bytes (input + S1/S2)"},
+            "tuning": {"seconds": round(tune_s, 2), "picks": picks,
+                       "note": "batch creation with the autotuner on an empty cache (every class timed)"},
             "shapes": "N in {64,256,1024,2048}, M in {64,256,1024}, F in {1,4,8}, T = M * U{1..2^17/M}, "
                       "L = 2^16/M; one graph launch per call"}
 

@@ -5,15 +5,19 @@
  * estimator and flag parameters, Sec. 2.2.1 and Sec. 3.2) with its own input,
  * outputs and normaliser state. sk_batch_compute runs one call of every
  * problem: pass A for all problems is one persistent kernel whose workgroups
- * take tasks from a device work queue, largest problems first. A task is a
+ * take tasks from a device work queue, the tasks whose lanes walk the most
+ * rows first (a task's duration follows its rows, not its bytes). A task is a
  * block and a chunk of 256 column groups for wide rows, or 256 / L
  * consecutive blocks side by side for rows of L <= 128 column groups (L a
  * power of two); every lane sums whole rows with the lane-replicated packed
  * power table. Pass B for all problems follows in a few more kernels; the
  * whole sequence is captured once into a HIP graph, so one call is one graph
- * launch. Pass A's rows per load (8 or 16) are chosen by the library's
- * autotuner (timed trial launches of the whole batch on the device), cached
- * in a JSON file keyed by the device arch and the batch's shapes.
+ * launch. Tile choices are made per problem class (N, M, F) by the library's
+ * autotuner: the class's problems alone are launched with every candidate
+ * and timed on the device (pass A rows per load {8, 16} x consecutive blocks
+ * per task {1, 2} for wide rows, then pass B chunk length {1, 2, 4}); each
+ * candidate's time and the pick are cached in a JSON file keyed by the
+ * device arch and the class, and a class found there is not timed again.
  *
  * Requirements: every problem has N % 16 == 0 and a 16-byte aligned input.
  * Errors as in sk.h.
@@ -32,7 +36,8 @@ extern "C" {
 typedef struct sk_batch_s* sk_batch_t;
 
 typedef struct {
-  int32_t autotune;        /* 1: time the rows-per-load candidates on the device (cached); 0: 16 */
+  int32_t autotune;        /* 1: time the tile candidates of each class on the device (cached);
+                              0: 16 rows per load, 1 block per task, the plan's pass B chunk */
   int32_t use_graph;       /* 1: capture the launch sequence into a HIP graph */
   const char* tune_cache;  /* JSON tuning cache path; NULL: env SK_TUNE_CACHE, or none */
 } sk_batch_opts;
@@ -58,12 +63,18 @@ int sk_batch_state_reset(sk_batch_t batch, void* stream);
  * count of pass A. */
 int sk_batch_get_tiles(sk_batch_t batch, int32_t j, int32_t* lanes_per_row, int32_t* pass_a_grid);
 
+/* Tile choices of problem j: pass A rows per load, blocks per task, pass B
+ * chunk length, and whether they came from the tuning cache (1) or from
+ * timing or the defaults (0). */
+int sk_batch_get_tuning(sk_batch_t batch, int32_t j, int32_t* rows_per_load, int32_t* blocks_per_task,
+                        int32_t* pass_b_chunk, int32_t* from_cache);
+
 /* History length (blocks) problem j's normaliser holds on the device now.
  * Synchronises the device. */
 int sk_batch_get_state(sk_batch_t batch, int32_t j, int32_t* hist_len);
 
 /* Profiling: runs pass A of the whole batch alone (the persistent kernel,
- * with the batch's tuned rows per load) 4 times on `stream`, the first as a
+ * with the batch's tile choices) 4 times on `stream`, the first as a
  * warm-up, and returns the best time in milliseconds. Synchronises `stream`.
  * It rewrites every problem's S1/S2 from the current inputs (the values a
  * call would write) and leaves the normaliser state alone. It resets the

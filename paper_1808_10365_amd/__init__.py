@@ -112,6 +112,8 @@ def load_library():
     lib.sk_batch_state_reset.argtypes = [VP, VP]
     lib.sk_batch_get_tiles.argtypes = [VP, I32, ctypes.POINTER(I32), ctypes.POINTER(I32)]
     lib.sk_batch_time_pass_a.argtypes = [VP, VP, ctypes.POINTER(ctypes.c_float)]
+    lib.sk_batch_get_tuning.argtypes = [VP, I32, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32),
+                                        ctypes.POINTER(I32)]
     lib.sk_batch_destroy.argtypes = [VP]
     lib.sk_batch_get_state.argtypes = [VP, I32, ctypes.POINTER(I32)]
     lib.sk_read_probe.argtypes = [VP, I64, I32, VP, VP]
@@ -138,7 +140,8 @@ def load_library():
     for name in ("sk_server_create", "sk_server_add_array", "sk_stream_submit", "sk_stream_poll",
                  "sk_server_drain", "sk_server_get_stats", "sk_server_destroy"):
         getattr(lib, name).restype = ctypes.c_int
-    for name in ("sk_batch_create", "sk_batch_compute", "sk_batch_state_reset", "sk_batch_get_tiles", "sk_batch_destroy", "sk_batch_get_state", "sk_batch_time_pass_a"):
+    for name in ("sk_batch_create", "sk_batch_compute", "sk_batch_state_reset", "sk_batch_get_tiles", "sk_batch_destroy", "sk_batch_get_state", "sk_batch_time_pass_a",
+                 "sk_batch_get_tuning"):
         getattr(lib, name).restype = ctypes.c_int
     for name in ("sk_plan_create", "sk_plan_destroy", "sk_plan_device_bytes", "sk_compute", "sk_flags",
                  "sk_state_reset", "sk_state_size", "sk_state_export", "sk_state_import",
@@ -293,10 +296,10 @@ class Plan:
             _check(self._lib.sk_plan_destroy(self.handle))
             self.handle = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # At interpreter shutdown the HIP runtime may already be gone: leave
         # the memory to the process exit instead of calling into it.
-        if sys.is_finalizing():
+        if _finalizing():
             return
         try:
             self.close()
@@ -491,6 +494,13 @@ class Batch:
         _check(self._lib.sk_batch_get_tiles(self.handle, j, ctypes.byref(lpr), ctypes.byref(grid)))
         return lpr.value, grid.value
 
+    def tuning(self, j: int) -> dict:
+        """Problem j's tile choices: pass A rows per load and blocks per task,
+        pass B chunk length, and whether they came from the tuning cache."""
+        v = [ctypes.c_int32() for _ in range(4)]
+        _check(self._lib.sk_batch_get_tuning(self.handle, j, *[ctypes.byref(x) for x in v]))
+        return dict(rows=v[0].value, blocks=v[1].value, chunk=v[2].value, from_cache=bool(v[3].value))
+
     def time_pass_a(self, stream=None) -> float:
         """Best of three runs of batched pass A alone, in milliseconds (profiling)."""
         import torch
@@ -504,8 +514,8 @@ class Batch:
             _check(self._lib.sk_batch_destroy(self.handle))
             self.handle = None
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing():
             return
         try:
             self.close()
@@ -599,8 +609,8 @@ class Server:
             self.handle = None
             self._keep.clear()
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing():
             return
         try:
             self.close()

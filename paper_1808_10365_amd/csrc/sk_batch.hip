@@ -25,7 +25,8 @@ struct BatchProb {
   PassATask a;                 // pass A task geometry (x, s1, s2, shapes, chunks, n_tasks)
   int32_t lpr;                 // pass A lanes per block row (256: wide rows in chunks; else one
                                // workgroup holds 256 / lpr blocks side by side)
-  int32_t window, hist_cap, chunk, n_chunks, waves, estimator, pad;
+  int32_t rows;                // pass A rows per load, 8 or 16 (tuned per problem class)
+  int32_t window, hist_cap, chunk, n_chunks, waves, estimator;
   double k_sigma, expect_offset, sigma_override;
   uint32_t* pc;                // pass B prefix sums
   int32_t* hs[2];              // history suffix sums, ping-pong
@@ -97,8 +98,7 @@ __device__ __forceinline__ int find_prob(const BatchProb* probs, int n, int64_t 
 
 // Persistent pass A over the whole batch: every workgroup fills its table
 // once, then takes tasks from one device counter until the queue is empty
-// (every wavefront then exits).
-template <int U>
+// (every wavefront then exits). Each problem has its own rows per load.
 __global__ __launch_bounds__(256) void batch_pass_a_kernel(const BatchProb* __restrict__ probs, int n,
                                                            int64_t total, uint32_t* counter) {
   __shared__ __attribute__((aligned(16))) uint32_t lut32[LANE_LUT_DWORDS];
@@ -114,7 +114,8 @@ __global__ __launch_bounds__(256) void batch_pass_a_kernel(const BatchProb* __re
     if (task >= total) break;
     const int p = find_prob<&BatchProb::a_begin>(probs, n, task);
     const BatchProb& P = probs[p];
-    pass_a_task_side_by_side<U>(P.a, P.lpr, task - P.a_begin, lut);
+    if (P.rows == 8) pass_a_task_side_by_side<8>(P.a, P.lpr, task - P.a_begin, lut);
+    else pass_a_task_side_by_side<16>(P.a, P.lpr, task - P.a_begin, lut);
   }
 }
 
@@ -140,30 +141,37 @@ __global__ __launch_bounds__(64 * SCAN_MAX_WAVES) void batch_scan_kernel(const B
   }
 }
 
-// Combine workgroups of the whole batch: (problem, channel, chunk), 8
-// wavefronts; a problem uses as many as the single-plan kernel does (the
-// others take no inputs), so results equal the plan's bit for bit.
-template <int R>
-__device__ __forceinline__ void batch_combine_r(const PassBArgs& a, int k, int f, int w, int W, CombineShared& sh) {
-  if (combine_sums_fit_32(a.n_inputs, 4, a.block_len)) combine_body<4, R, int32_t, false>(a, k, f, w, W, sh);
-  else combine_body<4, R, int64_t, false>(a, k, f, w, W, sh);
+// Combine workgroups of the whole batch: (problem, channel, group of 8 / W
+// chunks), 8 wavefronts, W per chunk as in the single-plan kernel (so results
+// equal the plan's bit for bit); a problem of narrow rows (W < 8) puts 8 / W
+// chunks into one workgroup instead of leaving wavefronts idle.
+template <int R, bool OFF32>
+__device__ __forceinline__ void batch_combine_r(const PassBArgs& a, int k, int f, int w, int W, CombineShared& sh,
+                                                bool live) {
+  if (combine_sums_fit_32(a.n_inputs, 4, a.block_len)) combine_body<4, R, int32_t, OFF32>(a, k, f, w, W, sh, live);
+  else combine_body<4, R, int64_t, OFF32>(a, k, f, w, W, sh, live);
 }
 
+template <bool OFF32>
 __global__ __launch_bounds__(64 * COMBINE_MAX_WAVES) void batch_combine_kernel(const BatchProb* __restrict__ probs,
                                                                               const BatchState* __restrict__ st, int n) {
-  __shared__ CombineShared sh;
+  __shared__ CombineShared sh[COMBINE_MAX_WAVES];
   const int64_t task = blockIdx.x;
   const int p = find_prob<&BatchProb::cb_begin>(probs, n, task);
   const BatchProb& P = probs[p];
   const int64_t lt = task - P.cb_begin;
   if (lt >= P.cb_count) return;                       // whole workgroup
   const PassBArgs a = make_args(P, st[p]);
-  const int k = (int)(lt % a.n_chunks), f = (int)(lt / a.n_chunks);
-  const int w = threadIdx.x >> 6;
+  const int W = P.waves, cpw = COMBINE_MAX_WAVES / W;
+  const int groups = (a.n_chunks + cpw - 1) / cpw;
+  const int f = (int)(lt / groups);
+  const int w = threadIdx.x >> 6, sub = w / W;
+  const int k = (int)(lt % groups) * cpw + sub;
+  const bool live = sub < cpw && k < a.n_chunks;
   switch (a.chunk) {
-    case 1: batch_combine_r<1>(a, k, f, w, P.waves, sh); break;
-    case 2: batch_combine_r<2>(a, k, f, w, P.waves, sh); break;
-    default: batch_combine_r<4>(a, k, f, w, P.waves, sh); break;
+    case 1: batch_combine_r<1, OFF32>(a, k, f, w % W, W, sh[sub < cpw ? sub : 0], live); break;
+    case 2: batch_combine_r<2, OFF32>(a, k, f, w % W, W, sh[sub < cpw ? sub : 0], live); break;
+    default: batch_combine_r<4, OFF32>(a, k, f, w % W, W, sh[sub < cpw ? sub : 0], live); break;
   }
 }
 
@@ -237,8 +245,9 @@ struct sk_batch_s {
   uint32_t* d_counter = nullptr;
   std::vector<void*> owned;
   int64_t total_a = 0, total_sc = 0, total_cb = 0;
+  bool off32 = true;               // every problem's per-channel arrays within 32-bit offsets
   int grid_a = 0;
-  int rows_a = 16;                 // pass A rows per load (autotuned: 8 or 16)
+  std::vector<int> tuned_from_cache;   // per table position: 1 if its class's pick came from the cache
   bool use_graph = false;
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
@@ -268,50 +277,198 @@ static int batch_alloc(sk_batch_s* b, void** p, size_t bytes) {
   return SK_OK;
 }
 
+// Pass A settings of one problem: rows per load (8, 16) and, for wide rows,
+// consecutive blocks per task.
+static void set_pass_a(BatchProb& P, int rows, int q) {
+  P.rows = rows;
+  P.a.block0 = 0;
+  P.a.block_end = P.a.n_blocks;
+  P.a.blocks_per_task = P.lpr >= 256 ? q : 256 / P.lpr;
+  P.a.chunks = P.lpr >= 256 ? (P.a.col_groups + 255) / 256 : 1;
+  P.a.n_tasks = (((int64_t)P.a.n_blocks + P.a.blocks_per_task - 1) / P.a.blocks_per_task) * P.a.chunks;
+}
+
+// Pass B chunk length of one problem.
+static void set_pass_b(BatchProb& P, int R) {
+  P.chunk = R;
+  P.n_chunks = (int32_t)((P.a.n_blocks + R - 1) / R);
+}
+
+struct Layout {
+  int64_t ta = 0, tsc = 0, tcb = 0;
+  bool off32 = true;
+};
+
+// Task ranges of every kernel over a table of problems.
+static Layout layout(std::vector<BatchProb>& tab) {
+  Layout l;
+  for (BatchProb& P : tab) {
+    const int64_t F = P.a.row_bytes / P.a.n_inputs;
+    P.a_begin = l.ta;
+    l.ta += P.a.n_tasks;
+    P.sc_begin = l.tsc;
+    P.sc_count = (P.window >= 2 && P.a.n_blocks > 0) ? F * ((P.a.n_inputs + 63) / 64) : 0;
+    l.tsc += P.sc_count;
+    P.cb_begin = l.tcb;
+    const int cpw = COMBINE_MAX_WAVES / P.waves;
+    P.cb_count = F * ((P.n_chunks + cpw - 1) / cpw);
+    l.tcb += P.cb_count;
+    if (!combine_offsets_fit_32(P.a.n_inputs, P.a.n_blocks, P.n_chunks, P.hist_cap)) l.off32 = false;
+  }
+  return l;
+}
+
+static void launch_pass_a_table(const BatchProb* d_tab, int n, int64_t total, int grid, uint32_t* counter,
+                                hipStream_t s) {
+  batch_pass_a_kernel<<<dim3(grid), dim3(256), 0, s>>>(d_tab, n, total, counter);
+}
+
+static void launch_pass_b_table(const BatchProb* d_tab, const BatchState* d_st, int n, const Layout& l,
+                                hipStream_t s) {
+  if (l.tsc > 0) batch_scan_kernel<<<dim3((unsigned)l.tsc), dim3(64 * SCAN_MAX_WAVES), 0, s>>>(d_tab, d_st, n);
+  if (l.tcb > 0) {
+    if (l.off32)
+      batch_combine_kernel<true><<<dim3((unsigned)l.tcb), dim3(64 * COMBINE_MAX_WAVES), 0, s>>>(d_tab, d_st, n);
+    else
+      batch_combine_kernel<false><<<dim3((unsigned)l.tcb), dim3(64 * COMBINE_MAX_WAVES), 0, s>>>(d_tab, d_st, n);
+  }
+}
+
 static int launch_sequence(sk_batch_s* b, hipStream_t s) {
-  if (b->rows_a == 8)
-    batch_pass_a_kernel<8><<<dim3(b->grid_a), dim3(256), 0, s>>>(b->d_probs, b->n, b->total_a, b->d_counter);
-  else
-    batch_pass_a_kernel<16><<<dim3(b->grid_a), dim3(256), 0, s>>>(b->d_probs, b->n, b->total_a, b->d_counter);
+  Layout l;
+  l.ta = b->total_a;
+  l.tsc = b->total_sc;
+  l.tcb = b->total_cb;
+  l.off32 = b->off32;
+  launch_pass_a_table(b->d_probs, b->n, b->total_a, b->grid_a, b->d_counter, s);
   SK_HIP_TRY(hipGetLastError());
-  if (b->total_sc > 0) {
-    batch_scan_kernel<<<dim3((unsigned)b->total_sc), dim3(64 * SCAN_MAX_WAVES), 0, s>>>(b->d_probs, b->d_state, b->n);
-    SK_HIP_TRY(hipGetLastError());
-  }
-  if (b->total_cb > 0) {
-    batch_combine_kernel<<<dim3((unsigned)b->total_cb), dim3(64 * COMBINE_MAX_WAVES), 0, s>>>(b->d_probs, b->d_state, b->n);
-    SK_HIP_TRY(hipGetLastError());
-  }
+  launch_pass_b_table(b->d_probs, b->d_state, b->n, l, s);
+  SK_HIP_TRY(hipGetLastError());
   batch_state_kernel<<<dim3(1), dim3(256), 0, s>>>(b->d_probs, b->d_state, b->n, b->d_counter);
   SK_HIP_TRY(hipGetLastError());
   return SK_OK;
 }
 
-// Time batched pass A over the whole batch for one rows-per-load value
-// (best of three after a warm-up run). Runs before the graph is captured.
-static float time_pass_a_batch(sk_batch_s* b, int rows, hipStream_t s) {
+// Best of `reps` timed runs of `run` (after one untimed run), in ms; the
+// queue counter is cleared before every pass A run. Runs before any graph
+// capture.
+template <typename Fn>
+static float best_time(hipStream_t s, uint32_t* counter, int reps, Fn run) {
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return 1e30f;
   if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return 1e30f; }
   float best = 1e30f;
-  for (int rep = 0; rep < 4; ++rep) {
-    (void)hipMemsetAsync(b->d_counter, 0, sizeof(uint32_t), s);
+  for (int rep = 0; rep <= reps; ++rep) {
+    (void)hipMemsetAsync(counter, 0, sizeof(uint32_t), s);
     (void)hipEventRecord(e0, s);
-    if (rows == 8)
-      batch_pass_a_kernel<8><<<dim3(b->grid_a), dim3(256), 0, s>>>(b->d_probs, b->n, b->total_a, b->d_counter);
-    else
-      batch_pass_a_kernel<16><<<dim3(b->grid_a), dim3(256), 0, s>>>(b->d_probs, b->n, b->total_a, b->d_counter);
+    run();
     (void)hipEventRecord(e1, s);
     (void)hipEventSynchronize(e1);
     float ms = 0;
     (void)hipEventElapsedTime(&ms, e0, e1);
-    if (rep > 0) best = std::min(best, ms);   // first run warms up
+    if (rep > 0 && ms < best) best = ms;     // the first run warms up
   }
-  (void)hipMemsetAsync(b->d_counter, 0, sizeof(uint32_t), s);
+  (void)hipMemsetAsync(counter, 0, sizeof(uint32_t), s);
   (void)hipStreamSynchronize(s);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   return best;
+}
+
+// Pass A of the whole batch alone (profiling), best of three.
+static float time_pass_a_batch(sk_batch_s* b, hipStream_t s) {
+  return best_time(s, b->d_counter, 3,
+                   [&] { launch_pass_a_table(b->d_probs, b->n, b->total_a, b->grid_a, b->d_counter, s); });
+}
+
+// Autotuner. Problems are grouped by class (N, M, F). For each class not in
+// the cache, the class's problems alone (a sub-table) are timed with every
+// candidate: pass A rows per load {8, 16} times blocks per task {1, 2}
+// (wide rows only), then, with the best of those, pass B chunk length
+// {1, 2, 4}. Every candidate's time (ns) and the pick go into the cache, keyed
+// by the device arch and the class; a class found in the cache takes its
+// pick without timing.
+static int tune_batch(sk_batch_s* b, const std::string& path, hipStream_t s) {
+  std::map<std::string, int> cache = load_cache(path);
+  std::map<std::string, std::vector<int>> classes;
+  for (int q = 0; q < b->n; ++q) {
+    const BatchProb& P = b->host[q];
+    char key[256];
+    snprintf(key, sizeof key, "%s|batch|N=%d|M=%d|F=%d", b->arch.c_str(), P.a.n_inputs, P.a.block_len,
+             (int)(P.a.row_bytes / P.a.n_inputs));
+    classes[key].push_back(q);
+  }
+  BatchProb* d_tab = nullptr;
+  if (hipMalloc((void**)&d_tab, sizeof(BatchProb) * b->n) != hipSuccess) {
+    set_error("hipMalloc of the tuning table failed");
+    return SK_ERR_NOMEM;
+  }
+  bool dirty = false;
+  int rc = SK_OK;
+  for (auto& kv : classes) {
+    const std::string& key = kv.first;
+    const std::vector<int>& members = kv.second;
+    auto it = cache.find(key + "|pick");
+    int rows = 16, q = 1, R = 4;
+    if (it != cache.end()) {
+      rows = it->second / 100;
+      q = it->second / 10 % 10;
+      R = it->second % 10;
+      for (int m : members) b->tuned_from_cache[m] = 1;
+    } else {
+      std::vector<BatchProb> sub;
+      for (int m : members) sub.push_back(b->host[m]);
+      const bool wide = sub[0].lpr >= 256;
+      float best = 1e30f;
+      for (int rr : {8, 16}) {
+        for (int qq : {1, 2}) {
+          if (qq > 1 && !wide) continue;
+          for (BatchProb& P : sub) set_pass_a(P, rr, qq);
+          const Layout l = layout(sub);
+          if (hipMemcpy(d_tab, sub.data(), sizeof(BatchProb) * sub.size(), hipMemcpyHostToDevice) != hipSuccess) {
+            rc = SK_ERR_DEVICE;
+            break;
+          }
+          const float t = best_time(s, b->d_counter, 3, [&] {
+            launch_pass_a_table(d_tab, (int)sub.size(), l.ta, b->grid_a, b->d_counter, s);
+          });
+          char ck[320];
+          snprintf(ck, sizeof ck, "%s|A|rows=%d|blocks=%d", key.c_str(), rr, qq);
+          cache[ck] = (int)(t * 1e6f);
+          if (t < best) { best = t; rows = rr; q = qq; }
+        }
+      }
+      for (BatchProb& P : sub) set_pass_a(P, rows, q);
+      best = 1e30f;
+      for (int RR : {1, 2, 4}) {
+        for (BatchProb& P : sub) set_pass_b(P, RR);
+        const Layout l = layout(sub);
+        if (hipMemcpy(d_tab, sub.data(), sizeof(BatchProb) * sub.size(), hipMemcpyHostToDevice) != hipSuccess) {
+          rc = SK_ERR_DEVICE;
+          break;
+        }
+        const float t = best_time(s, b->d_counter, 3, [&] {
+          launch_pass_b_table(d_tab, b->d_state, (int)sub.size(), l, s);
+        });
+        char ck[320];
+        snprintf(ck, sizeof ck, "%s|B|chunk=%d", key.c_str(), RR);
+        cache[ck] = (int)(t * 1e6f);
+        if (t < best) { best = t; R = RR; }
+      }
+      cache[key + "|pick"] = rows * 100 + q * 10 + R;
+      dirty = true;
+    }
+    for (int m : members) {
+      set_pass_a(b->host[m], rows, q);
+      set_pass_b(b->host[m], R);
+    }
+    if (rc) break;
+  }
+  (void)hipFree(d_tab);
+  if (rc == SK_OK && hipGetLastError() != hipSuccess) rc = SK_ERR_DEVICE;
+  if (rc) { set_error("autotuning launch failed"); return rc; }
+  if (dirty) save_cache(path, cache);
+  return SK_OK;
 }
 
 extern "C" {
@@ -337,14 +494,12 @@ int sk_batch_create(const sk_plan_desc* descs, int32_t n, const sk_batch_opts* o
   if (hipGetDeviceProperties(&prop, b->device) != hipSuccess) { batch_free(b); set_error("device query failed"); return SK_ERR_DEVICE; }
   b->arch = prop.gcnArchName;
   int occ = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, batch_pass_a_kernel<16>, 256, 0) != hipSuccess || occ < 1) occ = 2;
-  int occ8 = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ8, batch_pass_a_kernel<8>, 256, 0) == hipSuccess && occ8 >= 1)
-    occ = std::min(occ, occ8);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, batch_pass_a_kernel, 256, 0) != hipSuccess || occ < 1) occ = 2;
   b->grid_a = occ * prop.multiProcessorCount;
   b->use_graph = !opts || opts->use_graph;
 
-  // Largest pass A tasks first (task cost ~ M rows x 4 KiB per lane group).
+  // Table order while tuning: largest problems first (the queue order is
+  // set after tuning, below).
   b->order.resize(n);
   std::iota(b->order.begin(), b->order.end(), 0);
   std::stable_sort(b->order.begin(), b->order.end(), [&](int x, int y) {
@@ -378,8 +533,8 @@ int sk_batch_create(const sk_plan_desc* descs, int32_t n, const sk_batch_opts* o
     P.k_sigma = d.k_sigma;
     P.expect_offset = d.expect_offset;
     P.sigma_override = d.sigma_override;
-    P.chunk = pass_b_chunk((int32_t)N, (int32_t)F, B, L);
-    P.n_chunks = (int32_t)((B + P.chunk - 1) / P.chunk);
+    set_pass_a(P, 16, 1);
+    set_pass_b(P, pass_b_chunk((int32_t)N, (int32_t)F, B, L));
     P.waves = combine_waves((int32_t)N, 4);
     P.mask = nullptr;
     const sk_outputs& o = outs[j];
@@ -391,7 +546,8 @@ int sk_batch_create(const sk_plan_desc* descs, int32_t n, const sk_batch_opts* o
     if (rc) break;
     if (((uintptr_t)P.a.s1 | (uintptr_t)P.a.s2) % 16) { set_error("problem %d: outputs s1/s2 must be 16-byte aligned", j); rc = SK_ERR_INVALID_ARG; break; }
     if (L >= 2) {
-      if ((rc = batch_alloc(b, &p, pass_b_prefix_bytes((int32_t)N, (int32_t)F, B, P.chunk)))) break;
+      // Prefix sums for the shortest chunk the autotuner may pick (R = 1).
+      if ((rc = batch_alloc(b, &p, pass_b_prefix_bytes((int32_t)N, (int32_t)F, B, 1)))) break;
       P.pc = (uint32_t*)p;
       if ((rc = batch_alloc(b, &p, (size_t)F * P.hist_cap * N * 4))) break;
       P.hs[0] = (int32_t*)p;
@@ -413,34 +569,6 @@ int sk_batch_create(const sk_plan_desc* descs, int32_t n, const sk_batch_opts* o
   if (hipStreamCreate(&b->cap_stream) != hipSuccess) { batch_free(b); set_error("stream create failed"); return SK_ERR_DEVICE; }
   s = b->cap_stream;
 
-  // Task ranges.
-  int64_t ta = 0, tsc = 0, tcb = 0;
-  for (int q = 0; q < n; ++q) {
-    BatchProb& P = b->host[q];
-    const int64_t F = P.a.row_bytes / P.a.n_inputs;
-    P.a.block0 = 0;
-    P.a.block_end = P.a.n_blocks;
-    P.a.blocks_per_task = P.lpr >= 256 ? 1 : 256 / P.lpr;
-    P.a.chunks = P.lpr >= 256 ? (P.a.col_groups + 255) / 256 : 1;
-    P.a.n_tasks = (((int64_t)P.a.n_blocks + P.a.blocks_per_task - 1) / P.a.blocks_per_task) * P.a.chunks;
-    P.a_begin = ta;
-    ta += P.a.n_tasks;
-    P.sc_begin = tsc;
-    P.sc_count = (P.window >= 2 && P.a.n_blocks > 0) ? F * ((P.a.n_inputs + 63) / 64) : 0;
-    tsc += P.sc_count;
-    P.cb_begin = tcb;
-    P.cb_count = F * P.n_chunks;
-    tcb += P.cb_count;
-  }
-  if (ta >= (int64_t)UINT32_MAX || tsc >= (1LL << 31) || tcb >= (1LL << 31)) {
-    batch_free(b);
-    set_error("batch too large");
-    return SK_ERR_SHAPE;
-  }
-  b->total_a = ta;
-  b->total_sc = tsc;
-  b->total_cb = tcb;
-
   void* p = nullptr;
   if ((rc = batch_alloc(b, &p, sizeof(BatchProb) * n))) { batch_free(b); return rc; }
   b->owned.pop_back();
@@ -452,6 +580,7 @@ int sk_batch_create(const sk_plan_desc* descs, int32_t n, const sk_batch_opts* o
   b->owned.pop_back();
   b->d_counter = (uint32_t*)p;
   std::vector<BatchState> st(n, BatchState{0, 0});
+  (void)layout(b->host);
   if (hipMemcpyAsync(b->d_probs, b->host.data(), sizeof(BatchProb) * n, hipMemcpyHostToDevice, s) != hipSuccess ||
       hipMemcpyAsync(b->d_state, st.data(), sizeof(BatchState) * n, hipMemcpyHostToDevice, s) != hipSuccess ||
       hipMemsetAsync(b->d_counter, 0, sizeof(uint32_t), s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
@@ -460,30 +589,60 @@ int sk_batch_create(const sk_plan_desc* descs, int32_t n, const sk_batch_opts* o
     return SK_ERR_DEVICE;
   }
 
-  // Autotune pass A rows per load over the whole batch (cached by the
-  // batch's shapes).
+  // Per-class tile choices: timed on this batch's problems, or from the
+  // cache keyed by (arch, N, M, F).
+  b->tuned_from_cache.assign(n, 0);
   const bool tune = !opts || opts->autotune;
   if (tune) {
-    const std::string path = cache_path(opts);
-    std::map<std::string, int> cache = load_cache(path);
-    uint64_t h = 1469598103934665603ull;    // FNV-1a over the shape list
+    rc = tune_batch(b, cache_path(opts), s);
+    if (rc) { batch_free(b); return rc; }
+  }
+  // Longest tasks first. A task's duration is set by the rows each lane
+  // walks one after the other (M per block, times the blocks a wide-row task
+  // walks), not by its bytes: those lead the queue and the short tasks fill
+  // in behind them, so no long task starts when the queue is nearly empty.
+  // Ties go to the larger problem.
+  {
+    auto walk = [](const BatchProb& P) {
+      return (int64_t)P.a.block_len * (P.lpr >= 256 ? P.a.blocks_per_task : 1);
+    };
+    auto bytes = [](const BatchProb& P) { return (int64_t)P.a.n_blocks * P.a.block_len * P.a.row_bytes; };
+    std::vector<int> perm(n);
+    std::iota(perm.begin(), perm.end(), 0);
+    std::stable_sort(perm.begin(), perm.end(), [&](int x, int y) {
+      const int64_t wx = walk(b->host[x]), wy = walk(b->host[y]);
+      if (wx != wy) return wx > wy;
+      return bytes(b->host[x]) > bytes(b->host[y]);
+    });
+    std::vector<BatchProb> host(n);
+    std::vector<int> order(n), cached(n);
     for (int q = 0; q < n; ++q) {
-      const sk_plan_desc& d = b->desc[b->order[q]];
-      const int64_t v[4] = {d.n_inputs, d.n_channels, d.n_samples, d.block_len};
-      for (int64_t x : v)
-        for (int k = 0; k < 8; ++k) { h ^= (uint64_t)((x >> (8 * k)) & 0xFF); h *= 1099511628211ull; }
+      host[q] = b->host[perm[q]];
+      order[q] = b->order[perm[q]];
+      cached[q] = b->tuned_from_cache[perm[q]];
     }
-    char key[256];
-    snprintf(key, sizeof key, "%s|batch_pass_a_rows|n=%d|%016llx", b->arch.c_str(), n, (unsigned long long)h);
-    auto it = cache.find(key);
-    if (it != cache.end() && (it->second == 8 || it->second == 16)) {
-      b->rows_a = it->second;
-    } else {
-      const float t8 = time_pass_a_batch(b, 8, s);
-      const float t16 = time_pass_a_batch(b, 16, s);
-      b->rows_a = t8 < t16 ? 8 : 16;
-      cache[key] = b->rows_a;
-      save_cache(path, cache);
+    b->host.swap(host);
+    b->order.swap(order);
+    b->tuned_from_cache.swap(cached);
+  }
+  {
+    const Layout l = layout(b->host);
+    // The work-queue counter runs past the last task by one claim per
+    // workgroup; it must not wrap.
+    if (l.ta + (1LL << 24) >= (int64_t)UINT32_MAX || l.tsc >= (1LL << 31) || l.tcb >= (1LL << 31)) {
+      batch_free(b);
+      set_error("batch too large");
+      return SK_ERR_SHAPE;
+    }
+    b->total_a = l.ta;
+    b->total_sc = l.tsc;
+    b->total_cb = l.tcb;
+    b->off32 = l.off32;
+    if (hipMemcpyAsync(b->d_probs, b->host.data(), sizeof(BatchProb) * n, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemsetAsync(b->d_counter, 0, sizeof(uint32_t), s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
+      batch_free(b);
+      set_error("batch table upload failed");
+      return SK_ERR_DEVICE;
     }
   }
 
@@ -538,6 +697,24 @@ int sk_batch_get_tiles(sk_batch_t b, int32_t j, int32_t* lpr, int32_t* grid) {
   return SK_OK;
 }
 
+int sk_batch_get_tuning(sk_batch_t b, int32_t j, int32_t* rows, int32_t* blocks, int32_t* chunk,
+                        int32_t* from_cache) {
+  clear_error();
+  if (!b || j < 0 || j >= b->n || !rows || !blocks || !chunk || !from_cache) {
+    set_error("bad arguments");
+    return SK_ERR_INVALID_ARG;
+  }
+  for (int q = 0; q < b->n; ++q) {
+    if (b->order[q] != j) continue;
+    const BatchProb& P = b->host[q];
+    *rows = P.rows;
+    *blocks = P.a.blocks_per_task;
+    *chunk = P.chunk;
+    *from_cache = b->tuned_from_cache.empty() ? 0 : b->tuned_from_cache[q];
+  }
+  return SK_OK;
+}
+
 int sk_batch_time_pass_a(sk_batch_t b, void* stream, float* ms) {
   clear_error();
   if (!b || !ms) { set_error("bad arguments"); return SK_ERR_INVALID_ARG; }
@@ -546,7 +723,7 @@ int sk_batch_time_pass_a(sk_batch_t b, void* stream, float* ms) {
     set_error("batch was created on device %d, current device is %d", b->device, dev);
     return SK_ERR_INVALID_ARG;
   }
-  const float t = time_pass_a_batch(b, b->rows_a, (hipStream_t)stream);
+  const float t = time_pass_a_batch(b, (hipStream_t)stream);
   SK_HIP_TRY(hipGetLastError());
   if (!(t < 1e29f)) { set_error("pass A timing failed"); return SK_ERR_DEVICE; }
   *ms = t;

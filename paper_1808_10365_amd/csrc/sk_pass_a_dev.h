@@ -171,11 +171,12 @@ __device__ __forceinline__ void sum_rows(const uint8_t* base, int64_t G, int M, 
 
 // One 256-lane task with the packed lane table (Eq. singlesums), every lane
 // summing whole rows of one (block, column group). lpb = lanes per block row:
-// 256 for wide rows (task = block group of one block and a chunk of 256
-// column groups); a power of two >= the row's column groups otherwise (task =
-// t.blocks_per_task = 256 / lpb consecutive blocks side by side, lane l on
-// block l / lpb, column group l % lpb). Needs the PassATask fields chunks,
-// blocks_per_task, block0 and block_end set to match.
+// 256 for wide rows (task = t.blocks_per_task consecutive blocks, walked one
+// after the other, of a chunk of 256 column groups); a power of two >= the
+// row's column groups otherwise (task = t.blocks_per_task = 256 / lpb
+// consecutive blocks side by side, lane l on block l / lpb, column group
+// l % lpb). Needs the PassATask fields chunks, blocks_per_task, block0 and
+// block_end set to match.
 template <int U>
 __device__ __forceinline__ void pass_a_task_side_by_side(const PassATask& t, int lpb, int64_t task,
                                                          const LanePackedLut& lut) {
@@ -183,33 +184,37 @@ __device__ __forceinline__ void pass_a_task_side_by_side(const PassATask& t, int
   const int tid = threadIdx.x;
   const int64_t bg = task / t.chunks;
   const int ch = (int)(task % t.chunks);
-  int64_t b;
+  int64_t b, b_end;
   int g;
   if (lpb >= 256) {
-    b = t.block0 + bg;
+    b = t.block0 + bg * t.blocks_per_task;
+    b_end = b + t.blocks_per_task;
     g = ch * 256 + tid;
   } else {
     b = t.block0 + bg * t.blocks_per_task + tid / lpb;
+    b_end = b + 1;
     g = tid % lpb;
   }
-  if (b >= t.block_end || g >= t.col_groups) return;
+  if (b_end > t.block_end) b_end = t.block_end;
+  if (g >= t.col_groups) return;
   const int M = t.block_len;
   const int64_t G = t.row_bytes;
-  uint32_t s1[VEC], s2[VEC];
-#pragma unroll
-  for (int k = 0; k < VEC; ++k) s1[k] = s2[k] = 0;
-  sum_rows_packed<VEC, 1, U>(t.x + b * M * G + (int64_t)g * VEC, G, M, 0, lut, s1, s2);
   const int N = t.n_inputs, B = t.n_blocks;
   const int64_t col = (int64_t)g * VEC;
   const int64_t f = col / N, i = col % N;
-  int32_t* d1 = t.s1 + (f * B + b) * N + i;
-  int32_t* d2 = t.s2 + (f * B + b) * N + i;
+  for (; b < b_end; ++b) {
+    uint32_t s1[VEC], s2[VEC];
 #pragma unroll
-  for (int k = 0; k < VEC; k += 4) {
-    *reinterpret_cast<u32x4*>(d1 + k) = u32x4{s1[k], s1[k + 1], s1[k + 2], s1[k + 3]};
-    *reinterpret_cast<u32x4*>(d2 + k) = u32x4{s2[k], s2[k + 1], s2[k + 2], s2[k + 3]};
+    for (int k = 0; k < VEC; ++k) s1[k] = s2[k] = 0;
+    sum_rows_packed<VEC, 1, U>(t.x + b * M * G + (int64_t)g * VEC, G, M, 0, lut, s1, s2);
+    int32_t* d1 = t.s1 + (f * B + b) * N + i;
+    int32_t* d2 = t.s2 + (f * B + b) * N + i;
+#pragma unroll
+    for (int k = 0; k < VEC; k += 4) {
+      *reinterpret_cast<u32x4*>(d1 + k) = u32x4{s1[k], s1[k + 1], s1[k + 2], s1[k + 3]};
+      *reinterpret_cast<u32x4*>(d2 + k) = u32x4{s2[k], s2[k + 1], s2[k + 2], s2[k + 3]};
+    }
   }
 }
-
 
 }  // namespace sk

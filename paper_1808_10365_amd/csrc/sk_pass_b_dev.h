@@ -353,8 +353,14 @@ __device__ __forceinline__ const int32_t* elem_at(const int32_t* base, int64_t e
 // inputs (in bounds) and contributes nothing. Loads that a chunk does not
 // need are replaced by zeros in wavefront-uniform branches.
 template <int V, int R, typename RI, bool OFF32>
-__device__ __forceinline__ void combine_body(const PassBArgs& a, int k, int f, int w, int W, CombineShared& sh) {
+__device__ __forceinline__ void combine_body(const PassBArgs& a, int k, int f, int w, int W, CombineShared& sh,
+                                             bool live = true) {
   static_assert(R >= 1 && R <= COMBINE_MAX_R && (R & (R - 1)) == 0, "R a power of two <= 4");
+  if (!live) {
+    // A wavefront group with no chunk: meet the workgroup's one barrier.
+    __syncthreads();
+    return;
+  }
   constexpr int RO = R > 1 ? R - 1 : 1;               // old-row slots
   const int lane = threadIdx.x & 63;
   const int N = a.n_inputs, L = a.window, H = a.hist_len, B = a.n_blocks;

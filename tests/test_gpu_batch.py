@@ -88,18 +88,48 @@ def test_batch_two_calls_match_oracle_and_plans(graph, autotune, tmp_path):
 
 
 def test_batch_tiles_and_cache(tmp_path):
+    # The autotuner times every candidate of each (N, M, F) class, records the
+    # times and the pick in the cache, and the pick is the fastest recorded
+    # candidate; a second batch of the same classes takes the picks from the
+    # cache without timing.
+    import json
     probs = _problems(5, 4)
+    probs.append((probs[0][0], dict(probs[0][1])))         # two problems of one class
     xs = [torch.from_numpy(synth.generate(w, nthreads=2)[:kw["n_samples"]].copy()).to(DEV) for w, kw in probs]
     cache = tmp_path / "tune.json"
     b1 = sk.Batch([kw for _, kw in probs], xs, autotune=True, tune_cache=str(cache))
     tiles = [b1.tiles(j) for j in range(len(probs))]
-    assert cache.exists() and cache.read_text().count("batch_pass_a_rows") == 1
+    tun1 = [b1.tuning(j) for j in range(len(probs))]
+    print("tuning:", tun1, flush=True)
+    assert not any(t["from_cache"] for t in tun1)
+    assert tun1[0] == tun1[-1]
+    c = json.loads(cache.read_text())
+    classes = {(kw["n_inputs"], kw["block_len"], kw["n_channels"]) for _, kw in probs}
+    picks = [k for k in c if k.endswith("|pick")]
+    assert len(picks) == len(classes)
+    for j, (_, kw) in enumerate(probs):
+        key = next(k for k in picks if f"|N={kw['n_inputs']}|M={kw['block_len']}|F={kw['n_channels']}|" in k)
+        cls = key[:-len("|pick")]
+        a_times = {k: v for k, v in c.items() if k.startswith(cls + "|A|")}
+        b_times = {k: v for k, v in c.items() if k.startswith(cls + "|B|")}
+        wide = kw["n_inputs"] * kw["n_channels"] // 16 >= 256
+        assert len(a_times) == (4 if wide else 2) and len(b_times) == 3
+        t = tun1[j]
+        assert c[key] == t["rows"] * 100 + (t["blocks"] if wide else 1) * 10 + t["chunk"]
+        assert a_times[f"{cls}|A|rows={t['rows']}|blocks={t['blocks'] if wide else 1}"] == min(a_times.values())
+        assert b_times[f"{cls}|B|chunk={t['chunk']}"] == min(b_times.values())
+    b1.close()
     b2 = sk.Batch([kw for _, kw in probs], xs, autotune=True, tune_cache=str(cache))
+    tun2 = [b2.tuning(j) for j in range(len(probs))]
+    assert all(t["from_cache"] for t in tun2)
+    assert [{k: v for k, v in t.items() if k != "from_cache"} for t in tun2] == \
+        [{k: v for k, v in t.items() if k != "from_cache"} for t in tun1]
     assert [b2.tiles(j) for j in range(len(probs))] == tiles
     for (lpr, grid), (_, kw) in zip(tiles, probs):
         groups = kw["n_inputs"] * kw["n_channels"] // 16
         want = 256 if groups >= 256 else 1 << max(0, (groups - 1).bit_length())
         assert lpr == want and grid > 0
+    b2.close()
 
 
 def test_batch_wide_and_narrow_rows(tmp_path):
