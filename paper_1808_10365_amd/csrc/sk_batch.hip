@@ -26,7 +26,10 @@ struct BatchProb {
   int32_t lpr;                 // pass A lanes per block row (256: wide rows in chunks; else one
                                // workgroup holds 256 / lpr blocks side by side)
   int32_t rows;                // pass A rows per load, 8 or 16 (tuned per problem class)
-  int32_t window, hist_cap, chunk, n_chunks, waves, estimator;
+  int32_t window, hist_cap, chunk, n_chunks, estimator;
+  int32_t waves;               // combine waves per chunk (inputs / 256, at most 8)
+  int32_t scan_waves;          // scan waves per 64-input slice (power of two, at most 16)
+  int32_t wide_sums;           // 1: the combine's R1/R2 sums need 64 bits
   double k_sigma, expect_offset, sigma_override;
   uint32_t* pc;                // pass B prefix sums
   int32_t* hs[2];              // history suffix sums, ping-pong
@@ -39,7 +42,8 @@ struct BatchProb {
   float* sk_i;
   float* significance;
   // Task ranges of each kernel over the whole batch: pass A tasks, scan
-  // workgroups (channel, 64-input slice), combine workgroups (channel, chunk).
+  // workgroups (channel, group of 64-input slices), combine workgroups
+  // (channel, group of chunks; counted within the problem's combine class).
   int64_t a_begin, sc_begin, sc_count, cb_begin, cb_count;
 };
 
@@ -119,9 +123,11 @@ __global__ __launch_bounds__(256) void batch_pass_a_kernel(const BatchProb* __re
   }
 }
 
-// Scan workgroups of the whole batch: (problem, channel, 64-input slice),
-// 16 wavefronts each (the prefix sums are exact integers, so they do not
-// depend on how the chunks are spread over the wavefronts).
+// Scan workgroups of the whole batch: (problem, channel, group of 64-input
+// slices), 16 wavefronts, Ws per slice (the problem's scan_waves) and 16 / Ws
+// slices per workgroup. The chunk length is read at run time
+// (scan_body_rows); the prefix sums are exact integers, so they equal the
+// single-plan kernel's.
 __global__ __launch_bounds__(64 * SCAN_MAX_WAVES) void batch_scan_kernel(const BatchProb* __restrict__ probs,
                                                                         const BatchState* __restrict__ st, int n) {
   __shared__ uint32_t lds[SCAN_MAX_WAVES * 64];
@@ -131,33 +137,34 @@ __global__ __launch_bounds__(64 * SCAN_MAX_WAVES) void batch_scan_kernel(const B
   const int64_t lt = task - P.sc_begin;
   if (lt >= P.sc_count) return;                       // whole workgroup
   const PassBArgs a = make_args(P, st[p]);
+  const int Ws = P.scan_waves, spw = SCAN_MAX_WAVES / Ws;
   const int slices = (a.n_inputs + 63) / 64;
-  const int f = (int)(lt / slices), slice = (int)(lt % slices);
-  const int w = threadIdx.x >> 6, W = blockDim.x >> 6;
-  switch (a.chunk) {
-    case 1: scan_body<1>(a, f, slice, w, W, lds); break;
-    case 2: scan_body<2>(a, f, slice, w, W, lds); break;
-    default: scan_body<4>(a, f, slice, w, W, lds); break;
-  }
+  const int groups = (slices + spw - 1) / spw;
+  const int f = (int)(lt / groups);
+  const int w = threadIdx.x >> 6, sub = w / Ws;
+  const int slice = (int)(lt % groups) * spw + sub;   // >= slices: every lane idle, barriers kept
+  scan_body_rows(a, f, slice, w % Ws, Ws, lds + sub * Ws * 64);
 }
 
-// Combine workgroups of the whole batch: (problem, channel, group of 8 / W
-// chunks), 8 wavefronts, W per chunk as in the single-plan kernel (so results
-// equal the plan's bit for bit); a problem of narrow rows (W < 8) puts 8 / W
-// chunks into one workgroup instead of leaving wavefronts idle.
-template <int R, bool OFF32>
-__device__ __forceinline__ void batch_combine_r(const PassBArgs& a, int k, int f, int w, int W, CombineShared& sh,
-                                                bool live) {
-  if (combine_sums_fit_32(a.n_inputs, 4, a.block_len)) combine_body<4, R, int32_t, OFF32>(a, k, f, w, W, sh, live);
-  else combine_body<4, R, int64_t, OFF32>(a, k, f, w, W, sh, live);
-}
-
-template <bool OFF32>
-__global__ __launch_bounds__(64 * COMBINE_MAX_WAVES) void batch_combine_kernel(const BatchProb* __restrict__ probs,
-                                                                              const BatchState* __restrict__ st, int n) {
+// Combine workgroups of one class of problems (chunk length R, 32- or 64-bit
+// R1/R2 sums):
+// (problem, channel, group of 8 / W chunks), 8 wavefronts, W per chunk as in
+// the single-plan kernel (so results equal the plan's bit for bit); a problem
+// of narrow rows (W < 8) puts 8 / W chunks into one workgroup instead of
+// leaving wavefronts idle. members[0 .. count) are the class's table
+// positions, begins[] their first workgroups.
+template <int R, typename RI, bool OFF32>
+__global__ __launch_bounds__(64 * COMBINE_MAX_WAVES) void batch_combine_kernel(
+    const BatchProb* __restrict__ probs, const BatchState* __restrict__ st, const int32_t* __restrict__ members,
+    const int64_t* __restrict__ begins, int count) {
   __shared__ CombineShared sh[COMBINE_MAX_WAVES];
   const int64_t task = blockIdx.x;
-  const int p = find_prob<&BatchProb::cb_begin>(probs, n, task);
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (begins[mid] <= task) lo = mid; else hi = mid - 1;
+  }
+  const int p = members[lo];
   const BatchProb& P = probs[p];
   const int64_t lt = task - P.cb_begin;
   if (lt >= P.cb_count) return;                       // whole workgroup
@@ -168,11 +175,7 @@ __global__ __launch_bounds__(64 * COMBINE_MAX_WAVES) void batch_combine_kernel(c
   const int w = threadIdx.x >> 6, sub = w / W;
   const int k = (int)(lt % groups) * cpw + sub;
   const bool live = sub < cpw && k < a.n_chunks;
-  switch (a.chunk) {
-    case 1: batch_combine_r<1, OFF32>(a, k, f, w % W, W, sh[sub < cpw ? sub : 0], live); break;
-    case 2: batch_combine_r<2, OFF32>(a, k, f, w % W, W, sh[sub < cpw ? sub : 0], live); break;
-    default: batch_combine_r<4, OFF32>(a, k, f, w % W, W, sh[sub < cpw ? sub : 0], live); break;
-  }
+  combine_body<4, R, RI, OFF32>(a, k, f, w % W, W, sh[sub < cpw ? sub : 0], live);
 }
 
 // Last node: advance every problem's history and rearm the work queue.
@@ -233,6 +236,24 @@ void save_cache(const std::string& path, const std::map<std::string, int>& m) {
 
 }  // namespace
 
+// Task ranges of every kernel over a table of problems. Combine classes:
+// chunk length R in {1, 2, 4} (class R / 2 = 0, 1, 2) plus 3 when the R1/R2
+// sums need 64 bits.
+constexpr int N_COMBINE_CLASSES = 6;
+
+__host__ __device__ __forceinline__ int combine_class(int chunk, int wide_sums) {
+  return (chunk == 1 ? 0 : chunk == 2 ? 1 : 2) + 3 * wide_sums;
+}
+
+struct Layout {
+  int64_t ta = 0, tsc = 0;
+  int64_t tcb[N_COMBINE_CLASSES] = {};
+  int cls_off[N_COMBINE_CLASSES] = {}, cls_cnt[N_COMBINE_CLASSES] = {};
+  std::vector<int32_t> members;
+  std::vector<int64_t> begins;
+  bool off32 = true;
+};
+
 struct sk_batch_s {
   int n = 0;
   int device = 0;
@@ -243,10 +264,11 @@ struct sk_batch_s {
   BatchProb* d_probs = nullptr;
   BatchState* d_state = nullptr;
   uint32_t* d_counter = nullptr;
+  int32_t* d_members = nullptr;    // combine classes: table positions, class by class
+  int64_t* d_begins = nullptr;     // and their first combine workgroups
   std::vector<void*> owned;
-  int64_t total_a = 0, total_sc = 0, total_cb = 0;
-  bool off32 = true;               // every problem's per-channel arrays within 32-bit offsets
   int grid_a = 0;
+  Layout lay;                      // task ranges of the table as it is on the device
   std::vector<int> tuned_from_cache;   // per table position: 1 if its class's pick came from the cache
   bool use_graph = false;
   hipStream_t cap_stream = nullptr;
@@ -262,6 +284,8 @@ static void batch_free(sk_batch_s* b) {
   if (b->d_probs) (void)hipFree(b->d_probs);
   if (b->d_state) (void)hipFree(b->d_state);
   if (b->d_counter) (void)hipFree(b->d_counter);
+  if (b->d_members) (void)hipFree(b->d_members);
+  if (b->d_begins) (void)hipFree(b->d_begins);
   delete b;
 }
 
@@ -294,12 +318,6 @@ static void set_pass_b(BatchProb& P, int R) {
   P.n_chunks = (int32_t)((P.a.n_blocks + R - 1) / R);
 }
 
-struct Layout {
-  int64_t ta = 0, tsc = 0, tcb = 0;
-  bool off32 = true;
-};
-
-// Task ranges of every kernel over a table of problems.
 static Layout layout(std::vector<BatchProb>& tab) {
   Layout l;
   for (BatchProb& P : tab) {
@@ -307,15 +325,45 @@ static Layout layout(std::vector<BatchProb>& tab) {
     P.a_begin = l.ta;
     l.ta += P.a.n_tasks;
     P.sc_begin = l.tsc;
-    P.sc_count = (P.window >= 2 && P.a.n_blocks > 0) ? F * ((P.a.n_inputs + 63) / 64) : 0;
+    const int slices = (P.a.n_inputs + 63) / 64, spw = SCAN_MAX_WAVES / P.scan_waves;
+    P.sc_count = (P.window >= 2 && P.a.n_blocks > 0) ? F * ((slices + spw - 1) / spw) : 0;
     l.tsc += P.sc_count;
-    P.cb_begin = l.tcb;
-    const int cpw = COMBINE_MAX_WAVES / P.waves;
-    P.cb_count = F * ((P.n_chunks + cpw - 1) / cpw);
-    l.tcb += P.cb_count;
     if (!combine_offsets_fit_32(P.a.n_inputs, P.a.n_blocks, P.n_chunks, P.hist_cap)) l.off32 = false;
   }
+  for (int c = 0; c < N_COMBINE_CLASSES; ++c) {
+    l.cls_off[c] = (int)l.members.size();
+    for (size_t q = 0; q < tab.size(); ++q) {
+      BatchProb& P = tab[q];
+      if (combine_class(P.chunk, P.wide_sums) != c) continue;
+      const int64_t F = P.a.row_bytes / P.a.n_inputs;
+      const int cpw = COMBINE_MAX_WAVES / P.waves;
+      P.cb_begin = l.tcb[c];
+      P.cb_count = F * ((P.n_chunks + cpw - 1) / cpw);
+      l.tcb[c] += P.cb_count;
+      l.members.push_back((int32_t)q);
+      l.begins.push_back(P.cb_begin);
+    }
+    l.cls_cnt[c] = (int)l.members.size() - l.cls_off[c];
+  }
   return l;
+}
+
+// Device copies of a table and its combine class lists (capacity n).
+struct DeviceTable {
+  BatchProb* probs;
+  int32_t* members;
+  int64_t* begins;
+};
+
+static hipError_t upload_table(const DeviceTable& d, const std::vector<BatchProb>& tab, const Layout& l,
+                               hipStream_t s) {
+  hipError_t e = hipMemcpyAsync(d.probs, tab.data(), sizeof(BatchProb) * tab.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d.members, l.members.data(), sizeof(int32_t) * l.members.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d.begins, l.begins.data(), sizeof(int64_t) * l.begins.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  return e;
 }
 
 static void launch_pass_a_table(const BatchProb* d_tab, int n, int64_t total, int grid, uint32_t* counter,
@@ -323,26 +371,34 @@ static void launch_pass_a_table(const BatchProb* d_tab, int n, int64_t total, in
   batch_pass_a_kernel<<<dim3(grid), dim3(256), 0, s>>>(d_tab, n, total, counter);
 }
 
-static void launch_pass_b_table(const BatchProb* d_tab, const BatchState* d_st, int n, const Layout& l,
-                                hipStream_t s) {
-  if (l.tsc > 0) batch_scan_kernel<<<dim3((unsigned)l.tsc), dim3(64 * SCAN_MAX_WAVES), 0, s>>>(d_tab, d_st, n);
-  if (l.tcb > 0) {
-    if (l.off32)
-      batch_combine_kernel<true><<<dim3((unsigned)l.tcb), dim3(64 * COMBINE_MAX_WAVES), 0, s>>>(d_tab, d_st, n);
-    else
-      batch_combine_kernel<false><<<dim3((unsigned)l.tcb), dim3(64 * COMBINE_MAX_WAVES), 0, s>>>(d_tab, d_st, n);
-  }
+template <int R, typename RI>
+static void launch_combine_class(const DeviceTable& d, const BatchState* st, const Layout& l, hipStream_t s) {
+  const int c = combine_class(R, sizeof(RI) == 8 ? 1 : 0);
+  if (l.tcb[c] <= 0) return;
+  const dim3 grid((unsigned)l.tcb[c]), wg(64 * COMBINE_MAX_WAVES);
+  const int32_t* m = d.members + l.cls_off[c];
+  const int64_t* bg = d.begins + l.cls_off[c];
+  if (l.off32) batch_combine_kernel<R, RI, true><<<grid, wg, 0, s>>>(d.probs, st, m, bg, l.cls_cnt[c]);
+  else batch_combine_kernel<R, RI, false><<<grid, wg, 0, s>>>(d.probs, st, m, bg, l.cls_cnt[c]);
 }
 
+// Scan, then one combine launch per nonempty class, the longest first.
+static void launch_pass_b_table(const DeviceTable& d, const BatchState* st, int n, const Layout& l, hipStream_t s) {
+  if (l.tsc > 0) batch_scan_kernel<<<dim3((unsigned)l.tsc), dim3(64 * SCAN_MAX_WAVES), 0, s>>>(d.probs, st, n);
+  launch_combine_class<4, int32_t>(d, st, l, s);
+  launch_combine_class<2, int32_t>(d, st, l, s);
+  launch_combine_class<1, int32_t>(d, st, l, s);
+  launch_combine_class<4, int64_t>(d, st, l, s);
+  launch_combine_class<2, int64_t>(d, st, l, s);
+  launch_combine_class<1, int64_t>(d, st, l, s);
+}
+
+static DeviceTable device_table(const sk_batch_s* b) { return DeviceTable{b->d_probs, b->d_members, b->d_begins}; }
+
 static int launch_sequence(sk_batch_s* b, hipStream_t s) {
-  Layout l;
-  l.ta = b->total_a;
-  l.tsc = b->total_sc;
-  l.tcb = b->total_cb;
-  l.off32 = b->off32;
-  launch_pass_a_table(b->d_probs, b->n, b->total_a, b->grid_a, b->d_counter, s);
+  launch_pass_a_table(b->d_probs, b->n, b->lay.ta, b->grid_a, b->d_counter, s);
   SK_HIP_TRY(hipGetLastError());
-  launch_pass_b_table(b->d_probs, b->d_state, b->n, l, s);
+  launch_pass_b_table(device_table(b), b->d_state, b->n, b->lay, s);
   SK_HIP_TRY(hipGetLastError());
   batch_state_kernel<<<dim3(1), dim3(256), 0, s>>>(b->d_probs, b->d_state, b->n, b->d_counter);
   SK_HIP_TRY(hipGetLastError());
@@ -378,7 +434,7 @@ static float best_time(hipStream_t s, uint32_t* counter, int reps, Fn run) {
 // Pass A of the whole batch alone (profiling), best of three.
 static float time_pass_a_batch(sk_batch_s* b, hipStream_t s) {
   return best_time(s, b->d_counter, 3,
-                   [&] { launch_pass_a_table(b->d_probs, b->n, b->total_a, b->grid_a, b->d_counter, s); });
+                   [&] { launch_pass_a_table(b->d_probs, b->n, b->lay.ta, b->grid_a, b->d_counter, s); });
 }
 
 // Autotuner. Problems are grouped by class (N, M, F). For each class not in
@@ -398,8 +454,12 @@ static int tune_batch(sk_batch_s* b, const std::string& path, hipStream_t s) {
              (int)(P.a.row_bytes / P.a.n_inputs));
     classes[key].push_back(q);
   }
-  BatchProb* d_tab = nullptr;
-  if (hipMalloc((void**)&d_tab, sizeof(BatchProb) * b->n) != hipSuccess) {
+  DeviceTable d{nullptr, nullptr, nullptr};
+  if (hipMalloc((void**)&d.probs, sizeof(BatchProb) * b->n) != hipSuccess ||
+      hipMalloc((void**)&d.members, sizeof(int32_t) * b->n) != hipSuccess ||
+      hipMalloc((void**)&d.begins, sizeof(int64_t) * b->n) != hipSuccess) {
+    if (d.probs) (void)hipFree(d.probs);
+    if (d.members) (void)hipFree(d.members);
     set_error("hipMalloc of the tuning table failed");
     return SK_ERR_NOMEM;
   }
@@ -425,12 +485,12 @@ static int tune_batch(sk_batch_s* b, const std::string& path, hipStream_t s) {
           if (qq > 1 && !wide) continue;
           for (BatchProb& P : sub) set_pass_a(P, rr, qq);
           const Layout l = layout(sub);
-          if (hipMemcpy(d_tab, sub.data(), sizeof(BatchProb) * sub.size(), hipMemcpyHostToDevice) != hipSuccess) {
+          if (upload_table(d, sub, l, s) != hipSuccess) {
             rc = SK_ERR_DEVICE;
             break;
           }
           const float t = best_time(s, b->d_counter, 3, [&] {
-            launch_pass_a_table(d_tab, (int)sub.size(), l.ta, b->grid_a, b->d_counter, s);
+            launch_pass_a_table(d.probs, (int)sub.size(), l.ta, b->grid_a, b->d_counter, s);
           });
           char ck[320];
           snprintf(ck, sizeof ck, "%s|A|rows=%d|blocks=%d", key.c_str(), rr, qq);
@@ -443,12 +503,12 @@ static int tune_batch(sk_batch_s* b, const std::string& path, hipStream_t s) {
       for (int RR : {1, 2, 4}) {
         for (BatchProb& P : sub) set_pass_b(P, RR);
         const Layout l = layout(sub);
-        if (hipMemcpy(d_tab, sub.data(), sizeof(BatchProb) * sub.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        if (upload_table(d, sub, l, s) != hipSuccess) {
           rc = SK_ERR_DEVICE;
           break;
         }
         const float t = best_time(s, b->d_counter, 3, [&] {
-          launch_pass_b_table(d_tab, b->d_state, (int)sub.size(), l, s);
+          launch_pass_b_table(d, b->d_state, (int)sub.size(), l, s);
         });
         char ck[320];
         snprintf(ck, sizeof ck, "%s|B|chunk=%d", key.c_str(), RR);
@@ -464,7 +524,9 @@ static int tune_batch(sk_batch_s* b, const std::string& path, hipStream_t s) {
     }
     if (rc) break;
   }
-  (void)hipFree(d_tab);
+  (void)hipFree(d.probs);
+  (void)hipFree(d.members);
+  (void)hipFree(d.begins);
   if (rc == SK_OK && hipGetLastError() != hipSuccess) rc = SK_ERR_DEVICE;
   if (rc) { set_error("autotuning launch failed"); return rc; }
   if (dirty) save_cache(path, cache);
@@ -536,6 +598,8 @@ int sk_batch_create(const sk_plan_desc* descs, int32_t n, const sk_batch_opts* o
     set_pass_a(P, 16, 1);
     set_pass_b(P, pass_b_chunk((int32_t)N, (int32_t)F, B, L));
     P.waves = combine_waves((int32_t)N, 4);
+    P.scan_waves = scan_rows_waves(B);
+    P.wide_sums = combine_sums_fit_32((int32_t)N, 4, d.block_len) ? 0 : 1;
     P.mask = nullptr;
     const sk_outputs& o = outs[j];
     const size_t fbn = (size_t)F * B * N;
@@ -579,6 +643,12 @@ int sk_batch_create(const sk_plan_desc* descs, int32_t n, const sk_batch_opts* o
   if ((rc = batch_alloc(b, &p, sizeof(uint32_t)))) { batch_free(b); return rc; }
   b->owned.pop_back();
   b->d_counter = (uint32_t*)p;
+  if ((rc = batch_alloc(b, &p, sizeof(int32_t) * n))) { batch_free(b); return rc; }
+  b->owned.pop_back();
+  b->d_members = (int32_t*)p;
+  if ((rc = batch_alloc(b, &p, sizeof(int64_t) * n))) { batch_free(b); return rc; }
+  b->owned.pop_back();
+  b->d_begins = (int64_t*)p;
   std::vector<BatchState> st(n, BatchState{0, 0});
   (void)layout(b->host);
   if (hipMemcpyAsync(b->d_probs, b->host.data(), sizeof(BatchProb) * n, hipMemcpyHostToDevice, s) != hipSuccess ||
@@ -626,19 +696,18 @@ int sk_batch_create(const sk_plan_desc* descs, int32_t n, const sk_batch_opts* o
     b->tuned_from_cache.swap(cached);
   }
   {
-    const Layout l = layout(b->host);
+    b->lay = layout(b->host);
+    const Layout& l = b->lay;
     // The work-queue counter runs past the last task by one claim per
-    // workgroup; it must not wrap.
-    if (l.ta + (1LL << 24) >= (int64_t)UINT32_MAX || l.tsc >= (1LL << 31) || l.tcb >= (1LL << 31)) {
+    // workgroup; it must not wrap. Grids stay within 2^31 workgroups.
+    bool big = l.ta + (1LL << 24) >= (int64_t)UINT32_MAX || l.tsc >= (1LL << 31);
+    for (int c = 0; c < N_COMBINE_CLASSES; ++c) big = big || l.tcb[c] >= (1LL << 31);
+    if (big) {
       batch_free(b);
       set_error("batch too large");
       return SK_ERR_SHAPE;
     }
-    b->total_a = l.ta;
-    b->total_sc = l.tsc;
-    b->total_cb = l.tcb;
-    b->off32 = l.off32;
-    if (hipMemcpyAsync(b->d_probs, b->host.data(), sizeof(BatchProb) * n, hipMemcpyHostToDevice, s) != hipSuccess ||
+    if (upload_table(device_table(b), b->host, l, s) != hipSuccess ||
         hipMemsetAsync(b->d_counter, 0, sizeof(uint32_t), s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
       batch_free(b);
       set_error("batch table upload failed");

@@ -321,6 +321,72 @@ __device__ __forceinline__ void scan_body(const PassBArgs& a, int f, int slice, 
   }
 }
 
+// The same scan for a chunk length known only at run time (the batched
+// kernel's problems differ in it): each lane holds SCAN_ROWS rows of S1 per
+// round and writes its running sum at every chunk end, so the registers do
+// not depend on the chunk length. Rounds are SCAN_ROWS W rows; R (a power of
+// two) divides SCAN_ROWS. The prefix values are exact integers mod 2^32,
+// equal to scan_body's.
+constexpr int SCAN_ROWS = 32;
+
+__device__ __forceinline__ void scan_body_rows(const PassBArgs& a, int f, int slice, int w, int W, uint32_t* lds) {
+  const int R = a.chunk, lgR = __builtin_ctz((unsigned)a.chunk);
+  const int lane = threadIdx.x & 63;
+  const int i = slice * 64 + lane;
+  const bool active = i < a.n_inputs;
+  const int nk = a.n_chunks, B = a.n_blocks;
+  const int64_t rowN = a.n_inputs;
+  uint32_t* pc = a.pc + (int64_t)f * (nk + 1) * rowN + i;
+  if (w == 0 && active) pc[0] = 0u;
+  uint32_t carry = 0;
+  for (int base = 0; base < B; base += SCAN_ROWS * W) {
+    const int r0 = base + w * SCAN_ROWS;
+    uint32_t x[SCAN_ROWS];
+    const int32_t* p = a.s1 + ((int64_t)f * B + r0) * rowN + i;
+#pragma unroll
+    for (int r = 0; r < SCAN_ROWS; ++r) x[r] = (active && r0 + r < B) ? (uint32_t)p[(int64_t)r * rowN] : 0u;
+    uint32_t tot = 0;
+#pragma unroll
+    for (int r = 0; r < SCAN_ROWS; ++r) tot += x[r];
+    lds[w * 64 + lane] = tot;
+    __syncthreads();
+    uint32_t off = carry, all = carry;
+    for (int q = 0; q < W; ++q) {
+      const uint32_t t = lds[q * 64 + lane];
+      if (q < w) off += t;
+      all += t;
+    }
+    carry = all;
+    if (active) {
+#pragma unroll
+      for (int r = 0; r < SCAN_ROWS; ++r) {
+        off += x[r];
+        const int row = r0 + r;
+        // Chunk c ends at row c R + R - 1, or at B - 1 for a short last chunk.
+        if (row < B && (((row + 1) & (R - 1)) == 0 || row == B - 1)) pc[(int64_t)((row + R) >> lgR) * rowN] = off;
+      }
+    }
+    __syncthreads();
+  }
+  const int Hc = a.hist_cap;
+  const int from = Hc - a.hist_next_len, to = Hc - B;
+  if (active && a.hs_next) {
+    for (int s = from + w; s < to; s += W) {
+      const int32_t old = a.hist_len > 0 ? a.hs[((int64_t)f * Hc + s + B) * rowN + i] : 0;
+      a.hs_next[((int64_t)f * Hc + s) * rowN + i] = (int32_t)((uint32_t)old + carry);
+    }
+  }
+}
+
+// Waves per slice of the batched scan: a power of two covering the call's
+// rows in SCAN_ROWS-row lanes, at most SCAN_MAX_WAVES (so slices tile a
+// workgroup).
+__host__ __device__ __forceinline__ int scan_rows_waves(int64_t n_blocks) {
+  int W = 1;
+  while (W < SCAN_MAX_WAVES && (int64_t)W * SCAN_ROWS < n_blocks) W *= 2;
+  return W;
+}
+
 // ------------------------------------------------------------------ combine
 
 constexpr int COMBINE_MAX_WAVES = 8;
