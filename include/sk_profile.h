@@ -1,10 +1,12 @@
 /*
  * sk_profile.h - per-phase timing and tile control for sk_plan_t.
  *
- * For measurement tools and the autotuner: HIP events recorded on the
- * caller's stream around the two kernel phases of sk_compute (pass A: the
- * per-input block sums of Eq. singlesums; pass B: normaliser window, array
- * combine, estimator and flags of Eq. discreteMean .. final).
+ * For measurement tools and the autotuner: HIP events that the kernel
+ * dispatches of sk_compute record themselves (hipExtLaunchKernel) for its two
+ * phases (pass A: the per-input block sums of Eq. singlesums, from its
+ * kernel's start to its end; pass B: normaliser window, array combine,
+ * estimator and flags of Eq. discreteMean .. final, from its first kernel's
+ * start to its last kernel's end).
  */
 #ifndef SK_PROFILE_H
 #define SK_PROFILE_H
@@ -17,14 +19,14 @@
 extern "C" {
 #endif
 
-/* Record events around the phases of the next max_records sk_compute calls
- * on this plan (0 turns recording off and frees the events). Host-side only. */
+/* Record the phase durations of the next max_records sk_compute calls on
+ * this plan (0 turns recording off and frees the events). Host-side only. */
 int sk_profile_enable(sk_plan_t plan, int32_t max_records);
 
 /* Record only every stride-th call from now on (1, the default after
- * sk_profile_enable: every call). The events sit between dependent kernels
- * and cost a few microseconds per recorded call; a stride samples the phase
- * durations of a long run of calls while the others run unperturbed. */
+ * sk_profile_enable: every call). The timestamps travel with the dispatches,
+ * so a recorded call adds no packets between its kernels; a stride still
+ * bounds the number of events a long run needs. */
 int sk_profile_set_stride(sk_plan_t plan, int32_t stride);
 
 /* Wait for the recorded calls and return their phase durations in
@@ -87,6 +89,33 @@ int sk_plan_get_pass_a_tile(sk_plan_t plan, const uint8_t* d_packed, int32_t* ve
  * bytes % 16 == 0, else SK_ERR_INVALID_ARG. Asynchronous on `stream`; the
  * caller times it. The sink's contents carry no meaning. */
 int sk_read_probe(const uint8_t* d_x, int64_t bytes, int32_t workgroups, uint32_t* d_sink, void* stream);
+
+/* Result of sk_plan_autotune: the settings kept and their times. */
+typedef struct {
+  int32_t pass_a_variant;      /* 0..4, as SK_PASS_A_* */
+  int32_t pass_a_lanes;        /* lanes per row */
+  int32_t pass_a_blocks;       /* consecutive blocks per task */
+  int32_t pass_b_chunk;        /* blocks per combine workgroup (1, 2, 4) */
+  int32_t pass_b_vec;          /* inputs per combine lane (1 or 4) */
+  int32_t candidates;          /* combinations timed */
+  float ms_pass_a, ms_pass_b;  /* mean kernel times of the kept combination */
+  float ms_library_pass_a, ms_library_pass_b;  /* the library's own choice, same measurement */
+} sk_plan_tuning;
+
+/* Time every candidate tile combination of this plan on the device input
+ * d_x ([T][F][N] bytes) and keep the fastest: pass A variant (the library's
+ * choice; the deferred-store variant at 1, 2 and 4 blocks per task; the
+ * packed-table variants at 1024 and 256 lanes; blocks side by side for
+ * narrow rows), crossed with pass B chunk length {1, 2, 4}. Pass B inputs
+ * per lane stay as set (they order the FP64 combine). Each combination runs
+ * one untimed and `reps` (1..100) timed calls on `stream` without outputs;
+ * the kept one has the least mean pass A plus pass B kernel time. The
+ * normaliser state is exported before and imported after, so a stream in
+ * progress continues unchanged; results of later calls do not depend on the
+ * choice (integer sums are exact, and the combine's order does not depend on
+ * the chunk length). Synchronises `stream`; must not overlap other calls of
+ * the plan. `out` may be NULL. */
+int sk_plan_autotune(sk_plan_t plan, const uint8_t* d_x, int32_t reps, void* stream, sk_plan_tuning* out);
 
 #ifdef __cplusplus
 }

@@ -48,6 +48,14 @@ class Outputs(ctypes.Structure):
                 ("n_eff", ctypes.c_void_p), ("sk_i", ctypes.c_void_p), ("significance", ctypes.c_void_p)]
 
 
+class PlanTuning(ctypes.Structure):
+    _fields_ = [("pass_a_variant", ctypes.c_int32), ("pass_a_lanes", ctypes.c_int32),
+                ("pass_a_blocks", ctypes.c_int32), ("pass_b_chunk", ctypes.c_int32),
+                ("pass_b_vec", ctypes.c_int32), ("candidates", ctypes.c_int32),
+                ("ms_pass_a", ctypes.c_float), ("ms_pass_b", ctypes.c_float),
+                ("ms_library_pass_a", ctypes.c_float), ("ms_library_pass_b", ctypes.c_float)]
+
+
 class McDesc(ctypes.Structure):
     _fields_ = [("n_inputs", ctypes.c_int32), ("block_len", ctypes.c_int32), ("estimator", ctypes.c_int32),
                 ("clip", ctypes.c_int32), ("sigma", ctypes.c_double), ("n_sim", ctypes.c_int64),
@@ -104,6 +112,8 @@ def load_library():
     lib.sk_plan_set_pass_a_variant.argtypes = [VP, I32, I32]
     lib.sk_plan_set_pass_b_tile.argtypes = [VP, I32, I32]
     lib.sk_plan_set_pass_b_tile.restype = ctypes.c_int
+    lib.sk_plan_autotune.argtypes = [VP, VP, I32, VP, ctypes.POINTER(PlanTuning)]
+    lib.sk_plan_autotune.restype = ctypes.c_int
     lib.sk_profile_enable.argtypes = [VP, I32]
     lib.sk_profile_set_stride.argtypes = [VP, I32]
     lib.sk_profile_read.argtypes = [VP, VP, VP, I32, ctypes.POINTER(I32)]
@@ -318,6 +328,18 @@ class Plan:
         """Pass B blocks per combine workgroup (1, 2, 4; 0: library choice) and
         inputs per lane (1, 4; 0: library choice)."""
         _check(self._lib.sk_plan_set_pass_b_tile(self.handle, int(chunk), int(inputs_per_lane)))
+
+    def autotune(self, x: torch.Tensor, reps: int = 2, stream: Optional[torch.cuda.Stream] = None) -> dict:
+        """Time the plan's tile candidates on the input ``x`` ([T][F][N] uint8 on
+        the plan's device) and keep the fastest (``sk_plan_autotune``); the
+        normaliser state is kept. Returns the kept settings and their times."""
+        d = self.desc
+        _device_tensor(x, "x", torch.uint8, (d.n_samples, d.n_channels, d.n_inputs), self.device_index)
+        r = PlanTuning()
+        _check(self._lib.sk_plan_autotune(self.handle, ctypes.c_void_p(x.data_ptr()), int(reps),
+                                          _stream_handle(stream), ctypes.byref(r)))
+        return {k: (round(float(getattr(r, k)), 5) if k.startswith("ms_") else int(getattr(r, k)))
+                for k, _ in PlanTuning._fields_}
 
     def set_false_alarm(self, fap: float):
         """Flag at the fap and 1 - fap quantiles of a Pearson III law (0: symmetric k sigma)."""

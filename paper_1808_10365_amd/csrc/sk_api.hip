@@ -56,7 +56,7 @@ struct sk_plan_s {
   int pass_a_blocks = 0;   // consecutive blocks per pass A task (packed variants; 0 = library choice)
   int pass_b_vec;          // 0 = library choice, else 1 or 4 inputs per lane
   int n_cu = 256;          // compute units of the plan's device
-  std::vector<hipEvent_t> prof;   // 3 events per recorded call
+  std::vector<hipEvent_t> prof;   // 4 events per recorded call
   double* thresholds;             // [N + 1][2] false-alarm thresholds by N_eff, or null
   double fap;
   int32_t prof_max, prof_n;
@@ -154,9 +154,10 @@ int sk_plan_create(const sk_plan_desc* desc, sk_plan_t* out) {
   if (L >= 2) {
     p->pc_bytes = pass_b_prefix_bytes((int32_t)N, (int32_t)F, p->n_blocks, p->chunk);
     SK_ALLOC(p->pc, p->pc_bytes);
-    // Chunk sums from pass A when its tasks are the plan's pass B chunks.
-    if (p->chunk >= 2) {
-      p->cs_bytes = (size_t)F * (size_t)((p->n_blocks + p->chunk - 1) / p->chunk) * (size_t)N * sizeof(int32_t);
+    // Chunk sums from pass A when its tasks are the plan's pass B chunks
+    // (sized for the shortest such chunk, R = 2, which a tuner may pick).
+    if (p->n_blocks >= 2) {
+      p->cs_bytes = (size_t)F * (size_t)((p->n_blocks + 1) / 2) * (size_t)N * sizeof(int32_t);
       SK_ALLOC(p->cs, p->cs_bytes);
     }
     SK_ALLOC(p->hs[0], (size_t)F * p->hist_cap * N * sizeof(int32_t));
@@ -300,7 +301,7 @@ int sk_profile_enable(sk_plan_t p, int32_t max_records) {
   if (!p || max_records < 0) { set_error("bad arguments"); return SK_ERR_INVALID_ARG; }
   free_profile(p);
   if (max_records == 0) return SK_OK;
-  p->prof.resize((size_t)max_records * 3);
+  p->prof.resize((size_t)max_records * 4);
   for (auto& e : p->prof) SK_HIP_TRY(hipEventCreate(&e));
   p->prof_max = max_records;
   p->prof_n = 0;
@@ -322,9 +323,9 @@ int sk_profile_read(sk_plan_t p, float* ms_a, float* ms_b, int32_t cap, int32_t*
   if (!p || !n || (cap > 0 && (!ms_a || !ms_b))) { set_error("bad arguments"); return SK_ERR_INVALID_ARG; }
   const int32_t m = p->prof_n < cap ? p->prof_n : cap;
   for (int32_t j = 0; j < m; ++j) {
-    SK_HIP_TRY(hipEventSynchronize(p->prof[3 * j + 2]));
-    SK_HIP_TRY(hipEventElapsedTime(&ms_a[j], p->prof[3 * j], p->prof[3 * j + 1]));
-    SK_HIP_TRY(hipEventElapsedTime(&ms_b[j], p->prof[3 * j + 1], p->prof[3 * j + 2]));
+    SK_HIP_TRY(hipEventSynchronize(p->prof[4 * j + 3]));
+    SK_HIP_TRY(hipEventElapsedTime(&ms_a[j], p->prof[4 * j], p->prof[4 * j + 1]));
+    SK_HIP_TRY(hipEventElapsedTime(&ms_b[j], p->prof[4 * j + 2], p->prof[4 * j + 3]));
   }
   *n = m;
   p->prof_n = 0;
@@ -393,18 +394,13 @@ static PassBArgs make_pass_b_args(const sk_plan_desc& d, int64_t B, int32_t hist
 
 extern "C" {
 
-int sk_compute(sk_plan_t p, const uint8_t* d_packed, const uint8_t* d_mask, const sk_outputs* outs,
-               void* stream) {
-  clear_error();
-  if (!p || !outs) { set_error("NULL plan or outputs"); return SK_ERR_INVALID_ARG; }
-  if (!d_packed && p->d.n_samples > 0) { set_error("NULL input"); return SK_ERR_INVALID_ARG; }
-  int dev = -1;
-  SK_HIP_TRY(hipGetDevice(&dev));
-  if (dev != p->device) { set_error("plan was created on device %d, current device is %d", p->device, dev); return SK_ERR_INVALID_ARG; }
-  hipStream_t s = (hipStream_t)stream;
-  const int64_t B = p->n_blocks;
-  if (B == 0) return SK_OK;
+}  // extern "C"
 
+// One call of a plan (the body of sk_compute, arguments checked): pass A,
+// then pass B, with the given dispatch timing events (null: untimed).
+static int plan_call(sk_plan_s* p, const uint8_t* d_packed, const uint8_t* d_mask, const sk_outputs* outs,
+                     hipStream_t s, PassEvents ea, PassEvents eb) {
+  const int64_t B = p->n_blocks;
   CallBuffers cb;
   cb.s1 = outs->s1 ? outs->s1 : p->s1;
   cb.s2 = outs->s2 ? outs->s2 : p->s2;
@@ -427,20 +423,155 @@ int sk_compute(sk_plan_t p, const uint8_t* d_packed, const uint8_t* d_mask, cons
     a.cs = p->cs;
   }
 
-  const bool rec = p->prof_n < p->prof_max && (p->prof_calls++ % p->prof_stride) == 0;
-  if (rec) SK_HIP_TRY(hipEventRecord(p->prof[3 * p->prof_n], s));
-  int rc = launch_pass_a(t, c, s);
+  int rc = launch_pass_a(t, c, s, ea);
   if (rc) return rc;
-  if (rec) SK_HIP_TRY(hipEventRecord(p->prof[3 * p->prof_n + 1], s));
-  rc = launch_pass_b(a, s);
+  rc = launch_pass_b(a, s, eb);
   if (rc) return rc;
-  if (rec) {
-    SK_HIP_TRY(hipEventRecord(p->prof[3 * p->prof_n + 2], s));
-    p->prof_n += 1;
-  }
   if (p->hist_cap > 0) {
     p->hist_len = a.hist_next_len;
     p->cur = 1 - p->cur;
+  }
+  return SK_OK;
+}
+
+extern "C" {
+
+int sk_compute(sk_plan_t p, const uint8_t* d_packed, const uint8_t* d_mask, const sk_outputs* outs,
+               void* stream) {
+  clear_error();
+  if (!p || !outs) { set_error("NULL plan or outputs"); return SK_ERR_INVALID_ARG; }
+  if (!d_packed && p->d.n_samples > 0) { set_error("NULL input"); return SK_ERR_INVALID_ARG; }
+  int dev = -1;
+  SK_HIP_TRY(hipGetDevice(&dev));
+  if (dev != p->device) { set_error("plan was created on device %d, current device is %d", p->device, dev); return SK_ERR_INVALID_ARG; }
+  if (p->n_blocks == 0) return SK_OK;
+  // A recorded call's four timestamps come with its kernels' dispatches:
+  // pass A's kernel start and end, pass B's first start and last end.
+  const bool rec = p->prof_n < p->prof_max && (p->prof_calls++ % p->prof_stride) == 0;
+  PassEvents ea, eb;
+  if (rec) {
+    hipEvent_t* e = &p->prof[4 * p->prof_n];
+    ea = PassEvents{e[0], e[1]};
+    eb = PassEvents{e[2], e[3]};
+  }
+  const int rc = plan_call(p, d_packed, d_mask, outs, (hipStream_t)stream, ea, eb);
+  if (rc == SK_OK && rec) p->prof_n += 1;
+  return rc;
+}
+
+// Autotuner of one plan: every candidate (pass A variant and its lanes or
+// blocks per task, pass B chunk length) runs one
+// untimed and `reps` timed calls on d_x; the fastest mean of pass A plus
+// pass B kernel time (dispatch timestamps) is kept. The normaliser state is
+// saved before and restored after, so a stream in progress continues as if
+// the tuning calls had not run.
+int sk_plan_autotune(sk_plan_t p, const uint8_t* d_x, int32_t reps, void* stream, sk_plan_tuning* out) {
+  clear_error();
+  if (!p || !d_x || reps < 1 || reps > 100) { set_error("autotune: NULL plan or input, or reps outside 1..100"); return SK_ERR_INVALID_ARG; }
+  int dev = -1;
+  SK_HIP_TRY(hipGetDevice(&dev));
+  if (dev != p->device) { set_error("plan was created on device %d, current device is %d", p->device, dev); return SK_ERR_INVALID_ARG; }
+  hipStream_t s = (hipStream_t)stream;
+  if (p->n_blocks == 0) return SK_OK;
+  // Saved state and settings.
+  size_t sbytes = 0;
+  int rc = sk_state_size(p, &sbytes);
+  if (rc) return rc;
+  std::vector<uint8_t> saved(sbytes);
+  if ((rc = sk_state_export(p, saved.data(), sbytes, stream))) return rc;
+  const int keep_lpr = p->pass_a_lpr, keep_var = p->pass_a_variant, keep_blocks = p->pass_a_blocks;
+  const int32_t keep_chunk = p->chunk, keep_vec = p->pass_b_vec;
+
+  struct Cand { int variant, lpr, blocks, chunk, vec; };
+  std::vector<Cand> cands;
+  const int vec = pick_vec(d_x, p->d.n_inputs);
+  const int64_t cg = (int64_t)p->d.n_channels * p->d.n_inputs / vec;
+  std::vector<Cand> a_opts = {{-1, 0, 0, 0, 0}};
+  if (vec == 16) {
+    if (cg >= 512)
+      for (int q : {1, 2, 4}) a_opts.push_back({4, 0, q, 0, 0});
+    if (cg >= 512) a_opts.push_back({2, 1024, 1, 0, 0});
+    if (cg >= 256) {
+      a_opts.push_back({2, 256, 1, 0, 0});
+      a_opts.push_back({1, 256, 1, 0, 0});
+    }
+    if (cg < 256) a_opts.push_back({3, 0, 0, 0, 0});
+  }
+  // Pass B inputs per lane stay as set: they fix which inputs a lane sums
+  // first, so they change the combine's rounding; the chunk length does not.
+  for (const Cand& a : a_opts)
+    for (int R : {1, 2, 4}) cands.push_back({a.variant, a.lpr, a.blocks, R, keep_vec});
+
+  std::vector<hipEvent_t> ev(4 * (size_t)reps, nullptr);
+  for (auto& e : ev) {
+    if (hipEventCreate(&e) != hipSuccess) {
+      for (auto& x : ev) if (x) (void)hipEventDestroy(x);
+      set_error("autotune: event create failed");
+      return SK_ERR_DEVICE;
+    }
+  }
+  sk_outputs none;
+  memset(&none, 0, sizeof none);
+  float best = 1e30f, best_a = 0.f, best_b = 0.f, lib_a = 0.f, lib_b = 0.f;
+  size_t best_i = 0;
+  for (size_t ci = 0; ci < cands.size() && rc == SK_OK; ++ci) {
+    const Cand& c = cands[ci];
+    p->pass_a_lpr = c.lpr;
+    p->pass_a_variant = c.variant;
+    p->pass_a_blocks = c.blocks;
+    if ((rc = sk_plan_set_pass_b_tile(p, c.chunk, c.vec))) break;
+    if ((rc = plan_call(p, d_x, nullptr, &none, s, PassEvents(), PassEvents()))) break;
+    for (int r = 0; r < reps && rc == SK_OK; ++r)
+      rc = plan_call(p, d_x, nullptr, &none, s, PassEvents{ev[4 * r], ev[4 * r + 1]},
+                     PassEvents{ev[4 * r + 2], ev[4 * r + 3]});
+    if (rc) break;
+    if (hipStreamSynchronize(s) != hipSuccess) { rc = SK_ERR_DEVICE; set_error("autotune: synchronize failed"); break; }
+    float ta = 0.f, tb = 0.f;
+    for (int r = 0; r < reps; ++r) {
+      float x = 0.f, y = 0.f;
+      if (hipEventElapsedTime(&x, ev[4 * r], ev[4 * r + 1]) != hipSuccess ||
+          hipEventElapsedTime(&y, ev[4 * r + 2], ev[4 * r + 3]) != hipSuccess) {
+        rc = SK_ERR_DEVICE;
+        set_error("autotune: event timing failed");
+        break;
+      }
+      ta += x;
+      tb += y;
+    }
+    ta /= reps;
+    tb /= reps;
+    if (c.variant == -1 && c.lpr == 0 && c.blocks == 0 && c.chunk == keep_chunk) { lib_a = ta; lib_b = tb; }
+    if (ta + tb < best) { best = ta + tb; best_i = ci; best_a = ta; best_b = tb; }
+  }
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  if (rc) {
+    p->pass_a_lpr = keep_lpr;
+    p->pass_a_variant = keep_var;
+    p->pass_a_blocks = keep_blocks;
+    (void)sk_plan_set_pass_b_tile(p, keep_chunk, keep_vec);
+    (void)sk_state_import(p, saved.data(), sbytes, stream);
+    return rc;
+  }
+  const Cand& c = cands[best_i];
+  p->pass_a_lpr = c.lpr;
+  p->pass_a_variant = c.variant;
+  p->pass_a_blocks = c.blocks;
+  if ((rc = sk_plan_set_pass_b_tile(p, c.chunk, c.vec))) return rc;
+  if ((rc = sk_state_import(p, saved.data(), sbytes, stream))) return rc;
+  if (out) {
+    PassATask t;
+    const PassAConfig pc = plan_pass_a_config(p, d_x, &t);
+    out->pass_a_variant = pc.variant;
+    out->pass_a_lanes = pc.lpr;
+    out->pass_a_blocks = t.blocks_per_task;
+    out->pass_b_chunk = p->chunk;
+    out->pass_b_vec = make_pass_b_args(p->d, p->n_blocks, p->hist_cap, p->chunk, p->pass_b_vec, nullptr, &none,
+                                       CallBuffers{p->s1, p->s2, p->pc, nullptr, nullptr, 0}, nullptr).vec;
+    out->candidates = (int32_t)cands.size();
+    out->ms_pass_a = best_a;
+    out->ms_pass_b = best_b;
+    out->ms_library_pass_a = lib_a;
+    out->ms_library_pass_b = lib_b;
   }
   return SK_OK;
 }

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <stdint.h>
 
 #include <string>
@@ -57,7 +58,24 @@ struct PassAConfig {
   int grid;    // workgroups launched (<= tasks; grid-stride beyond)
 };
 
-int launch_pass_a(const PassATask& t, const PassAConfig& c, hipStream_t s);
+// Timing of a pass, recorded by the kernel dispatches themselves (either
+// event may be null): `start` when the pass's first kernel starts, `stop`
+// when its last one ends. The timestamps come with the dispatch packets
+// (hipExtLaunchKernel), so a timed call has no extra packets between its
+// kernels.
+struct PassEvents {
+  hipEvent_t start = nullptr;
+  hipEvent_t stop = nullptr;
+};
+
+template <typename... P, typename... A>
+inline void launch_kernel(void (*k)(P...), dim3 grid, dim3 wg, uint32_t lds, hipStream_t s, hipEvent_t start,
+                          hipEvent_t stop, A... args) {
+  if (start || stop) hipExtLaunchKernelGGL(k, grid, wg, lds, s, start, stop, 0u, static_cast<P>(args)...);
+  else k<<<grid, wg, lds, s>>>(static_cast<P>(args)...);
+}
+
+int launch_pass_a(const PassATask& t, const PassAConfig& c, hipStream_t s, PassEvents ev = PassEvents());
 int pick_vec(const uint8_t* x, int32_t n_inputs);
 // Lanes per row the variant supports; the planner clamps into [lo, hi].
 void pass_a_lane_range(int vec, int variant, int* lo, int* hi);
@@ -107,7 +125,7 @@ int pass_b_chunk(int32_t n_inputs, int32_t n_channels, int64_t n_blocks, int32_t
 int pass_b_vec(int32_t n_inputs);
 // Device bytes of the prefix buffer: F (ceil(B / R) + 1) N uint32.
 size_t pass_b_prefix_bytes(int32_t n_inputs, int32_t n_channels, int64_t n_blocks, int32_t chunk);
-int launch_pass_b(const PassBArgs& a, hipStream_t s);
+int launch_pass_b(const PassBArgs& a, hipStream_t s, PassEvents ev = PassEvents());
 
 double pearson3_quantile(double mean, double sd, double skew, double p);
 

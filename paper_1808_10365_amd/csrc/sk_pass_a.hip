@@ -117,29 +117,29 @@ __global__ __launch_bounds__(wg_size<LPR>()) void pass_a_shared_kernel(PassATask
 }
 
 template <int VEC, int LPR>
-static int launch_shared_one(const PassATask& t, int grid, hipStream_t s) {
+static int launch_shared_one(const PassATask& t, int grid, hipStream_t s, PassEvents ev) {
   constexpr int WG = wg_size<LPR>();
   constexpr int RP = WG / LPR;
   const size_t lds = RP > 1 ? sizeof(uint32_t) * WG * (2 * VEC + 1) : 0;
-  pass_a_shared_kernel<VEC, LPR><<<dim3(grid), dim3(WG), lds, s>>>(t);
+  launch_kernel(pass_a_shared_kernel<VEC, LPR>, dim3(grid), dim3(WG), (uint32_t)lds, s, ev.start, ev.stop, t);
   SK_HIP_TRY(hipGetLastError());
   return SK_OK;
 }
 
 template <int VEC>
-static int launch_shared(const PassATask& t, int lpr, int grid, hipStream_t s) {
+static int launch_shared(const PassATask& t, int lpr, int grid, hipStream_t s, PassEvents ev) {
   switch (lpr) {
-    case 1: return launch_shared_one<VEC, 1>(t, grid, s);
-    case 2: return launch_shared_one<VEC, 2>(t, grid, s);
-    case 4: return launch_shared_one<VEC, 4>(t, grid, s);
-    case 8: return launch_shared_one<VEC, 8>(t, grid, s);
-    case 16: return launch_shared_one<VEC, 16>(t, grid, s);
-    case 32: return launch_shared_one<VEC, 32>(t, grid, s);
-    case 64: return launch_shared_one<VEC, 64>(t, grid, s);
-    case 128: return launch_shared_one<VEC, 128>(t, grid, s);
-    case 256: return launch_shared_one<VEC, 256>(t, grid, s);
-    case 512: return launch_shared_one<VEC, 512>(t, grid, s);
-    case 1024: return launch_shared_one<VEC, 1024>(t, grid, s);
+    case 1: return launch_shared_one<VEC, 1>(t, grid, s, ev);
+    case 2: return launch_shared_one<VEC, 2>(t, grid, s, ev);
+    case 4: return launch_shared_one<VEC, 4>(t, grid, s, ev);
+    case 8: return launch_shared_one<VEC, 8>(t, grid, s, ev);
+    case 16: return launch_shared_one<VEC, 16>(t, grid, s, ev);
+    case 32: return launch_shared_one<VEC, 32>(t, grid, s, ev);
+    case 64: return launch_shared_one<VEC, 64>(t, grid, s, ev);
+    case 128: return launch_shared_one<VEC, 128>(t, grid, s, ev);
+    case 256: return launch_shared_one<VEC, 256>(t, grid, s, ev);
+    case 512: return launch_shared_one<VEC, 512>(t, grid, s, ev);
+    case 1024: return launch_shared_one<VEC, 1024>(t, grid, s, ev);
   }
   set_error("pass A: unsupported lanes-per-row %d", lpr);
   return SK_ERR_INVALID_ARG;
@@ -174,11 +174,11 @@ __global__ __launch_bounds__(LPR) void pass_a_packed_kernel(PassATask t) {
 }
 
 template <int U>
-static int launch_packed(const PassATask& t, int lpr, int grid, hipStream_t s) {
+static int launch_packed(const PassATask& t, int lpr, int grid, hipStream_t s, PassEvents ev) {
   switch (lpr) {
-    case 256: pass_a_packed_kernel<256, U><<<dim3(grid), dim3(256), 0, s>>>(t); break;
-    case 512: pass_a_packed_kernel<512, U><<<dim3(grid), dim3(512), 0, s>>>(t); break;
-    case 1024: pass_a_packed_kernel<1024, U><<<dim3(grid), dim3(1024), 0, s>>>(t); break;
+    case 256: launch_kernel(pass_a_packed_kernel<256, U>, dim3(grid), dim3(256), 0, s, ev.start, ev.stop, t); break;
+    case 512: launch_kernel(pass_a_packed_kernel<512, U>, dim3(grid), dim3(512), 0, s, ev.start, ev.stop, t); break;
+    case 1024: launch_kernel(pass_a_packed_kernel<1024, U>, dim3(grid), dim3(1024), 0, s, ev.start, ev.stop, t); break;
     default:
       set_error("pass A: packed lane-table variant needs 256..1024 lanes per row, got %d", lpr);
       return SK_ERR_INVALID_ARG;
@@ -282,21 +282,22 @@ void pass_a_lane_range(int vec, int variant, int* lo, int* hi) {
 }
 
 template <int VEC>
-static int launch_vec(const PassATask& t, int lpr, int variant, int grid, hipStream_t s) {
+static int launch_vec(const PassATask& t, int lpr, int variant, int grid, hipStream_t s, PassEvents ev) {
   if constexpr (VEC == 16) {
+    const dim3 g(grid), w512(512);
     switch (variant) {
-      case 1: return launch_packed<8>(t, lpr, grid, s);
-      case 2: return launch_packed<16>(t, lpr, grid, s);
+      case 1: return launch_packed<8>(t, lpr, grid, s, ev);
+      case 2: return launch_packed<16>(t, lpr, grid, s, ev);
       case 3:
-        pass_a_side_by_side_kernel<16><<<dim3(grid), dim3(256), 0, s>>>(t, lpr);
+        launch_kernel(pass_a_side_by_side_kernel<16>, g, dim3(256), 0, s, ev.start, ev.stop, t, lpr);
         SK_HIP_TRY(hipGetLastError());
         return SK_OK;
       case 4:
         switch (t.blocks_per_task) {
-          case 1: pass_a_deferred_kernel<1, 16><<<dim3(grid), dim3(512), 0, s>>>(t); break;
-          case 2: pass_a_deferred_kernel<2, 16><<<dim3(grid), dim3(512), 0, s>>>(t); break;
-          case 3: pass_a_deferred_kernel<3, 16><<<dim3(grid), dim3(512), 0, s>>>(t); break;
-          case 4: pass_a_deferred_kernel<4, 16><<<dim3(grid), dim3(512), 0, s>>>(t); break;
+          case 1: launch_kernel(pass_a_deferred_kernel<1, 16>, g, w512, 0, s, ev.start, ev.stop, t); break;
+          case 2: launch_kernel(pass_a_deferred_kernel<2, 16>, g, w512, 0, s, ev.start, ev.stop, t); break;
+          case 3: launch_kernel(pass_a_deferred_kernel<3, 16>, g, w512, 0, s, ev.start, ev.stop, t); break;
+          case 4: launch_kernel(pass_a_deferred_kernel<4, 16>, g, w512, 0, s, ev.start, ev.stop, t); break;
           default:
             set_error("pass A: deferred-store variant needs 1..4 blocks per task, got %d", t.blocks_per_task);
             return SK_ERR_INVALID_ARG;
@@ -306,7 +307,7 @@ static int launch_vec(const PassATask& t, int lpr, int variant, int grid, hipStr
       default: break;
     }
   }
-  return launch_shared<VEC>(t, lpr, grid, s);
+  return launch_shared<VEC>(t, lpr, grid, s, ev);
 }
 
 int pick_vec(const uint8_t* x, int32_t n_inputs) {
@@ -393,13 +394,13 @@ PassAConfig default_pass_a_config(int vec, int64_t row_bytes, int64_t n_blocks, 
   return c;
 }
 
-int launch_pass_a(const PassATask& t, const PassAConfig& c, hipStream_t s) {
+int launch_pass_a(const PassATask& t, const PassAConfig& c, hipStream_t s, PassEvents ev) {
   if (t.n_tasks <= 0) return SK_OK;
   const int grid = (int)(c.grid < t.n_tasks ? c.grid : t.n_tasks);
   switch (c.vec) {
-    case 16: return launch_vec<16>(t, c.lpr, c.variant, grid, s);
-    case 4: return launch_vec<4>(t, c.lpr, c.variant, grid, s);
-    case 1: return launch_vec<1>(t, c.lpr, c.variant, grid, s);
+    case 16: return launch_vec<16>(t, c.lpr, c.variant, grid, s, ev);
+    case 4: return launch_vec<4>(t, c.lpr, c.variant, grid, s, ev);
+    case 1: return launch_vec<1>(t, c.lpr, c.variant, grid, s, ev);
   }
   set_error("pass A: unsupported vector width %d", c.vec);
   return SK_ERR_INVALID_ARG;

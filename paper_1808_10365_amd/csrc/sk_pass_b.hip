@@ -32,20 +32,22 @@ __global__ __launch_bounds__(64 * COMBINE_MAX_WAVES) void combine_kernel(PassBAr
 }
 
 template <int V, int R>
-static void launch_combine_r(const PassBArgs& a, bool fit32, dim3 grid, dim3 wg, hipStream_t s) {
+static void launch_combine_r(const PassBArgs& a, bool fit32, dim3 grid, dim3 wg, hipStream_t s, hipEvent_t e0,
+                             hipEvent_t e1) {
   const bool off32 = combine_offsets_fit_32(a.n_inputs, a.n_blocks, a.n_chunks, a.hist_cap);
-  if (fit32 && off32) combine_kernel<V, R, int32_t, true><<<grid, wg, 0, s>>>(a);
-  else if (fit32) combine_kernel<V, R, int32_t, false><<<grid, wg, 0, s>>>(a);
-  else if (off32) combine_kernel<V, R, int64_t, true><<<grid, wg, 0, s>>>(a);
-  else combine_kernel<V, R, int64_t, false><<<grid, wg, 0, s>>>(a);
+  if (fit32 && off32) launch_kernel(combine_kernel<V, R, int32_t, true>, grid, wg, 0, s, e0, e1, a);
+  else if (fit32) launch_kernel(combine_kernel<V, R, int32_t, false>, grid, wg, 0, s, e0, e1, a);
+  else if (off32) launch_kernel(combine_kernel<V, R, int64_t, true>, grid, wg, 0, s, e0, e1, a);
+  else launch_kernel(combine_kernel<V, R, int64_t, false>, grid, wg, 0, s, e0, e1, a);
 }
 
 template <int V>
-static int launch_combine_v(const PassBArgs& a, bool fit32, dim3 grid, dim3 wg, hipStream_t s) {
+static int launch_combine_v(const PassBArgs& a, bool fit32, dim3 grid, dim3 wg, hipStream_t s, hipEvent_t e0,
+                            hipEvent_t e1) {
   switch (a.chunk) {
-    case 1: launch_combine_r<V, 1>(a, fit32, grid, wg, s); break;
-    case 2: launch_combine_r<V, 2>(a, fit32, grid, wg, s); break;
-    case 4: launch_combine_r<V, 4>(a, fit32, grid, wg, s); break;
+    case 1: launch_combine_r<V, 1>(a, fit32, grid, wg, s, e0, e1); break;
+    case 2: launch_combine_r<V, 2>(a, fit32, grid, wg, s, e0, e1); break;
+    case 4: launch_combine_r<V, 4>(a, fit32, grid, wg, s, e0, e1); break;
     default:
       set_error("pass B: chunk length %d is not 1, 2 or 4", a.chunk);
       return SK_ERR_INVALID_ARG;
@@ -54,25 +56,27 @@ static int launch_combine_v(const PassBArgs& a, bool fit32, dim3 grid, dim3 wg, 
   return SK_OK;
 }
 
-int launch_pass_b(const PassBArgs& a, hipStream_t s) {
+int launch_pass_b(const PassBArgs& a, hipStream_t s, PassEvents ev) {
   if (a.n_blocks <= 0) return SK_OK;
   const int F = a.n_channels;
+  hipEvent_t start = ev.start;
   if (a.window >= 2) {
     const dim3 grid((a.n_inputs + 63) / 64, F), wg(64 * scan_waves(a.n_chunks));
     switch (a.chunk) {
-      case 1: scan_kernel<1><<<grid, wg, 0, s>>>(a); break;
-      case 2: scan_kernel<2><<<grid, wg, 0, s>>>(a); break;
-      case 4: scan_kernel<4><<<grid, wg, 0, s>>>(a); break;
+      case 1: launch_kernel(scan_kernel<1>, grid, wg, 0, s, start, nullptr, a); break;
+      case 2: launch_kernel(scan_kernel<2>, grid, wg, 0, s, start, nullptr, a); break;
+      case 4: launch_kernel(scan_kernel<4>, grid, wg, 0, s, start, nullptr, a); break;
       default:
         set_error("pass B: chunk length %d is not 1, 2 or 4", a.chunk);
         return SK_ERR_INVALID_ARG;
     }
     SK_HIP_TRY(hipGetLastError());
+    start = nullptr;
   }
   const dim3 grid(a.n_chunks, F), wg(64 * combine_waves(a.n_inputs, a.vec));
   const bool fit32 = combine_sums_fit_32(a.n_inputs, a.vec, a.block_len);
-  if (a.vec == 4) return launch_combine_v<4>(a, fit32, grid, wg, s);
-  return launch_combine_v<1>(a, fit32, grid, wg, s);
+  if (a.vec == 4) return launch_combine_v<4>(a, fit32, grid, wg, s, start, ev.stop);
+  return launch_combine_v<1>(a, fit32, grid, wg, s, start, ev.stop);
 }
 
 int pass_b_vec(int32_t n_inputs) { return n_inputs % 4 == 0 ? 4 : 1; }
