@@ -49,8 +49,12 @@ def parse():
                     help="offered loads as fractions of the measured saturated frame rate")
     ap.add_argument("--no-ceiling", action="store_true", help="skip the read-only stream ceiling")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched (32 problems) measurement")
-    ap.add_argument("--profile-stride", type=int, default=4,
-                    help="record pass A / pass B events on every n-th timed call (1: every call)")
+    ap.add_argument("--profile-stride", type=int, default=0,
+                    help="record pass A / pass B kernel times on every n-th timed call "
+                         "(0: two calls, the first and the middle one)")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the library's tile choice (no plan autotuning)")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the tiny, Pathfinder and CHIME M=1024 measurements")
     ap.add_argument("--no-next-rows", action="store_true",
                     help="skip the SK_i / false-alarm / diagnostic / Monte-Carlo measurements")
     ap.add_argument("--batched-steps", type=int, default=10)
@@ -242,6 +246,84 @@ def batched_same_workload(w, xd, args):
             "pass_a": {"ms": round(pa_ms, 4), "GBps": round(pa_gbs, 1), "frac": round(pa_gbs / HBM_PEAK_GBS, 4),
                        "note": "persistent pass A kernel alone, best of 3; algorithmic bytes (input + S1/S2)"},
             "lanes_per_row": lpr, "note": "one-problem batch of this workload, one graph launch per call"}
+
+
+def config_bench(name, dev, steps, warmup, autotune=True):
+    """One more workload through the plain call: its own plan (autotuned as in
+    the main run), inputs resident in HBM and rotated over at least 4 buffers
+    (and >= 1 GB) when small, pass A and pass B kernel times from the
+    dispatches of every call. The tiny workload reports device and wall
+    latency per call instead of bandwidth."""
+    import ctypes
+    import numpy as np
+    import torch
+    import paper_1808_10365_amd as sk
+    import synth
+    w = workload(name)
+    x = synth.generate(w)
+    L = w.norm_window
+    delta, sig = sk.digitised_expectation(w.sigma, w.block_len)
+    plan = sk.Plan(w.n_inputs, w.n_channels, w.n_samples, w.block_len, norm_window=L, k_sigma=5.0,
+                   expect_offset=delta, sigma_override=sig)
+    nbuf = 1 if x.nbytes >= (1 << 30) else min(64, max(4, int(np.ceil(1.0e9 / x.nbytes))))
+    xd = [torch.from_numpy(x).to(dev) for _ in range(nbuf)]
+    out = plan.alloc_outputs(dev)
+    tuning = plan.autotune(xd[0], reps=2) if autotune else None
+    for j in range(warmup):
+        plan.compute_into(xd[j % nbuf], out)
+    torch.cuda.synchronize()
+    lib = sk.load_library()
+    assert lib.sk_profile_enable(plan.handle, ctypes.c_int32(steps)) == 0
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for j in range(steps):
+        plan.compute_into(xd[j % nbuf], out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_step = e0.elapsed_time(e1) / steps
+    ms_a = (ctypes.c_float * steps)()
+    ms_b = (ctypes.c_float * steps)()
+    n = ctypes.c_int32()
+    assert lib.sk_profile_read(plan.handle, ms_a, ms_b, steps, ctypes.byref(n)) == 0
+    ms_a = np.array(ms_a[:n.value], dtype=np.float64)
+    ms_b = np.array(ms_b[:n.value], dtype=np.float64)
+    lib.sk_profile_enable(plan.handle, 0)
+    B = w.n_samples // w.block_len
+    a_bytes = x.nbytes + 8 * w.n_channels * B * w.n_inputs
+    a_gbs = a_bytes / (ms_a.mean() * 1e-3) / 1e9
+    res = {"workload": f"{w.name}: N={w.n_inputs} F={w.n_channels} T={w.n_samples} M={w.block_len} L={L}",
+           "input_bytes": x.nbytes, "input_buffers_rotated": nbuf, "steps": steps, "warmup": warmup,
+           "ms_per_call": round(ms_step, 5),
+           "pass_a_us": round(float(ms_a.mean()) * 1e3, 2), "pass_b_us": round(float(ms_b.mean()) * 1e3, 2),
+           "plan_autotune": tuning}
+    if name == "tiny":
+        dev_us = (ms_a + ms_b) * 1e3
+        wall = []
+        for j in range(200):
+            t0 = time.perf_counter()
+            plan.compute_into(xd[j % nbuf], out)
+            torch.cuda.synchronize()
+            wall.append((time.perf_counter() - t0) * 1e6)
+        wall = np.array(wall)
+        res.update({"device_us": {"p50": round(float(np.percentile(dev_us, 50)), 2),
+                                  "p99": round(float(np.percentile(dev_us, 99)), 2),
+                                  "note": "pass A + pass B kernel times of each timed call"},
+                    "stream_us_per_call": round(ms_step * 1e3, 2),
+                    "wall_us_per_call": {"p50": round(float(np.percentile(wall, 50)), 2),
+                                         "p99": round(float(np.percentile(wall, 99)), 2),
+                                         "note": "host time of one call plus a device synchronisation, 200 calls"}})
+    else:
+        gbs = x.nbytes / (ms_step * 1e-3) / 1e9
+        res.update({"GBps": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                    "pass_a_roofline": {"achieved": round(a_gbs, 1), "frac": round(a_gbs / HBM_PEAK_GBS, 4),
+                                        "algorithmic_bytes_per_launch": a_bytes,
+                                        "note": "input bytes + 8 B of S1/S2 per (channel, block, input) over the "
+                                                "pass A kernel time"}})
+    plan.close()
+    del xd
+    torch.cuda.empty_cache()
+    return res
 
 
 def pass_a_bytes(ws):
@@ -489,6 +571,15 @@ def main():
     xd = [torch.from_numpy(x).to(dev) for _ in range(nbuf)]
     out = plan.alloc_outputs(dev)
     stream = torch.cuda.current_stream()
+    # Plan set-up: the autotuner times the tile candidates on this frame and
+    # keeps the fastest (as a deployment would once per array shape).
+    tuning = None
+    if not args.no_autotune and not (args.lpr or args.variant >= 0 or args.grid or args.chunk or args.bvec
+                                     or args.ablocks):
+        t0 = time.perf_counter()
+        tuning = plan.autotune(xd[0], reps=2)
+        tuning["seconds"] = round(time.perf_counter() - t0, 3)
+        print(f"# plan autotune: {tuning}", file=sys.stderr, flush=True)
 
     for j in range(args.warmup):
         plan.compute_into(xd[j % nbuf], out)
@@ -499,7 +590,7 @@ def main():
     # Per-phase events (pass A / pass B durations) on every stride-th call of
     # the timed loop: each recorded call carries a few microseconds of event
     # overhead between its kernels.
-    stride = max(1, args.profile_stride)
+    stride = args.profile_stride if args.profile_stride > 0 else max(1, args.steps // 2)
     n_rec = (args.steps + stride - 1) // stride
     rc = lib.sk_profile_enable(plan.handle, ctypes.c_int32(n_rec))
     assert rc == 0
@@ -572,15 +663,18 @@ def main():
             "block_len": w.block_len, "norm_window_blocks": L, "input_bytes": in_bytes,
             "input_buffers_rotated": nbuf,
             "pass_a_tile": {"vec_bytes": vec.value, "lanes_per_row": lpr.value, "workgroups": wgs.value},
+            "plan_autotune": tuning,
         },
         "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
         "samples_per_s": round(in_bytes / (ms_step * 1e-3), 1),
         "frame_latency_ms": {"p50": round(float(np.percentile(step_ms, 50)), 4),
                              "p99": round(float(np.percentile(step_ms, 99)), 4),
-                             "note": "device time of one sk_compute (pass A + pass B), HIP events on the recorded calls"},
+                             "note": "device time of one sk_compute (pass A + pass B kernel times) on the recorded calls"},
         "pass_ms": {"pass_a_avg": round(float(ms_a.mean()), 4), "pass_b_avg": round(float(ms_b.mean()), 4),
                     "recorded_calls": int(n.value), "record_stride": stride,
-                    "note": "pass A: the per-input sums kernel; pass B: the scan and combine kernels after it"},
+                    "note": "kernel times from the dispatches' own timestamps (hipExtLaunchKernel events) on "
+                            "the recorded calls; pass A: the per-input sums kernel; pass B: first start to last "
+                            "end of the scan and combine kernels after it"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
@@ -605,6 +699,13 @@ def main():
         res["next_rows"] = next_rows_bench(w, xd[0], L, delta, sig, dev, max(10, args.steps // 2))
     del xd
     torch.cuda.empty_cache()
+    if not args.no_configs:
+        res["configs"] = {}
+        for name, steps in (("tiny", 500), ("pathfinder", 200), ("chime1024", 100)):
+            if name == args.workload:
+                continue
+            print(f"# config {name}", file=sys.stderr, flush=True)
+            res["configs"][name] = config_bench(name, dev, steps, 20, autotune=not args.no_autotune)
     if not args.no_serving:
         print("# serving: Poisson arrivals from two arrays", file=sys.stderr, flush=True)
         res["serving"] = serving_bench(args, dev)
