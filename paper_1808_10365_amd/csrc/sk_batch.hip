@@ -141,7 +141,7 @@ __global__ __launch_bounds__(64 * SCAN_MAX_WAVES) void batch_scan_kernel(const B
   const int slices = (a.n_inputs + 63) / 64;
   const int groups = (slices + spw - 1) / spw;
   const int f = (int)(lt / groups);
-  const int w = threadIdx.x >> 6, sub = w / Ws;
+  const int w = wave_id(), sub = w / Ws;
   const int slice = (int)(lt % groups) * spw + sub;   // >= slices: every lane idle, barriers kept
   scan_body_rows(a, f, slice, w % Ws, Ws, lds + sub * Ws * 64);
 }
@@ -172,7 +172,7 @@ __global__ __launch_bounds__(64 * COMBINE_MAX_WAVES) void batch_combine_kernel(
   const int W = P.waves, cpw = COMBINE_MAX_WAVES / W;
   const int groups = (a.n_chunks + cpw - 1) / cpw;
   const int f = (int)(lt / groups);
-  const int w = threadIdx.x >> 6, sub = w / W;
+  const int w = wave_id(), sub = w / W;
   const int k = (int)(lt % groups) * cpw + sub;
   const bool live = sub < cpw && k < a.n_chunks;
   combine_body<4, R, RI, OFF32>(a, k, f, w % W, W, sh[sub < cpw ? sub : 0], live);

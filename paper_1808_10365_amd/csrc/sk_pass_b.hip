@@ -22,13 +22,13 @@ namespace sk {
 template <int R>
 __global__ __launch_bounds__(64 * SCAN_MAX_WAVES) void scan_kernel(PassBArgs a) {
   __shared__ uint32_t lds[SCAN_MAX_WAVES * 64];
-  scan_body<R>(a, blockIdx.y, blockIdx.x, threadIdx.x >> 6, blockDim.x >> 6, lds);
+  scan_body<R>(a, blockIdx.y, blockIdx.x, wave_id(), blockDim.x >> 6, lds);
 }
 
 template <int V, int R, typename RI, bool OFF32>
 __global__ __launch_bounds__(64 * COMBINE_MAX_WAVES) void combine_kernel(PassBArgs a) {
   __shared__ CombineShared sh;
-  combine_body<V, R, RI, OFF32>(a, blockIdx.x, blockIdx.y, threadIdx.x >> 6, blockDim.x >> 6, sh);
+  combine_body<V, R, RI, OFF32>(a, blockIdx.x, blockIdx.y, wave_id(), blockDim.x >> 6, sh);
 }
 
 template <int V, int R>

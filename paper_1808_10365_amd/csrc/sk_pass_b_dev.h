@@ -243,6 +243,12 @@ __device__ __forceinline__ void finish(const PassBArgs& a, int f, int b, double 
   if (a.n_eff) a.n_eff[o] = n;
 }
 
+// Index of the calling wavefront in its workgroup, in a scalar register (the
+// compiler cannot tell on its own that it is the same for every lane, and
+// would keep everything derived from it per lane).
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
+
+// ------------------------------------------------------------------ scan
 // ------------------------------------------------------------------ scan
 
 constexpr int SCAN_MAX_WAVES = 16;
