@@ -32,6 +32,7 @@ struct BatchProb {
   int32_t wide_sums;           // 1: the combine's R1/R2 sums need 64 bits
   double k_sigma, expect_offset, sigma_override;
   uint32_t* pc;                // pass B prefix sums
+  int32_t* cs_buf;             // chunk sums (wide rows, window >= 2; sized for chunks of 2 blocks), or null
   int32_t* hs[2];              // history suffix sums, ping-pong
   const uint8_t* mask;
   int64_t* r1;
@@ -57,7 +58,7 @@ __device__ __forceinline__ PassBArgs make_args(const BatchProb& P, const BatchSt
   PassBArgs a;
   a.s1 = P.a.s1;
   a.s2 = P.a.s2;
-  a.cs = nullptr;
+  a.cs = P.a.cs;
   a.hs = P.hs[S.parity];
   a.hs_next = P.hs[S.parity ^ 1];
   a.pc = P.pc;
@@ -205,19 +206,34 @@ std::string cache_path(const sk_batch_opts* o) {
   return e ? e : "";
 }
 
-// Flat JSON object of "key": integer pairs, one per line.
+// Flat JSON object of "key": integer pairs (any layout; keys hold no
+// escaped quotes). Anything else in the file is skipped.
 std::map<std::string, int> load_cache(const std::string& path) {
   std::map<std::string, int> m;
   if (path.empty()) return m;
   FILE* f = fopen(path.c_str(), "r");
   if (!f) return m;
-  char line[512];
-  while (fgets(line, sizeof line, f)) {
-    char key[400];
-    int v;
-    if (sscanf(line, " \"%399[^\"]\" : %d", key, &v) == 2) m[key] = v;
-  }
+  std::string text;
+  char buf[4096];
+  size_t got;
+  while ((got = fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, got);
   fclose(f);
+  size_t pos = 0;
+  while ((pos = text.find('"', pos)) != std::string::npos) {
+    const size_t end = text.find('"', pos + 1);
+    if (end == std::string::npos) break;
+    const std::string key = text.substr(pos + 1, end - pos - 1);
+    size_t q = end + 1;
+    while (q < text.size() && (text[q] == ' ' || text[q] == '\t' || text[q] == '\n' || text[q] == '\r')) ++q;
+    if (q < text.size() && text[q] == ':') {
+      char* stop = nullptr;
+      const long v = strtol(text.c_str() + q + 1, &stop, 10);
+      if (stop != text.c_str() + q + 1) m[key] = (int)v;
+      pos = stop ? (size_t)(stop - text.c_str()) : q + 1;
+    } else {
+      pos = end + 1;
+    }
+  }
   return m;
 }
 
@@ -304,6 +320,7 @@ static int batch_alloc(sk_batch_s* b, void** p, size_t bytes) {
 // Pass A settings of one problem: rows per load (8, 16) and, for wide rows,
 // consecutive blocks per task.
 static void set_pass_a(BatchProb& P, int rows, int q) {
+  P.a.cs = nullptr;             // set by set_pass_b, which follows
   P.rows = rows;
   P.a.block0 = 0;
   P.a.block_end = P.a.n_blocks;
@@ -312,10 +329,15 @@ static void set_pass_a(BatchProb& P, int rows, int q) {
   P.a.n_tasks = (((int64_t)P.a.n_blocks + P.a.blocks_per_task - 1) / P.a.blocks_per_task) * P.a.chunks;
 }
 
-// Pass B chunk length of one problem.
+// Pass B chunk length of one problem. When pass A's wide-row tasks walk
+// exactly one chunk, they write its S1 total and the scan reads those chunk
+// sums instead of the rows.
 static void set_pass_b(BatchProb& P, int R) {
   P.chunk = R;
   P.n_chunks = (int32_t)((P.a.n_blocks + R - 1) / R);
+  const bool cs = P.cs_buf && P.lpr >= 256 && R >= 2 && P.a.blocks_per_task == R;
+  P.a.cs = cs ? P.cs_buf : nullptr;
+  P.scan_waves = scan_rows_waves(cs ? P.n_chunks : P.a.n_blocks);
 }
 
 static Layout layout(std::vector<BatchProb>& tab) {
@@ -439,11 +461,15 @@ static float time_pass_a_batch(sk_batch_s* b, hipStream_t s) {
 
 // Autotuner. Problems are grouped by class (N, M, F). For each class not in
 // the cache, the class's problems alone (a sub-table) are timed with every
-// candidate: pass A rows per load {8, 16} times blocks per task {1, 2}
-// (wide rows only), then, with the best of those, pass B chunk length
-// {1, 2, 4}. Every candidate's time (ns) and the pick go into the cache, keyed
-// by the device arch and the class; a class found in the cache takes its
-// pick without timing.
+// candidate, best of three launches after one untimed: first pass A alone
+// over rows per load {8, 16} x blocks per task {1, 2, 4} (wide rows; 1 for
+// narrow rows), then whole calls (pass A and pass B) with the best rows and
+// blocks over pass B chunk length {1, 2, 4}, and, for wide rows with a
+// window, with blocks per task equal to the chunk {2, 4} (pass A then hands
+// the scan its chunk sums). The least whole-call time is kept. Every
+// candidate's time (ns) and the pick go into the cache, keyed by the device
+// arch and the class; a class found in the cache takes its pick without
+// timing.
 static int tune_batch(sk_batch_s* b, const std::string& path, hipStream_t s) {
   std::map<std::string, int> cache = load_cache(path);
   std::map<std::string, std::vector<int>> classes;
@@ -479,11 +505,12 @@ static int tune_batch(sk_batch_s* b, const std::string& path, hipStream_t s) {
       std::vector<BatchProb> sub;
       for (int m : members) sub.push_back(b->host[m]);
       const bool wide = sub[0].lpr >= 256;
+      // Step 1: pass A alone over rows per load x blocks per task.
       float best = 1e30f;
       for (int rr : {8, 16}) {
-        for (int qq : {1, 2}) {
+        for (int qq : {1, 2, 4}) {
           if (qq > 1 && !wide) continue;
-          for (BatchProb& P : sub) set_pass_a(P, rr, qq);
+          for (BatchProb& P : sub) { set_pass_a(P, rr, qq); set_pass_b(P, P.chunk); }
           const Layout l = layout(sub);
           if (upload_table(d, sub, l, s) != hipSuccess) {
             rc = SK_ERR_DEVICE;
@@ -497,23 +524,33 @@ static int tune_batch(sk_batch_s* b, const std::string& path, hipStream_t s) {
           cache[ck] = (int)(t * 1e6f);
           if (t < best) { best = t; rows = rr; q = qq; }
         }
+        if (rc) break;
       }
-      for (BatchProb& P : sub) set_pass_a(P, rows, q);
+      // Step 2: whole calls (pass A, then pass B) over the chunk length,
+      // with step 1's pass A, and for wide rows also with tasks of one chunk
+      // (pass A then writes the chunk sums the scan reads).
+      std::vector<std::pair<int, int>> ab;   // (blocks per task, chunk)
+      for (int RR : {1, 2, 4}) ab.push_back({q, RR});
+      if (wide && sub[0].window >= 2)
+        for (int RR : {2, 4})
+          if (RR != q) ab.push_back({RR, RR});
       best = 1e30f;
-      for (int RR : {1, 2, 4}) {
-        for (BatchProb& P : sub) set_pass_b(P, RR);
+      for (const auto& c : ab) {
+        if (rc) break;
+        for (BatchProb& P : sub) { set_pass_a(P, rows, c.first); set_pass_b(P, c.second); }
         const Layout l = layout(sub);
         if (upload_table(d, sub, l, s) != hipSuccess) {
           rc = SK_ERR_DEVICE;
           break;
         }
         const float t = best_time(s, b->d_counter, 3, [&] {
+          launch_pass_a_table(d.probs, (int)sub.size(), l.ta, b->grid_a, b->d_counter, s);
           launch_pass_b_table(d, b->d_state, (int)sub.size(), l, s);
         });
         char ck[320];
-        snprintf(ck, sizeof ck, "%s|B|chunk=%d", key.c_str(), RR);
+        snprintf(ck, sizeof ck, "%s|AB|rows=%d|blocks=%d|chunk=%d", key.c_str(), rows, c.first, c.second);
         cache[ck] = (int)(t * 1e6f);
-        if (t < best) { best = t; R = RR; }
+        if (t < best) { best = t; q = c.first; R = c.second; }
       }
       cache[key + "|pick"] = rows * 100 + q * 10 + R;
       dirty = true;
@@ -595,10 +632,7 @@ int sk_batch_create(const sk_plan_desc* descs, int32_t n, const sk_batch_opts* o
     P.k_sigma = d.k_sigma;
     P.expect_offset = d.expect_offset;
     P.sigma_override = d.sigma_override;
-    set_pass_a(P, 16, 1);
-    set_pass_b(P, pass_b_chunk((int32_t)N, (int32_t)F, B, L));
     P.waves = combine_waves((int32_t)N, 4);
-    P.scan_waves = scan_rows_waves(B);
     P.wide_sums = combine_sums_fit_32((int32_t)N, 4, d.block_len) ? 0 : 1;
     P.mask = nullptr;
     const sk_outputs& o = outs[j];
@@ -613,11 +647,17 @@ int sk_batch_create(const sk_plan_desc* descs, int32_t n, const sk_batch_opts* o
       // Prefix sums for the shortest chunk the autotuner may pick (R = 1).
       if ((rc = batch_alloc(b, &p, pass_b_prefix_bytes((int32_t)N, (int32_t)F, B, 1)))) break;
       P.pc = (uint32_t*)p;
+      if (P.lpr >= 256 && B >= 2) {
+        if ((rc = batch_alloc(b, &p, (size_t)F * (size_t)((B + 1) / 2) * N * 4))) break;
+        P.cs_buf = (int32_t*)p;
+      }
       if ((rc = batch_alloc(b, &p, (size_t)F * P.hist_cap * N * 4))) break;
       P.hs[0] = (int32_t*)p;
       if ((rc = batch_alloc(b, &p, (size_t)F * P.hist_cap * N * 4))) break;
       P.hs[1] = (int32_t*)p;
     }
+    set_pass_a(P, 16, 1);
+    set_pass_b(P, pass_b_chunk((int32_t)N, (int32_t)F, B, L));
     P.r1 = o.r1;
     P.r2 = o.r2;
     P.v = o.v;

@@ -176,7 +176,9 @@ __device__ __forceinline__ void sum_rows(const uint8_t* base, int64_t G, int M, 
 // row's column groups otherwise (task = t.blocks_per_task = 256 / lpb
 // consecutive blocks side by side, lane l on block l / lpb, column group
 // l % lpb). Needs the PassATask fields chunks, blocks_per_task, block0 and
-// block_end set to match.
+// block_end set to match. With wide rows and t.cs set, the task also writes
+// its blocks' S1 total (the chunk sum of pass B chunks of blocks_per_task
+// blocks); narrow rows need t.cs null.
 template <int U>
 __device__ __forceinline__ void pass_a_task_side_by_side(const PassATask& t, int lpb, int64_t task,
                                                          const LanePackedLut& lut) {
@@ -202,6 +204,10 @@ __device__ __forceinline__ void pass_a_task_side_by_side(const PassATask& t, int
   const int N = t.n_inputs, B = t.n_blocks;
   const int64_t col = (int64_t)g * VEC;
   const int64_t f = col / N, i = col % N;
+  const int64_t b_first = b;
+  uint32_t c[VEC];
+#pragma unroll
+  for (int k = 0; k < VEC; ++k) c[k] = 0;
   for (; b < b_end; ++b) {
     uint32_t s1[VEC], s2[VEC];
 #pragma unroll
@@ -214,6 +220,17 @@ __device__ __forceinline__ void pass_a_task_side_by_side(const PassATask& t, int
       *reinterpret_cast<u32x4*>(d1 + k) = u32x4{s1[k], s1[k + 1], s1[k + 2], s1[k + 3]};
       *reinterpret_cast<u32x4*>(d2 + k) = u32x4{s2[k], s2[k + 1], s2[k + 2], s2[k + 3]};
     }
+#pragma unroll
+    for (int k = 0; k < VEC; ++k) c[k] += s1[k];
+  }
+  if (lpb >= 256 && t.cs) {
+    // S1 over the task's blocks (wide rows): the chunk sums the prefix scan
+    // reads instead of the rows when the task's blocks are one pass B chunk.
+    const int Q = t.blocks_per_task;
+    const int64_t nk = (t.n_blocks + Q - 1) / Q;
+    int32_t* d = t.cs + (f * nk + (b_first - t.block0) / Q) * N + i;
+#pragma unroll
+    for (int k = 0; k < VEC; k += 4) *reinterpret_cast<u32x4*>(d + k) = u32x4{c[k], c[k + 1], c[k + 2], c[k + 3]};
   }
 }
 

@@ -328,29 +328,33 @@ __device__ __forceinline__ void scan_body(const PassBArgs& a, int f, int slice, 
 }
 
 // The same scan for a chunk length known only at run time (the batched
-// kernel's problems differ in it): each lane holds SCAN_ROWS rows of S1 per
-// round and writes its running sum at every chunk end, so the registers do
-// not depend on the chunk length. Rounds are SCAN_ROWS W rows; R (a power of
-// two) divides SCAN_ROWS. The prefix values are exact integers mod 2^32,
-// equal to scan_body's.
+// kernel's problems differ in it): each lane holds SCAN_ROWS units (rows of
+// S1, or pass A's chunk sums) per round and writes its running sum at every
+// chunk end, so the registers do not depend on the chunk length. Rounds are
+// SCAN_ROWS W units; R (a power of two) divides SCAN_ROWS. The prefix values
+// are exact integers mod 2^32, equal to scan_body's.
 constexpr int SCAN_ROWS = 32;
 
 __device__ __forceinline__ void scan_body_rows(const PassBArgs& a, int f, int slice, int w, int W, uint32_t* lds) {
-  const int R = a.chunk, lgR = __builtin_ctz((unsigned)a.chunk);
+  // Units: the chunk sums from pass A when the call has them (every unit
+  // ends a chunk), else the rows of S1 (a chunk ends every R rows).
+  const int nk = a.n_chunks, B = a.n_blocks;
+  const int U = a.cs ? nk : B;
+  const int R = a.cs ? 1 : a.chunk, lgR = __builtin_ctz((unsigned)R);
   const int lane = threadIdx.x & 63;
   const int i = slice * 64 + lane;
   const bool active = i < a.n_inputs;
-  const int nk = a.n_chunks, B = a.n_blocks;
   const int64_t rowN = a.n_inputs;
   uint32_t* pc = a.pc + (int64_t)f * (nk + 1) * rowN + i;
   if (w == 0 && active) pc[0] = 0u;
+  const int32_t* src = a.cs ? a.cs + (int64_t)f * nk * rowN + i : a.s1 + (int64_t)f * B * rowN + i;
   uint32_t carry = 0;
-  for (int base = 0; base < B; base += SCAN_ROWS * W) {
+  for (int base = 0; base < U; base += SCAN_ROWS * W) {
     const int r0 = base + w * SCAN_ROWS;
     uint32_t x[SCAN_ROWS];
-    const int32_t* p = a.s1 + ((int64_t)f * B + r0) * rowN + i;
+    const int32_t* p = src + (int64_t)r0 * rowN;
 #pragma unroll
-    for (int r = 0; r < SCAN_ROWS; ++r) x[r] = (active && r0 + r < B) ? (uint32_t)p[(int64_t)r * rowN] : 0u;
+    for (int r = 0; r < SCAN_ROWS; ++r) x[r] = (active && r0 + r < U) ? (uint32_t)p[(int64_t)r * rowN] : 0u;
     uint32_t tot = 0;
 #pragma unroll
     for (int r = 0; r < SCAN_ROWS; ++r) tot += x[r];
@@ -368,8 +372,8 @@ __device__ __forceinline__ void scan_body_rows(const PassBArgs& a, int f, int sl
       for (int r = 0; r < SCAN_ROWS; ++r) {
         off += x[r];
         const int row = r0 + r;
-        // Chunk c ends at row c R + R - 1, or at B - 1 for a short last chunk.
-        if (row < B && (((row + 1) & (R - 1)) == 0 || row == B - 1)) pc[(int64_t)((row + R) >> lgR) * rowN] = off;
+        // Chunk c ends at unit c R + R - 1, or at U - 1 for a short last chunk.
+        if (row < U && (((row + 1) & (R - 1)) == 0 || row == U - 1)) pc[(int64_t)((row + R) >> lgR) * rowN] = off;
       }
     }
     __syncthreads();
