@@ -318,6 +318,7 @@ def config_bench(name, dev, steps, warmup, autotune=True):
         res.update({"GBps": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
                     "pass_a_roofline": {"achieved": round(a_gbs, 1), "frac": round(a_gbs / HBM_PEAK_GBS, 4),
                                         "algorithmic_bytes_per_launch": a_bytes,
+                                        "traffic": traffic_from_profile(name, a_bytes),
                                         "note": "input bytes + 8 B of S1/S2 per (channel, block, input) over the "
                                                 "pass A kernel time"}})
     plan.close()

@@ -6,15 +6,15 @@ Reads the SQLite database rocprofv3 writes (``-d DIR -o run``) and prints:
   min, max, total) from the kernel trace; with ``--calls`` also the
   batched form's graph calls (a ``batch_pass_a_kernel`` dispatch followed
   by the batched scan / combine kernels up to ``batch_state_kernel``),
-  grouped by pass A duration class, so the autotuner's trial launches are
-  kept apart from the calls themselves;
+  grouped by their kernel sequence (the autotuner's trial launches, which
+  never end in the state kernel, are not counted as calls);
 * ``counters FETCH_DIR WRITE_DIR``: FETCH_SIZE and WRITE_SIZE per dispatch
   (KiB), scaled to bytes by what the same counters read for one device copy
   of ``--copy-bytes`` bytes (the ``__amd_rocclr_copyBuffer`` dispatch of
   ``bench.py --copy-probe-mib``);
 * ``pmc DIR``: mean per dispatch of every counter collected, per kernel.
 
-Usage: ``python -m paper_1808_10365_amd.rocprof_summary trace DIR [--calls]``.
+Usage: ``python -m paper_1808_10365_amd.rocprof_summary trace DIR [--calls] [--include REGEX]``.
 """
 from __future__ import annotations
 
@@ -23,6 +23,7 @@ import collections
 import glob
 import json
 import os
+import re
 import sqlite3
 import statistics
 import sys
@@ -45,11 +46,13 @@ def kernel_rows(d: str):
     return list(con.execute("select name, start, end from kernels order by start"))
 
 
-def trace(d: str, calls: bool = False) -> str:
+def trace(d: str, calls: bool = False, include: str = "") -> str:
     rows = kernel_rows(d)
     per = collections.defaultdict(list)
+    pat = re.compile(include) if include else None
     for n, s, e in rows:
-        per[n].append((e - s) / 1e3)
+        if pat is None or pat.search(n):
+            per[n].append((e - s) / 1e3)
     out = [f"{'kernel':70s} {'n':>5s} {'avg_us':>10s} {'med_us':>10s} {'min_us':>10s} {'max_us':>10s} {'total_ms':>10s}"]
     for n, v in sorted(per.items(), key=lambda kv: -sum(kv[1])):
         out.append(f"{_short(n):70s} {len(v):5d} {statistics.fmean(v):10.2f} {statistics.median(v):10.2f} "
@@ -63,18 +66,19 @@ def trace(d: str, calls: bool = False) -> str:
             if "batch_pass_a_kernel" in rows[i][0] and i + 1 < len(rows) and \
                     ("batch_scan_kernel" in rows[i + 1][0] or "batch_combine_kernel" in rows[i + 1][0]):
                 j = i + 1
-                while j < len(rows) and "batch_state_kernel" not in rows[j][0]:
+                while j < len(rows) and "batch_state_kernel" not in rows[j][0] and \
+                        "batch_pass_a_kernel" not in rows[j][0]:
                     j += 1
-                if j < len(rows):
+                if j < len(rows) and "batch_state_kernel" in rows[j][0]:
                     seqs.append(rows[i:j + 1])
                     i = j + 1
                     continue
             i += 1
         groups = collections.defaultdict(list)
         for sq in seqs:
-            pa = (sq[0][2] - sq[0][1]) / 1e3
-            groups[len(sq), round(pa, -2)].append(sq)
-        for (n_k, _), gs in sorted(groups.items(), key=lambda kv: kv[0]):
+            groups[tuple(k[0] for k in sq)].append(sq)
+        for names_k, gs in sorted(groups.items(), key=lambda kv: (len(kv[0]), kv[0])):
+            n_k = len(names_k)
             pa = [(g[0][2] - g[0][1]) / 1e3 for g in gs]
             pb = [(g[-1][1] - g[1][1]) / 1e3 for g in gs]
             wall = [(g[-1][2] - g[0][1]) / 1e3 for g in gs]
@@ -146,6 +150,7 @@ def main(argv=None):
     t = sub.add_parser("trace")
     t.add_argument("dir")
     t.add_argument("--calls", action="store_true")
+    t.add_argument("--include", default="", help="only kernels whose name matches this regular expression")
     c = sub.add_parser("counters")
     c.add_argument("fetch_dir")
     c.add_argument("write_dir")
@@ -155,7 +160,7 @@ def main(argv=None):
     p.add_argument("dir")
     a = ap.parse_args(argv)
     if a.cmd == "trace":
-        print(trace(a.dir, a.calls))
+        print(trace(a.dir, a.calls, a.include))
     elif a.cmd == "counters":
         r = counters(a.fetch_dir, a.write_dir, a.copy_bytes)
         print(json.dumps(r, indent=1) if a.json else counters_text(r))
