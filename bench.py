@@ -502,19 +502,28 @@ def serving_bench(args, dev):
             tickets.append((j, a, t))
         srv.drain()
         lat, busy = [], srv.stats()
+        wait, run_t = [], []
         t_first, t_last = None, None
         for j, a, t in tickets:
             r = srv.poll(t)
             assert r.status == 0
             lat.append(r.t_done - sched[j])
+            wait.append(r.t_admit - sched[j])
+            run_t.append(r.t_done - r.t_admit)
             t_last = r.t_done if t_last is None else max(t_last, r.t_done)
         span = t_last - sched[0]
         nbytes = sum(frame_bytes[a] for _, a, _ in tickets)
         srv.close()
         lat = np.array(lat) * 1e3
+        wait = np.array(wait) * 1e3
+        run_t = np.array(run_t) * 1e3
         return {"offered_frames_per_s": round(rate_hz, 1) if rate_hz > 0 else "saturating burst",
                 "frames": n_frames, "p50_ms": round(float(np.percentile(lat, 50)), 4),
                 "p99_ms": round(float(np.percentile(lat, 99)), 4), "mean_ms": round(float(lat.mean()), 4),
+                "arrival_to_admit_ms": {"p50": round(float(np.percentile(wait, 50)), 4),
+                                        "p99": round(float(np.percentile(wait, 99)), 4)},
+                "admit_to_done_ms": {"p50": round(float(np.percentile(run_t, 50)), 4),
+                                     "p99": round(float(np.percentile(run_t, 99)), 4)},
                 "achieved_GBps": round(nbytes / span / 1e9, 1), "frames_per_s": round(n_frames / span, 1),
                 "peak_inflight": int(busy.peak_inflight)}
 
@@ -524,6 +533,9 @@ def serving_bench(args, dev):
                        "block_len": a["w"].block_len, "norm_window_blocks": a["w"].norm_window,
                        "frame_bytes": a["w"].nbytes} for a in arrays],
            "arrival": "Poisson, arrays chosen 50/50, frames resident in HBM on arrival",
+           "latency_parts": "arrival_to_admit: scheduled arrival to the dispatcher admitting the frame (host "
+                            "submit loop, queueing, admission); admit_to_done: admission to the host observing "
+                            "completion (device work, sharing the GPU with other frames in flight, event poll)",
            "saturated": sat, "runs": []}
     for load in [float(v) for v in args.serving_loads.split(",") if v]:
         res["runs"].append(dict(load=load, **run(load * cap, args.serving_frames, seed=int(load * 100))))

@@ -261,6 +261,37 @@ def test_state_reset_and_continuation():
         q.import_state(p.export_state())
 
 
+# ----------------------------------------------------------------------------- size limits
+
+def test_max_inputs():
+    # N = 16384, the largest a plan accepts: each combine wavefront walks 8
+    # groups of 256 inputs (8 wavefronts per chunk) and the raw sums need 64
+    # bits; wide rows of 2048 column groups in pass A.
+    N, F, M, B, L = 16384, 2, 64, 13, 5
+    w = synth.Workload("maxn", N, F, M * B, M, 61, np.random.default_rng(3).uniform(1.5, 3.5, N), [])
+    both(synth.generate(w, nthreads=4), M, L, what="N = 16384")
+
+
+def test_window_much_longer_than_calls():
+    # L = 2^12 blocks of M = 16 (window power sum 2^12 * 16 * 128 = 2^23), in
+    # calls of 40 blocks: the history is carried for 100 calls before the
+    # window fills, then slides; every call is checked against the oracle
+    # over the whole stream at the end.
+    N, F, M, B, L, calls = 32, 2, 16, 40, 1 << 12, 110
+    T = M * B
+    w = synth.Workload("longw", N, F, calls * T, M, 62, np.random.default_rng(4).uniform(1.5, 3.5, N), [])
+    x = synth.generate(w, nthreads=4)
+    _say(f"case long window: N={N} F={F} M={M} L={L}, {calls} calls of {B} blocks")
+    plan = sk.Plan(N, F, T, M, norm_window=L, k_sigma=5.0)
+    xd = torch.from_numpy(x).to(DEV)
+    outs = [plan.compute(xd[k * T:(k + 1) * T], want=sk.ALL_OUTPUTS) for k in range(calls)]
+    torch.cuda.synchronize()
+    cat = {k: torch.cat([getattr(o, k).cpu() for o in outs], dim=1) for k in sk.ALL_OUTPUTS}
+    plan.close()
+    ref = oracle.sk(x, M, L, 0, 5.0, 0.0, 0.0)
+    check_result(SimpleNamespace(**cat), ref, M, L, 0, 5.0, 0.0, 0.0, what="long window")
+
+
 # ----------------------------------------------------------------------------- full-size workloads
 
 def _workload_parity(w, L, reps=1):
