@@ -348,7 +348,8 @@ static Layout layout(std::vector<BatchProb>& tab) {
     l.ta += P.a.n_tasks;
     P.sc_begin = l.tsc;
     const int slices = (P.a.n_inputs + 63) / 64, spw = SCAN_MAX_WAVES / P.scan_waves;
-    P.sc_count = (P.window >= 2 && P.a.n_blocks > 0) ? F * ((slices + spw - 1) / spw) : 0;
+    P.sc_count = (P.a.n_blocks > 0 && pass_b_needs_scan(P.window, P.chunk, P.a.n_blocks))
+                     ? F * ((slices + spw - 1) / spw) : 0;
     l.tsc += P.sc_count;
     if (!combine_offsets_fit_32(P.a.n_inputs, P.a.n_blocks, P.n_chunks, P.hist_cap)) l.off32 = false;
   }

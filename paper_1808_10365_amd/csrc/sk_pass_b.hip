@@ -60,7 +60,7 @@ int launch_pass_b(const PassBArgs& a, hipStream_t s, PassEvents ev) {
   if (a.n_blocks <= 0) return SK_OK;
   const int F = a.n_channels;
   hipEvent_t start = ev.start;
-  if (a.window >= 2) {
+  if (pass_b_needs_scan(a.window, a.chunk, a.n_blocks)) {
     const dim3 grid((a.n_inputs + 63) / 64, F), wg(64 * scan_waves(a.n_chunks));
     switch (a.chunk) {
       case 1: launch_kernel(scan_kernel<1>, grid, wg, 0, s, start, nullptr, a); break;

@@ -397,6 +397,15 @@ __host__ __device__ __forceinline__ int scan_rows_waves(int64_t n_blocks) {
   return W;
 }
 
+// Whether a call needs the prefix scan. With a window of at most one chunk
+// (L <= R) no combine workgroup reads prefix sums: a window start lies in the
+// chunk before, as edge rows. When the call also spans the window
+// (B >= L - 1) no older history is carried either, and the combine forms the
+// next history's suffix sums from the rows it reads.
+__host__ __device__ __forceinline__ bool pass_b_needs_scan(int window, int chunk, int64_t n_blocks) {
+  return window >= 2 && !(window <= chunk && n_blocks >= window - 1);
+}
+
 // ------------------------------------------------------------------ combine
 
 constexpr int COMBINE_MAX_WAVES = 8;
@@ -449,6 +458,7 @@ __device__ __forceinline__ void combine_body(const PassBArgs& a, int k, int f, i
   // are edge rows, a subset of the R - 1 old rows [wa, wa + R - 1).
   const int kc = wa <= 0 ? 0 : (wa + R - 1) / R;
   const bool use_pc = L >= 2 && kc < k;
+  const bool scan_free = L >= 2 && !pass_b_needs_scan(L, R, B);   // no prefix sums this call
   const int edges = L >= 2 && wa > 0 ? (kc * R < b0 ? kc * R : b0) - wa : 0;
   const int hn = a.hist_next_len;
   const int tail_from = B - hn;                       // first position of the next history
@@ -513,11 +523,36 @@ __device__ __forceinline__ void combine_body(const PassBArgs& a, int k, int f, i
       } else {
         zero(hsv[0]);
       }
-      if ((use_pc || tail) && k > 0) pck.load(elem_at<OFF32>(pcc, (int64_t)k * N + il));
+      if (!scan_free && (use_pc || tail) && k > 0) pck.load(elem_at<OFF32>(pcc, (int64_t)k * N + il));
       else zero(pck);
       if (use_pc && kc > 0) pcl.load(elem_at<OFF32>(pcc, (int64_t)kc * N + il));
       else zero(pcl);
-      if (tail) pct.load(elem_at<OFF32>(pcc, (int64_t)a.n_chunks * N + il));
+      if (tail && !scan_free) pct.load(elem_at<OFF32>(pcc, (int64_t)a.n_chunks * N + il));
+      if (tail && scan_free) {
+        // S1 from the chunk's first block to the end of the call: its own rows
+        // plus the at most R - 2 rows after it (pck is zero, so the next
+        // history's suffix sums below come out as pct minus the rows before).
+        IVec<V> after;
+        zero(after);
+#pragma unroll
+        for (int j = 0; j < RO; ++j) {
+          const int y = b0 + nb + j;
+          if (R > 1 && y < B) {
+            IVec<V> r;
+            r.load(elem_at<OFF32>(s1c, (int64_t)y * N + il));
+#pragma unroll
+            for (int q = 0; q < V; ++q) after.v[q] = (int32_t)((uint32_t)after.v[q] + (uint32_t)r.v[q]);
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < V; ++q) {
+          uint32_t t = (uint32_t)after.v[q];
+#pragma unroll
+          for (int j = 0; j < R; ++j)
+            if (j < nb) t += (uint32_t)x1[j].v[q];
+          pct.v[q] = (int32_t)t;
+        }
+      }
     }
     uint32_t use = active ? (1u << V) - 1 : 0u;
     if (a.mask) {

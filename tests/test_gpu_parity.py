@@ -396,6 +396,44 @@ def test_pass_b_tiles(vec, N, L):
         assert np.array_equal(a, b, equal_nan=a.dtype.kind == "f"), name
 
 
+@pytest.mark.parametrize("L", [2, 3, 4])
+def test_pass_b_small_window_without_scan(L):
+    # Windows of at most one chunk (L <= R) in calls at least as long as the
+    # window skip the prefix scan: the combine takes the window start from
+    # edge rows and the next history's suffix sums from the rows, including
+    # the rows of the next chunk when the history starts in an earlier one
+    # (calls of 6, 5, 7, 3 and 9 blocks at R = 4). One plan per chunk length,
+    # carried from call to call; R = 1 (which scans) is the reference, bit
+    # for bit, and the oracle checks all of them.
+    N, F, M = 320, 2, 16
+    cuts = [6, 5, 7, 3, 9]
+    x = synth.generate(synth.Workload("sw", N, F, sum(cuts) * M, M, 70 + L, np.full(N, 2.4), []), nthreads=2)
+    ref = oracle.sk(x, M, L)
+    res = {}
+    for R in (1, 2, 4):
+        plans = {c: sk.Plan(N, F, c * M, M, norm_window=L) for c in set(cuts)}
+        for p in plans.values():
+            p.set_pass_b_tile(R, 0)
+        outs, t0, state = [], 0, None
+        for c in cuts:
+            p = plans[c]
+            if state is not None:
+                p.import_state(state)
+            outs.append(p.compute(torch.from_numpy(x[t0:t0 + c * M].copy()).to(DEV), want=sk.ALL_OUTPUTS))
+            torch.cuda.synchronize()
+            state = p.export_state()
+            t0 += c * M
+        cat = {name: torch.cat([getattr(o, name) for o in outs], dim=1) for name in sk.ALL_OUTPUTS}
+        check_result(SimpleNamespace(**cat), ref, M, L, what=f"small window R={R} L={L}")
+        res[R] = cat
+        for p in plans.values():
+            p.close()
+    for R in (2, 4):
+        for name in sk.ALL_OUTPUTS:
+            a, b = res[1][name].cpu().numpy(), res[R][name].cpu().numpy()
+            assert np.array_equal(a, b, equal_nan=a.dtype.kind == "f"), (R, name)
+
+
 @pytest.mark.parametrize("R", [1, 2, 4])
 @pytest.mark.parametrize("L", [2, 7, 256])
 def test_pass_b_one_plan_many_calls(R, L):
