@@ -450,10 +450,11 @@ class Batch:
     """Many independent problems in one graph launch per call (``sk_batch_t``).
 
     ``plans`` is a list of dicts with the Plan keyword arguments; ``inputs`` the
-    device tensors [T][F][N]; outputs are allocated here (all kinds)."""
+    device tensors [T][F][N]; the outputs named in ``want`` are allocated here
+    (the others are not computed)."""
 
     def __init__(self, plans, inputs, autotune: bool = True, use_graph: bool = True,
-                 tune_cache: Optional[str] = None):
+                 tune_cache: Optional[str] = None, want: Sequence[str] = DEFAULT_OUTPUTS):
         self._lib = load_library()
         n = len(plans)
         if n < 1 or len(inputs) != n:
@@ -470,15 +471,9 @@ class Batch:
             T, F, N, M = d.n_samples, d.n_channels, d.n_inputs, d.block_len
             _device_tensor(x, f"input {j}", torch.uint8, (T, F, N), self.device_index)
             B = T // M
-            r = Result(torch.empty((F, B, N), dtype=torch.int32, device=x.device),
-                       torch.empty((F, B, N), dtype=torch.int32, device=x.device),
-                       torch.empty((F, B), dtype=torch.int64, device=x.device),
-                       torch.empty((F, B), dtype=torch.int64, device=x.device),
-                       torch.empty((F, B), dtype=torch.float32, device=x.device),
-                       torch.empty((F, B), dtype=torch.uint8, device=x.device),
-                       torch.empty((F, B), dtype=torch.int32, device=x.device),
-                       torch.empty((F, B, N), dtype=torch.float32, device=x.device),
-                       torch.empty((F, B), dtype=torch.float32, device=x.device))
+            specs = _output_specs(F, B, N)
+            r = Result(*[torch.empty(specs[k][0], dtype=specs[k][1], device=x.device) if k in want else None
+                         for k in ALL_OUTPUTS])
             self.outputs.append(r)
             outs[j] = Outputs(*[_ptr(getattr(r, k)) for k in ALL_OUTPUTS])
         self._inputs = list(inputs)

@@ -59,7 +59,7 @@ def test_batch_two_calls_match_oracle_and_plans(graph, autotune, tmp_path):
     first = [torch.from_numpy(np.ascontiguousarray(x[:kw["n_samples"]])).to(DEV) for x, (_, kw) in zip(xs, probs)]
     second = [torch.from_numpy(np.ascontiguousarray(x[kw["n_samples"]:])).to(DEV) for x, (_, kw) in zip(xs, probs)]
     batch = sk.Batch([kw for _, kw in probs], first, autotune=autotune, use_graph=graph,
-                     tune_cache=str(tmp_path / "tune.json"))
+                     tune_cache=str(tmp_path / "tune.json"), want=sk.ALL_OUTPUTS)
     plans = [sk.Plan(**kw) for _, kw in probs]
     res_batch, res_plan = [], []
     for inputs in (first, second):
@@ -138,7 +138,8 @@ def test_batch_tiles_and_cache(tmp_path):
 
 
 def test_batch_wide_and_narrow_rows(tmp_path):
-    # Rows of 512 column groups (two 256-lane chunks per block), of 1 group
+    # Default outputs (no SK_i or significance computed). Rows of 512 column
+    # groups (two 256-lane chunks per block), of 1 group
     # (256 blocks side by side per workgroup) and of 48 groups (a block row
     # padded to 64 lanes), with a block count that leaves a partial last task.
     shapes = [(2048, 4, 64 * 9, 64, 3), (16, 1, 16 * 301, 16, 4), (256, 3, 32 * 45, 32, 2)]
@@ -173,7 +174,7 @@ def test_batch_time_pass_a_leaves_calls_intact(tmp_path):
     first = [torch.from_numpy(np.ascontiguousarray(x[:kw["n_samples"]])).to(DEV) for x, (_, kw) in zip(xs, probs)]
     second = [torch.from_numpy(np.ascontiguousarray(x[kw["n_samples"]:])).to(DEV) for x, (_, kw) in zip(xs, probs)]
     batch = sk.Batch([kw for _, kw in probs], first, autotune=False, use_graph=True,
-                     tune_cache=str(tmp_path / "tune.json"))
+                     tune_cache=str(tmp_path / "tune.json"), want=sk.ALL_OUTPUTS)
     res = []
     for call, inputs in enumerate((first, second)):
         outs = batch.compute(inputs)
@@ -219,7 +220,7 @@ def test_batch_chunk_sums_from_pass_a(q, tmp_path):
         probs.append(dict(n_inputs=N, n_channels=F, n_samples=M * B, block_len=M, norm_window=L, k_sigma=4.5))
     first = [torch.from_numpy(np.ascontiguousarray(x[:kw["n_samples"]])).to(DEV) for x, kw in zip(xs, probs)]
     second = [torch.from_numpy(np.ascontiguousarray(x[kw["n_samples"]:])).to(DEV) for x, kw in zip(xs, probs)]
-    batch = sk.Batch(probs, first, autotune=True, use_graph=True, tune_cache=str(path))
+    batch = sk.Batch(probs, first, autotune=True, use_graph=True, tune_cache=str(path), want=sk.ALL_OUTPUTS)
     for j in range(len(probs)):
         t = batch.tuning(j)
         print("problem", j, t, flush=True)

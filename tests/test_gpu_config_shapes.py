@@ -60,7 +60,7 @@ def test_batched_draw_two_calls():
     assert any(w.block_len == 1024 for w in ws) and any(w.n_inputs == 2048 for w in ws)
     firsts = [torch.from_numpy(x[:w.n_samples]).to(DEV) for x, w in zip(streams, ws)]
     seconds = [torch.from_numpy(x[w.n_samples:]).to(DEV) for x, w in zip(streams, ws)]
-    batch = sk.Batch(plans, firsts, autotune=False, use_graph=True)
+    batch = sk.Batch(plans, firsts, autotune=False, use_graph=True, want=sk.ALL_OUTPUTS)
     got = [[], []]
     for call, xs in enumerate((firsts, seconds)):
         outs = batch.compute(xs if call else None)
