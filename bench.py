@@ -268,7 +268,7 @@ def config_bench(name, dev, steps, warmup, autotune=True):
     nbuf = 1 if x.nbytes >= (1 << 30) else min(64, max(4, int(np.ceil(1.0e9 / x.nbytes))))
     xd = [torch.from_numpy(x).to(dev) for _ in range(nbuf)]
     out = plan.alloc_outputs(dev)
-    tuning = plan.autotune(xd[0], reps=2) if autotune else None
+    tuning = plan.autotune(xd[0], reps=3) if autotune else None
     for j in range(warmup):
         plan.compute_into(xd[j % nbuf], out)
     torch.cuda.synchronize()
@@ -590,7 +590,7 @@ def main():
     if not args.no_autotune and not (args.lpr or args.variant >= 0 or args.grid or args.chunk or args.bvec
                                      or args.ablocks):
         t0 = time.perf_counter()
-        tuning = plan.autotune(xd[0], reps=2)
+        tuning = plan.autotune(xd[0], reps=3)
         tuning["seconds"] = round(time.perf_counter() - t0, 3)
         print(f"# plan autotune: {tuning}", file=sys.stderr, flush=True)
 

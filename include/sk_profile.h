@@ -98,7 +98,7 @@ typedef struct {
   int32_t pass_b_chunk;        /* blocks per combine workgroup (1, 2, 4) */
   int32_t pass_b_vec;          /* inputs per combine lane (1 or 4) */
   int32_t candidates;          /* combinations timed */
-  float ms_pass_a, ms_pass_b;  /* mean kernel times of the kept combination */
+  float ms_pass_a, ms_pass_b;  /* pooled kernel-time estimates of the kept combination */
   float ms_library_pass_a, ms_library_pass_b;  /* the library's own choice, same measurement */
 } sk_plan_tuning;
 
@@ -108,8 +108,12 @@ typedef struct {
  * packed-table variants at 1024 and 256 lanes; blocks side by side for
  * narrow rows), crossed with pass B chunk length {1, 2, 4}. Pass B inputs
  * per lane stay as set (they order the FP64 combine). Each combination runs
- * one untimed and `reps` (1..100) timed calls on `stream` without outputs;
- * the kept one has the least mean pass A plus pass B kernel time. The
+ * one untimed and `reps` (1..100) timed calls on `stream` without outputs.
+ * Each pass's time is estimated from every combination that runs that pass
+ * the same way (pass A: its launched variant, lanes, blocks per task and
+ * whether it writes chunk sums; pass B: its chunk length and whether it
+ * reads them), and the kept combination has the least sum of the two
+ * estimates. The
  * normaliser state is exported before and imported after, so a stream in
  * progress continues unchanged; results of later calls do not depend on the
  * choice (integer sums are exact, and the combine's order does not depend on

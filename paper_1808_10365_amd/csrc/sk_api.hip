@@ -398,8 +398,9 @@ extern "C" {
 
 // One call of a plan (the body of sk_compute, arguments checked): pass A,
 // then pass B, with the given dispatch timing events (null: untimed).
+// *chunk_sums (if given) tells whether pass A handed the scan its chunk sums.
 static int plan_call(sk_plan_s* p, const uint8_t* d_packed, const uint8_t* d_mask, const sk_outputs* outs,
-                     hipStream_t s, PassEvents ea, PassEvents eb) {
+                     hipStream_t s, PassEvents ea, PassEvents eb, bool* chunk_sums = nullptr) {
   const int64_t B = p->n_blocks;
   CallBuffers cb;
   cb.s1 = outs->s1 ? outs->s1 : p->s1;
@@ -422,6 +423,7 @@ static int plan_call(sk_plan_s* p, const uint8_t* d_packed, const uint8_t* d_mas
     t.cs = p->cs;
     a.cs = p->cs;
   }
+  if (chunk_sums) *chunk_sums = t.cs != nullptr;
 
   int rc = launch_pass_a(t, c, s, ea);
   if (rc) return rc;
@@ -461,8 +463,8 @@ int sk_compute(sk_plan_t p, const uint8_t* d_packed, const uint8_t* d_mask, cons
 
 // Autotuner of one plan: every candidate (pass A variant and its lanes or
 // blocks per task, pass B chunk length) runs one
-// untimed and `reps` timed calls on d_x; the fastest mean of pass A plus
-// pass B kernel time (dispatch timestamps) is kept. The normaliser state is
+// untimed and `reps` timed calls on d_x; the least pooled estimate of pass A
+// plus pass B kernel time (dispatch timestamps) is kept. The normaliser state is
 // saved before and restored after, so a stream in progress continues as if
 // the tuning calls had not run.
 int sk_plan_autotune(sk_plan_t p, const uint8_t* d_x, int32_t reps, void* stream, sk_plan_tuning* out) {
@@ -512,21 +514,30 @@ int sk_plan_autotune(sk_plan_t p, const uint8_t* d_x, int32_t reps, void* stream
   }
   sk_outputs none;
   memset(&none, 0, sizeof none);
-  float best = 1e30f, best_a = 0.f, best_b = 0.f, lib_a = 0.f, lib_b = 0.f;
-  size_t best_i = 0;
+  // Per candidate: summed pass A and pass B times of its timed calls, and
+  // whether pass A wrote the chunk sums (which changes both passes' work).
+  std::vector<double> sum_a(cands.size(), 0.0), sum_b(cands.size(), 0.0);
+  std::vector<char> with_cs(cands.size(), 0);
+  std::vector<Cand> resolved(cands.size());   // pass A as launched (the library's choice made concrete)
   for (size_t ci = 0; ci < cands.size() && rc == SK_OK; ++ci) {
     const Cand& c = cands[ci];
     p->pass_a_lpr = c.lpr;
     p->pass_a_variant = c.variant;
     p->pass_a_blocks = c.blocks;
     if ((rc = sk_plan_set_pass_b_tile(p, c.chunk, c.vec))) break;
+    {
+      PassATask t;
+      const PassAConfig pc = plan_pass_a_config(p, d_x, &t);
+      resolved[ci] = Cand{pc.variant, pc.lpr, t.blocks_per_task, c.chunk, c.vec};
+    }
     if ((rc = plan_call(p, d_x, nullptr, &none, s, PassEvents(), PassEvents()))) break;
+    bool cs = false;
     for (int r = 0; r < reps && rc == SK_OK; ++r)
       rc = plan_call(p, d_x, nullptr, &none, s, PassEvents{ev[4 * r], ev[4 * r + 1]},
-                     PassEvents{ev[4 * r + 2], ev[4 * r + 3]});
+                     PassEvents{ev[4 * r + 2], ev[4 * r + 3]}, &cs);
     if (rc) break;
+    with_cs[ci] = cs;
     if (hipStreamSynchronize(s) != hipSuccess) { rc = SK_ERR_DEVICE; set_error("autotune: synchronize failed"); break; }
-    float ta = 0.f, tb = 0.f;
     for (int r = 0; r < reps; ++r) {
       float x = 0.f, y = 0.f;
       if (hipEventElapsedTime(&x, ev[4 * r], ev[4 * r + 1]) != hipSuccess ||
@@ -535,13 +546,34 @@ int sk_plan_autotune(sk_plan_t p, const uint8_t* d_x, int32_t reps, void* stream
         set_error("autotune: event timing failed");
         break;
       }
-      ta += x;
-      tb += y;
+      sum_a[ci] += x;
+      sum_b[ci] += y;
     }
-    ta /= reps;
-    tb /= reps;
-    if (c.variant == -1 && c.lpr == 0 && c.blocks == 0 && c.chunk == keep_chunk) { lib_a = ta; lib_b = tb; }
-    if (ta + tb < best) { best = ta + tb; best_i = ci; best_a = ta; best_b = tb; }
+  }
+  // Pooled estimates: pass A's time depends on its own settings (and on
+  // whether it writes chunk sums), pass B's on the chunk length (and on
+  // whether it reads them). Each pass is estimated from every candidate that
+  // shares its settings, so one noisy pass A trial does not decide pass B.
+  float best = 1e30f, best_a = 0.f, best_b = 0.f, lib_a = 0.f, lib_b = 0.f;
+  size_t best_i = 0;
+  if (rc == SK_OK) {
+    auto same_a = [&](size_t i, size_t j) {
+      return resolved[i].variant == resolved[j].variant && resolved[i].lpr == resolved[j].lpr &&
+             resolved[i].blocks == resolved[j].blocks && with_cs[i] == with_cs[j];
+    };
+    auto same_b = [&](size_t i, size_t j) { return cands[i].chunk == cands[j].chunk && with_cs[i] == with_cs[j]; };
+    for (size_t ci = 0; ci < cands.size(); ++ci) {
+      double ta = 0.0, tb = 0.0;
+      int na = 0, nb = 0;
+      for (size_t cj = 0; cj < cands.size(); ++cj) {
+        if (same_a(ci, cj)) { ta += sum_a[cj]; ++na; }
+        if (same_b(ci, cj)) { tb += sum_b[cj]; ++nb; }
+      }
+      const float ea_ms = (float)(ta / ((double)na * reps)), eb_ms = (float)(tb / ((double)nb * reps));
+      const Cand& c = cands[ci];
+      if (c.variant == -1 && c.lpr == 0 && c.blocks == 0 && c.chunk == keep_chunk) { lib_a = ea_ms; lib_b = eb_ms; }
+      if (ea_ms + eb_ms < best) { best = ea_ms + eb_ms; best_i = ci; best_a = ea_ms; best_b = eb_ms; }
+    }
   }
   for (auto& e : ev) (void)hipEventDestroy(e);
   if (rc) {
