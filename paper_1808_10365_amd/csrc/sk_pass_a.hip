@@ -211,14 +211,18 @@ int pass_a_side_by_side_lanes(int64_t col_groups) {
 // registers and stores them only after its last block. With about one task
 // per CU the call becomes a read phase followed by a write phase: mixing
 // the sums' writes into the read stream costs far more than their bytes
-// (CHIME M = 256: 335 against 382 us with a store after each block).
+// (CHIME M = 256: 335 against 382 us with a store after each block). The
+// two wavefronts of each SIMD keep level through SimdBalance.
 template <int Q, int U>
 __global__ __launch_bounds__(512) void pass_a_deferred_kernel(PassATask t) {
   constexpr int VEC = 16;
   __shared__ __attribute__((aligned(16))) uint32_t lut32[LANE_LUT_DWORDS];
+  __shared__ uint32_t simd_of[8], progress[8];
   const int tid = threadIdx.x;
   fill_lane_packed_lut<512>(lut32, tid);
+  simd_balance_post(simd_of, progress, tid);
   __syncthreads();
+  SimdBalance bal = simd_balance_pair(simd_of, progress, 8);
   const LanePackedLut lut{reinterpret_cast<const uint8_t*>(lut32), (uint32_t)(tid & 63) * 4};
   const int M = t.block_len;
   const int64_t G = t.row_bytes;
@@ -232,8 +236,10 @@ __global__ __launch_bounds__(512) void pass_a_deferred_kernel(PassATask t) {
 #pragma unroll
       for (int k = 0; k < VEC; ++k) a1[q][k] = a2[q][k] = 0;
       if (b0 + q < t.block_end)
-        sum_rows_packed<VEC, 1, U>(t.x + (int64_t)(b0 + q) * M * G + (int64_t)g * VEC, G, M, 0, lut, a1[q], a2[q]);
+        sum_rows_packed<VEC, 1, U>(t.x + (int64_t)(b0 + q) * M * G + (int64_t)g * VEC, G, M, 0, lut, a1[q], a2[q],
+                                   bal);
     }
+    __builtin_amdgcn_s_setprio(0);
 #pragma unroll
     for (int q = 0; q < Q; ++q)
       if (b0 + q < t.block_end) store_group<VEC>(t, b0 + q, g, a1[q], a2[q]);

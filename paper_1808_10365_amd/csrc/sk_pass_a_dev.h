@@ -99,11 +99,66 @@ __device__ __forceinline__ void fill_lane_packed_lut(uint32_t* t, int tid) {
   }
 }
 
+// Nothing between packed runs.
+struct NoBalance {
+  __device__ __forceinline__ void operator()() {}
+};
+
+// Wavefronts that share a SIMD do not progress alike: the instruction
+// arbiter favours the older one, so with equal work the younger one ends
+// last and then runs alone, with half the loads in flight, for the end of
+// the kernel (CHIME M = 256, variant 4: the first wavefront of each SIMD
+// ended its reads about 55 us before the second). After every packed run a
+// wavefront posts its progress in LDS and compares it with its partner's
+// (another wavefront of the workgroup on the same SIMD): ahead, it drops to
+// priority 0; level or behind, it takes priority 2. No wavefront waits.
+struct SimdBalance {
+  uint32_t* prog;   // LDS, one word per wavefront of the workgroup
+  int self, partner;
+  uint32_t done;
+  __device__ __forceinline__ void operator()() {
+    ++done;
+    // Every lane stores the same value: no divergent branch.
+    __atomic_store_n(&prog[self], done, __ATOMIC_RELAXED);
+    const uint32_t other = __builtin_amdgcn_readfirstlane(__atomic_load_n(&prog[partner], __ATOMIC_RELAXED));
+    // One asm block for the compare and both priorities, so the compiler's
+    // control flow (and its register allocation) is not split.
+    asm volatile("s_cmp_gt_u32 %0, %1\n\ts_cbranch_scc0 1f\n\ts_setprio 0\n\ts_branch 2f\n1:\n\ts_setprio 2\n2:"
+                 :: "s"(__builtin_amdgcn_readfirstlane(done)), "s"(other) : "scc");
+  }
+};
+
+// SIMD of the calling wavefront (HW_ID bits 5:4).
+__device__ __forceinline__ uint32_t simd_id() {
+  return (uint32_t)__builtin_amdgcn_s_getreg(4 | (4 << 6) | (1 << 11));
+}
+
+// First half of setting up SimdBalance for a workgroup of `waves`
+// wavefronts: each posts its SIMD and zero progress. The caller then
+// synchronises the workgroup before simd_balance_pair.
+__device__ __forceinline__ void simd_balance_post(uint32_t* sid, uint32_t* prog, int tid) {
+  if ((tid & 63) == 0) {
+    sid[tid >> 6] = simd_id();
+    prog[tid >> 6] = 0;
+  }
+}
+
+// Second half: the partner is the first other wavefront on the same SIMD
+// (none: the wavefront is its own partner and always takes priority 2).
+__device__ __forceinline__ SimdBalance simd_balance_pair(const uint32_t* sid, uint32_t* prog, int waves) {
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  int partner = w;
+  for (int j = waves - 1; j >= 0; --j)
+    if (j != w && sid[j] == sid[w]) partner = j;
+  return SimdBalance{prog, w, __builtin_amdgcn_readfirstlane(partner), 0u};
+}
+
 // Rows ph, ph + RP, ... (< M) of this lane with the packed table, in loads of
-// U rows, unpacking every PACK_ROWS rows.
-template <int VEC, int RP, int U>
+// U rows, unpacking every PACK_ROWS rows; `bal` runs after every packed run.
+template <int VEC, int RP, int U, typename Balance = NoBalance>
 __device__ __forceinline__ void sum_rows_packed(const uint8_t* base, int64_t G, int M, int ph,
-                                                const LanePackedLut& lut, uint32_t* s1, uint32_t* s2) {
+                                                const LanePackedLut& lut, uint32_t* s1, uint32_t* s2,
+                                                Balance&& bal = Balance()) {
   static_assert(VEC >= 4 && U % 2 == 0 && PACK_ROWS % U == 0, "whole row pairs per packed run");
   const int nrow = ph < M ? (M - ph + RP - 1) / RP : 0;
   const int64_t step = (int64_t)RP * G;
@@ -137,6 +192,7 @@ __device__ __forceinline__ void sum_rows_packed(const uint8_t* base, int64_t G, 
       s1[k] += acc[k] & ((1u << PACK_SHIFT) - 1);
       s2[k] += acc[k] >> PACK_SHIFT;
     }
+    bal();
   }
 }
 
