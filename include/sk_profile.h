@@ -121,6 +121,22 @@ typedef struct {
  * the plan. `out` may be NULL. */
 int sk_plan_autotune(sk_plan_t plan, const uint8_t* d_x, int32_t reps, void* stream, sk_plan_tuning* out);
 
+/* Per-wavefront timeline of pass A (diagnostic). Runs the plan's pass A once
+ * on d_x ([T][F][N] bytes), writing the sums into the plan's own S1/S2
+ * buffers (pass B does not run; the normaliser state is untouched). The
+ * plan's pass A must be the deferred-store variant (SK_PASS_A_DEFERRED, as
+ * the library picks for CHIME-like rows) with one workgroup per task. Lane 0
+ * of every wavefront writes 6 uint64 at d_out[6 (8 workgroup + wavefront)]:
+ * the GPU real-time clock (100 MHz) at its start, after its last read and
+ * after its stores completed, then its XCD id, its HW_ID register and its
+ * SIMD. simd_balance: 1 as the library runs (the wavefronts of each SIMD
+ * kept level by priority), 0 left to the instruction arbiter (needs 4 blocks
+ * per task), for comparison. d_out holds cap records (device memory); *n_waves
+ * receives the number written. Asynchronous on `stream`. SK_ERR_INVALID_ARG
+ * for another variant, too small a cap, or bad arguments. */
+int sk_plan_pass_a_timeline(sk_plan_t plan, const uint8_t* d_x, int32_t simd_balance, uint64_t* d_out, int64_t cap,
+                            int64_t* n_waves, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -128,6 +128,7 @@ def load_library():
     lib.sk_batch_get_state.argtypes = [VP, I32, ctypes.POINTER(I32)]
     lib.sk_read_probe.argtypes = [VP, I64, I32, VP, VP]
     lib.sk_plan_set_pass_a_blocks.argtypes = [VP, I32]
+    lib.sk_plan_pass_a_timeline.argtypes = [VP, VP, I32, VP, I64, ctypes.POINTER(I64), VP]
     lib.sk_server_now.restype = ctypes.c_double
     lib.sk_server_create.argtypes = [ctypes.POINTER(ServerDesc), ctypes.POINTER(VP)]
     lib.sk_server_add_array.argtypes = [VP, ctypes.POINTER(PlanDesc), ctypes.POINTER(I32)]
@@ -157,7 +158,7 @@ def load_library():
                  "sk_state_reset", "sk_state_size", "sk_state_export", "sk_state_import",
                  "sk_digitised_expectation", "sk_plan_set_pass_a_tile", "sk_plan_get_pass_a_tile",
                  "sk_profile_enable", "sk_profile_set_stride", "sk_profile_read", "sk_plan_set_pass_a_variant", "sk_read_probe",
-                 "sk_plan_set_pass_a_blocks"):
+                 "sk_plan_set_pass_a_blocks", "sk_plan_pass_a_timeline"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -349,6 +350,23 @@ class Plan:
         lo, hi = ctypes.c_double(), ctypes.c_double()
         _check(self._lib.sk_plan_get_thresholds(self.handle, int(n_eff), ctypes.byref(lo), ctypes.byref(hi)))
         return lo.value, hi.value
+
+    def pass_a_timeline(self, x: torch.Tensor, simd_balance: bool = True,
+                        stream: Optional[torch.cuda.Stream] = None) -> "numpy.ndarray":
+        """Per-wavefront timeline of one pass A launch (``sk_plan_pass_a_timeline``):
+        int64 rows of (start, reads done, end) in 100 MHz clock ticks, XCD id,
+        HW_ID and SIMD. The plan's pass A must be the deferred-store variant."""
+        d = self.desc
+        _device_tensor(x, "x", torch.uint8, (d.n_samples, d.n_channels, d.n_inputs), self.device_index)
+        B = d.n_samples // d.block_len
+        cap = 8 * (B * ((d.n_channels * d.n_inputs // 16 + 511) // 512) + 1)
+        out = torch.zeros((cap, 6), dtype=torch.int64, device=x.device)
+        n = ctypes.c_int64()
+        _check(self._lib.sk_plan_pass_a_timeline(self.handle, ctypes.c_void_p(x.data_ptr()), int(bool(simd_balance)),
+                                                 ctypes.c_void_p(out.data_ptr()), cap, ctypes.byref(n),
+                                                 _stream_handle(stream)))
+        (stream or torch.cuda.current_stream(x.device)).synchronize()
+        return out[:n.value].cpu().numpy()
 
     def set_pass_a_blocks(self, blocks: int):
         """Consecutive blocks per pass A task with the packed-table variants (0: library choice)."""

@@ -209,6 +209,8 @@ static PassAConfig pass_a_config(const sk_plan_desc& d, int64_t B, const PassATu
   t->block_len = d.block_len;
   t->n_blocks = (int32_t)B;
   t->cs = nullptr;
+  t->timeline = nullptr;
+  t->simd_balance = 1;
   PassAConfig c = default_pass_a_config(vec, t->row_bytes, B, d.block_len, u.lpr == 0 && u.variant < 0, u.n_cu);
   if (u.lpr) c.lpr = u.lpr;
   if (u.variant >= 0) c.variant = u.variant;
@@ -606,6 +608,48 @@ int sk_plan_autotune(sk_plan_t p, const uint8_t* d_x, int32_t reps, void* stream
     out->ms_library_pass_b = lib_b;
   }
   return SK_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+int sk_plan_pass_a_timeline(sk_plan_t p, const uint8_t* d_x, int32_t simd_balance, uint64_t* d_out, int64_t cap,
+                            int64_t* n_waves, void* stream) {
+  clear_error();
+  if (!p || !d_x || !d_out || !n_waves || cap < 0 || (simd_balance != 0 && simd_balance != 1)) {
+    set_error("timeline: NULL argument, negative capacity, or simd_balance not 0 or 1");
+    return SK_ERR_INVALID_ARG;
+  }
+  *n_waves = 0;
+  int dev = -1;
+  SK_HIP_TRY(hipGetDevice(&dev));
+  if (dev != p->device) { set_error("plan was created on device %d, current device is %d", p->device, dev); return SK_ERR_INVALID_ARG; }
+  if (p->n_blocks == 0) return SK_OK;
+  PassATask t;
+  const PassAConfig c = plan_pass_a_config(p, d_x, &t);
+  if (!pass_a_deferred(c.vec, c.variant)) {
+    set_error("timeline: the plan's pass A is variant %d, not the deferred-store variant 4", c.variant);
+    return SK_ERR_INVALID_ARG;
+  }
+  if ((int64_t)c.grid != t.n_tasks || (!simd_balance && t.blocks_per_task != 4)) {
+    set_error("timeline: needs one workgroup per task (%d for %lld), and 4 blocks per task without the SIMD balance",
+              c.grid, (long long)t.n_tasks);
+    return SK_ERR_INVALID_ARG;
+  }
+  const int64_t waves = (int64_t)c.grid * 8;
+  if (waves > cap) {
+    set_error("timeline: %lld wavefronts, room for %lld", (long long)waves, (long long)cap);
+    return SK_ERR_INVALID_ARG;
+  }
+  t.x = d_x;
+  t.s1 = p->s1;
+  t.s2 = p->s2;
+  t.timeline = d_out;
+  t.simd_balance = simd_balance;
+  const int rc = launch_pass_a(t, c, (hipStream_t)stream);
+  if (rc == SK_OK) *n_waves = waves;
+  return rc;
 }
 
 }  // extern "C"

@@ -321,6 +321,8 @@ static int batch_alloc(sk_batch_s* b, void** p, size_t bytes) {
 // consecutive blocks per task.
 static void set_pass_a(BatchProb& P, int rows, int q) {
   P.a.cs = nullptr;             // set by set_pass_b, which follows
+  P.a.timeline = nullptr;
+  P.a.simd_balance = 1;
   P.rows = rows;
   P.a.block0 = 0;
   P.a.block_end = P.a.n_blocks;

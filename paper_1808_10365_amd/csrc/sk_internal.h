@@ -49,6 +49,10 @@ struct PassATask {
   int32_t blocks_per_task;  // consecutive blocks one task walks (packed-table variants; else 1)
   int32_t* cs;          // variant 4 only, or null: [F][ceil(B / Q)][N] S1 summed over each
                         // task's Q blocks (the chunk sums of pass B's scan when its R == Q)
+  uint64_t* timeline;   // variant 4 only, or null: 6 words per wavefront (see
+                        // sk_plan_pass_a_timeline), one task per workgroup
+  int32_t simd_balance; // variant 4: 1 = wavefronts of a SIMD kept level (the library's
+                        // setting), 0 = left to the arbiter (timeline comparisons only)
 };
 
 struct PassAConfig {

@@ -213,9 +213,17 @@ int pass_a_side_by_side_lanes(int64_t col_groups) {
 // the sums' writes into the read stream costs far more than their bytes
 // (CHIME M = 256: 335 against 382 us with a store after each block). The
 // two wavefronts of each SIMD keep level through SimdBalance.
-template <int Q, int U>
+//
+// With t.timeline set (one task per workgroup), lane 0 of every wavefront
+// records the real-time clock (100 MHz) at its start, after its reads (the
+// stamp depends on the sums, so it follows the last load) and after its
+// stores have completed, then its XCD and HW_ID registers, at
+// timeline[6 (8 blockIdx.x + wavefront) ...]. BAL = false leaves the
+// wavefronts of a SIMD to the arbiter (for timelines that compare).
+template <int Q, int U, bool BAL = true>
 __global__ __launch_bounds__(512) void pass_a_deferred_kernel(PassATask t) {
   constexpr int VEC = 16;
+  const uint64_t t_start = __builtin_amdgcn_s_memrealtime();
   __shared__ __attribute__((aligned(16))) uint32_t lut32[LANE_LUT_DWORDS];
   __shared__ uint32_t simd_of[8], progress[8];
   const int tid = threadIdx.x;
@@ -223,9 +231,11 @@ __global__ __launch_bounds__(512) void pass_a_deferred_kernel(PassATask t) {
   simd_balance_post(simd_of, progress, tid);
   __syncthreads();
   SimdBalance bal = simd_balance_pair(simd_of, progress, 8);
+  NoBalance arbiter;
   const LanePackedLut lut{reinterpret_cast<const uint8_t*>(lut32), (uint32_t)(tid & 63) * 4};
   const int M = t.block_len;
   const int64_t G = t.row_bytes;
+  uint64_t t_reads = 0;
   for (int64_t task = blockIdx.x; task < t.n_tasks; task += gridDim.x) {
     const int b0 = t.block0 + (int)(task / t.chunks) * Q;
     const int g = (int)(task % t.chunks) * 512 + tid;
@@ -235,9 +245,17 @@ __global__ __launch_bounds__(512) void pass_a_deferred_kernel(PassATask t) {
     for (int q = 0; q < Q; ++q) {
 #pragma unroll
       for (int k = 0; k < VEC; ++k) a1[q][k] = a2[q][k] = 0;
-      if (b0 + q < t.block_end)
-        sum_rows_packed<VEC, 1, U>(t.x + (int64_t)(b0 + q) * M * G + (int64_t)g * VEC, G, M, 0, lut, a1[q], a2[q],
-                                   bal);
+      if (b0 + q < t.block_end) {
+        const uint8_t* base = t.x + (int64_t)(b0 + q) * M * G + (int64_t)g * VEC;
+        if constexpr (BAL) sum_rows_packed<VEC, 1, U>(base, G, M, 0, lut, a1[q], a2[q], bal);
+        else sum_rows_packed<VEC, 1, U>(base, G, M, 0, lut, a1[q], a2[q], arbiter);
+      }
+    }
+    if (t.timeline) {
+      uint32_t dep = 0;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) dep |= a1[q][0] >> 31;
+      t_reads = __builtin_amdgcn_s_memrealtime() + __builtin_amdgcn_readfirstlane(dep);
     }
     __builtin_amdgcn_s_setprio(0);
 #pragma unroll
@@ -260,6 +278,19 @@ __global__ __launch_bounds__(512) void pass_a_deferred_kernel(PassATask t) {
       int32_t* d = t.cs + (f * nk + (b0 - t.block0) / Q) * N + i;
 #pragma unroll
       for (int k = 0; k < VEC; k += 4) *reinterpret_cast<u32x4*>(d + k) = u32x4{c[k], c[k + 1], c[k + 2], c[k + 3]};
+    }
+  }
+  if (t.timeline) {
+    __builtin_amdgcn_s_waitcnt(0);
+    const uint64_t t_end = __builtin_amdgcn_s_memrealtime();
+    if ((tid & 63) == 0) {
+      uint64_t* o = t.timeline + ((int64_t)blockIdx.x * 8 + (tid >> 6)) * 6;
+      o[0] = t_start;
+      o[1] = t_reads;
+      o[2] = t_end;
+      o[3] = (uint32_t)__builtin_amdgcn_s_getreg(20 | (3 << 11));   // XCC_ID bits 3:0
+      o[4] = (uint32_t)__builtin_amdgcn_s_getreg(4 | (31 << 11));   // HW_ID
+      o[5] = simd_id();
     }
   }
 }
@@ -303,7 +334,10 @@ static int launch_vec(const PassATask& t, int lpr, int variant, int grid, hipStr
           case 1: launch_kernel(pass_a_deferred_kernel<1, 16>, g, w512, 0, s, ev.start, ev.stop, t); break;
           case 2: launch_kernel(pass_a_deferred_kernel<2, 16>, g, w512, 0, s, ev.start, ev.stop, t); break;
           case 3: launch_kernel(pass_a_deferred_kernel<3, 16>, g, w512, 0, s, ev.start, ev.stop, t); break;
-          case 4: launch_kernel(pass_a_deferred_kernel<4, 16>, g, w512, 0, s, ev.start, ev.stop, t); break;
+          case 4:
+            if (t.simd_balance) launch_kernel(pass_a_deferred_kernel<4, 16>, g, w512, 0, s, ev.start, ev.stop, t);
+            else launch_kernel(pass_a_deferred_kernel<4, 16, false>, g, w512, 0, s, ev.start, ev.stop, t);
+            break;
           default:
             set_error("pass A: deferred-store variant needs 1..4 blocks per task, got %d", t.blocks_per_task);
             return SK_ERR_INVALID_ARG;
