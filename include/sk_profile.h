@@ -95,6 +95,7 @@ typedef struct {
   int32_t pass_a_variant;      /* 0..4, as SK_PASS_A_* */
   int32_t pass_a_lanes;        /* lanes per row */
   int32_t pass_a_blocks;       /* consecutive blocks per task */
+  int32_t pass_a_chunk_sums;   /* 1: pass A writes the chunk sums the scan reads */
   int32_t pass_b_chunk;        /* blocks per combine workgroup (1, 2, 4) */
   int32_t pass_b_vec;          /* inputs per combine lane (1 or 4) */
   int32_t candidates;          /* combinations timed */
@@ -104,7 +105,8 @@ typedef struct {
 
 /* Time every candidate tile combination of this plan on the device input
  * d_x ([T][F][N] bytes) and keep the fastest: pass A variant (the library's
- * choice; the deferred-store variant at 1, 2 and 4 blocks per task; the
+ * choice; the deferred-store variant at 1, 2 and 4 blocks per task, and
+ * at 2 and 4 without writing the chunk sums for a scan of that chunk; the
  * packed-table variants at 1024 and 256 lanes; blocks side by side for
  * narrow rows), crossed with pass B chunk length {1, 2, 4}. Pass B inputs
  * per lane stay as set (they order the FP64 combine). Each combination runs

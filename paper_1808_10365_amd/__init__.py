@@ -50,7 +50,8 @@ class Outputs(ctypes.Structure):
 
 class PlanTuning(ctypes.Structure):
     _fields_ = [("pass_a_variant", ctypes.c_int32), ("pass_a_lanes", ctypes.c_int32),
-                ("pass_a_blocks", ctypes.c_int32), ("pass_b_chunk", ctypes.c_int32),
+                ("pass_a_blocks", ctypes.c_int32), ("pass_a_chunk_sums", ctypes.c_int32),
+                ("pass_b_chunk", ctypes.c_int32),
                 ("pass_b_vec", ctypes.c_int32), ("candidates", ctypes.c_int32),
                 ("ms_pass_a", ctypes.c_float), ("ms_pass_b", ctypes.c_float),
                 ("ms_library_pass_a", ctypes.c_float), ("ms_library_pass_b", ctypes.c_float)]

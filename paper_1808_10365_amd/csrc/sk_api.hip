@@ -54,6 +54,7 @@ struct sk_plan_s {
   int pass_a_variant = -1; // pass A variant; -1 = heuristic
   int pass_a_grid;         // 0 = one workgroup per task
   int pass_a_blocks = 0;   // consecutive blocks per pass A task (packed variants; 0 = library choice)
+  int chunk_sums = 1;      // pass A hands the scan chunk sums when its tasks are the chunks (autotuner may clear)
   int pass_b_vec;          // 0 = library choice, else 1 or 4 inputs per lane
   int n_cu = 256;          // compute units of the plan's device
   std::vector<hipEvent_t> prof;   // 4 events per recorded call
@@ -420,7 +421,7 @@ static int plan_call(sk_plan_s* p, const uint8_t* d_packed, const uint8_t* d_mas
   t.cs = nullptr;
   PassBArgs a = make_pass_b_args(p->d, B, p->hist_cap, p->chunk, p->pass_b_vec, d_mask, outs, cb, p->thresholds);
   // Pass A tasks of Q = R consecutive blocks hand the scan its chunk sums.
-  if (a.window >= 2 && p->cs && pass_a_deferred(c.vec, c.variant) && t.blocks_per_task == a.chunk &&
+  if (a.window >= 2 && p->cs && p->chunk_sums && pass_a_deferred(c.vec, c.variant) && t.blocks_per_task == a.chunk &&
       (size_t)a.n_channels * a.n_chunks * a.n_inputs * sizeof(int32_t) <= p->cs_bytes) {
     t.cs = p->cs;
     a.cs = p->cs;
@@ -484,27 +485,34 @@ int sk_plan_autotune(sk_plan_t p, const uint8_t* d_x, int32_t reps, void* stream
   std::vector<uint8_t> saved(sbytes);
   if ((rc = sk_state_export(p, saved.data(), sbytes, stream))) return rc;
   const int keep_lpr = p->pass_a_lpr, keep_var = p->pass_a_variant, keep_blocks = p->pass_a_blocks;
+  const int keep_cs = p->chunk_sums;
   const int32_t keep_chunk = p->chunk, keep_vec = p->pass_b_vec;
 
-  struct Cand { int variant, lpr, blocks, chunk, vec; };
+  // cs: whether pass A may hand the scan its chunk sums.
+  struct Cand { int variant, lpr, blocks, chunk, vec, cs; };
   std::vector<Cand> cands;
   const int vec = pick_vec(d_x, p->d.n_inputs);
   const int64_t cg = (int64_t)p->d.n_channels * p->d.n_inputs / vec;
-  std::vector<Cand> a_opts = {{-1, 0, 0, 0, 0}};
+  std::vector<Cand> a_opts = {{-1, 0, 0, 0, 0, 1}};
   if (vec == 16) {
-    if (cg >= 512)
-      for (int q : {1, 2, 4}) a_opts.push_back({4, 0, q, 0, 0});
-    if (cg >= 512) a_opts.push_back({2, 1024, 1, 0, 0});
-    if (cg >= 256) {
-      a_opts.push_back({2, 256, 1, 0, 0});
-      a_opts.push_back({1, 256, 1, 0, 0});
+    if (cg >= 512) {
+      for (int q : {1, 2, 4}) a_opts.push_back({4, 0, q, 0, 0, 1});
+      // The same tasks without the chunk sums where they would be written.
+      if (p->cs)
+        for (int q : {2, 4}) a_opts.push_back({4, 0, q, 0, 0, 0});
     }
-    if (cg < 256) a_opts.push_back({3, 0, 0, 0, 0});
+    if (cg >= 512) a_opts.push_back({2, 1024, 1, 0, 0, 1});
+    if (cg >= 256) {
+      a_opts.push_back({2, 256, 1, 0, 0, 1});
+      a_opts.push_back({1, 256, 1, 0, 0, 1});
+    }
+    if (cg < 256) a_opts.push_back({3, 0, 0, 0, 0, 1});
   }
   // Pass B inputs per lane stay as set: they fix which inputs a lane sums
   // first, so they change the combine's rounding; the chunk length does not.
   for (const Cand& a : a_opts)
-    for (int R : {1, 2, 4}) cands.push_back({a.variant, a.lpr, a.blocks, R, keep_vec});
+    for (int R : {1, 2, 4})
+      if (a.cs || R == a.blocks) cands.push_back({a.variant, a.lpr, a.blocks, R, keep_vec, a.cs});
 
   std::vector<hipEvent_t> ev(4 * (size_t)reps, nullptr);
   for (auto& e : ev) {
@@ -526,11 +534,12 @@ int sk_plan_autotune(sk_plan_t p, const uint8_t* d_x, int32_t reps, void* stream
     p->pass_a_lpr = c.lpr;
     p->pass_a_variant = c.variant;
     p->pass_a_blocks = c.blocks;
+    p->chunk_sums = c.cs;
     if ((rc = sk_plan_set_pass_b_tile(p, c.chunk, c.vec))) break;
     {
       PassATask t;
       const PassAConfig pc = plan_pass_a_config(p, d_x, &t);
-      resolved[ci] = Cand{pc.variant, pc.lpr, t.blocks_per_task, c.chunk, c.vec};
+      resolved[ci] = Cand{pc.variant, pc.lpr, t.blocks_per_task, c.chunk, c.vec, c.cs};
     }
     if ((rc = plan_call(p, d_x, nullptr, &none, s, PassEvents(), PassEvents()))) break;
     bool cs = false;
@@ -582,6 +591,7 @@ int sk_plan_autotune(sk_plan_t p, const uint8_t* d_x, int32_t reps, void* stream
     p->pass_a_lpr = keep_lpr;
     p->pass_a_variant = keep_var;
     p->pass_a_blocks = keep_blocks;
+    p->chunk_sums = keep_cs;
     (void)sk_plan_set_pass_b_tile(p, keep_chunk, keep_vec);
     (void)sk_state_import(p, saved.data(), sbytes, stream);
     return rc;
@@ -590,6 +600,7 @@ int sk_plan_autotune(sk_plan_t p, const uint8_t* d_x, int32_t reps, void* stream
   p->pass_a_lpr = c.lpr;
   p->pass_a_variant = c.variant;
   p->pass_a_blocks = c.blocks;
+  p->chunk_sums = c.cs;
   if ((rc = sk_plan_set_pass_b_tile(p, c.chunk, c.vec))) return rc;
   if ((rc = sk_state_import(p, saved.data(), sbytes, stream))) return rc;
   if (out) {
@@ -599,6 +610,17 @@ int sk_plan_autotune(sk_plan_t p, const uint8_t* d_x, int32_t reps, void* stream
     out->pass_a_lanes = pc.lpr;
     out->pass_a_blocks = t.blocks_per_task;
     out->pass_b_chunk = p->chunk;
+    bool cs = false;
+    {
+      // Whether the kept combination hands the scan chunk sums (the same
+      // test as a call's).
+      PassBArgs pb = make_pass_b_args(p->d, p->n_blocks, p->hist_cap, p->chunk, p->pass_b_vec, nullptr, &none,
+                                      CallBuffers{p->s1, p->s2, p->pc, nullptr, nullptr, 0}, nullptr);
+      cs = pb.window >= 2 && p->cs && p->chunk_sums && pass_a_deferred(pc.vec, pc.variant) &&
+           t.blocks_per_task == pb.chunk &&
+           (size_t)pb.n_channels * pb.n_chunks * pb.n_inputs * sizeof(int32_t) <= p->cs_bytes;
+    }
+    out->pass_a_chunk_sums = cs ? 1 : 0;
     out->pass_b_vec = make_pass_b_args(p->d, p->n_blocks, p->hist_cap, p->chunk, p->pass_b_vec, nullptr, &none,
                                        CallBuffers{p->s1, p->s2, p->pc, nullptr, nullptr, 0}, nullptr).vec;
     out->candidates = (int32_t)cands.size();

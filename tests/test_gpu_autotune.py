@@ -49,7 +49,12 @@ def test_autotune_keeps_stream_results(N, F, M, B, L):
             wide = N % 16 == 0 and N * F // 16 >= 512
             mid = N % 16 == 0 and N * F // 16 >= 256
             n_a = 1 + (3 + 1 if wide else 0) + (2 if mid else 0) + (1 if N % 16 == 0 and N * F // 16 < 256 else 0)
-            assert pick["candidates"] == 3 * n_a
+            # Wide rows also time 2- and 4-block tasks without chunk sums,
+            # each at its own chunk length only.
+            assert pick["candidates"] == 3 * n_a + (2 if wide else 0)
+            assert pick["pass_a_chunk_sums"] in (0, 1)
+            if pick["pass_a_chunk_sums"]:
+                assert pick["pass_a_variant"] == 4 and pick["pass_a_blocks"] == pick["pass_b_chunk"]
             assert pick["pass_b_chunk"] in (1, 2, 4)
             assert pick["pass_b_vec"] in (1, 4)
             assert pick["ms_pass_a"] > 0 and pick["ms_pass_b"] > 0
