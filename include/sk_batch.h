@@ -6,16 +6,21 @@
  * outputs and normaliser state. sk_batch_compute runs one call of every
  * problem: pass A for all problems is one persistent kernel whose workgroups
  * take tasks from a device work queue, the tasks whose lanes walk the most
- * rows first (a task's duration follows its rows, not its bytes). A task is a
- * block and a chunk of 256 column groups for wide rows, or 256 / L
- * consecutive blocks side by side for rows of L <= 128 column groups (L a
- * power of two); every lane sums whole rows with the lane-replicated packed
- * power table. Pass B for all problems follows in a few more kernels; the
+ * rows first (a task's duration follows its rows, not its bytes). Its
+ * workgroups have 512 lanes. For rows of >= 512 column groups a task is 1, 2
+ * or 4 consecutive blocks of a chunk of 512 column groups, run by the whole
+ * workgroup with its blocks' sums stored after its last block; otherwise a
+ * task runs on half a workgroup and is consecutive blocks of a chunk of 256
+ * column groups (rows of 256..511 groups), or 256 / L consecutive blocks
+ * side by side for rows of L <= 128 column groups (L a power of two). Every
+ * lane sums whole rows with the lane-replicated packed power table, and the
+ * two wavefronts of each SIMD are kept level. Pass B for all problems follows
+ * in a few more kernels; the
  * whole sequence is captured once into a HIP graph, so one call is one graph
  * launch. Tile choices are made per problem class (N, M, F) by the library's
  * autotuner: the class's problems alone are launched with every candidate
  * and timed on the device (pass A rows per load {8, 16} x consecutive blocks
- * per task {1, 2} for wide rows, then pass B chunk length {1, 2, 4}); each
+ * per task {1, 2, 4} for wide rows, then pass B chunk length {1, 2, 4}); each
  * candidate's time and the pick are cached in a JSON file keyed by the
  * device arch and the class, and a class found there is not timed again.
  *
@@ -58,9 +63,9 @@ int sk_batch_compute(sk_batch_t batch, const uint8_t* const* d_inputs, void* str
 /* Forget every problem's normaliser history. Synchronises `stream`. */
 int sk_batch_state_reset(sk_batch_t batch, void* stream);
 
-/* Lanes per block row of problem j's pass A tasks (256 for wide rows, else
- * the power of two covering its column groups) and the persistent workgroup
- * count of pass A. */
+/* Lanes per block row of problem j's pass A tasks (512 for rows of >= 512
+ * column groups, 256 for 256..511, else the power of two covering its column
+ * groups) and the persistent workgroup count of pass A. */
 int sk_batch_get_tiles(sk_batch_t batch, int32_t j, int32_t* lanes_per_row, int32_t* pass_a_grid);
 
 /* Tile choices of problem j: pass A rows per load, blocks per task, pass B

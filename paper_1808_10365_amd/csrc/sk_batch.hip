@@ -23,8 +23,10 @@ int validate_desc(const sk_plan_desc* d);
 // One problem as the batched kernels see it (device table entry).
 struct BatchProb {
   PassATask a;                 // pass A task geometry (x, s1, s2, shapes, chunks, n_tasks)
-  int32_t lpr;                 // pass A lanes per block row (256: wide rows in chunks; else one
-                               // workgroup holds 256 / lpr blocks side by side)
+  int32_t lpr;                 // pass A lanes per block row: 512 (rows of >= 512 column groups,
+                               // 512-group tasks run by a whole workgroup with deferred stores),
+                               // 256 (wide rows in 256-group chunks), else 256 / lpr blocks side
+                               // by side in half a workgroup
   int32_t rows;                // pass A rows per load, 8 or 16 (tuned per problem class)
   int32_t window, hist_cap, chunk, n_chunks, estimator;
   int32_t waves;               // combine waves per chunk (inputs / 256, at most 8)
@@ -102,25 +104,55 @@ __device__ __forceinline__ int find_prob(const BatchProb* probs, int n, int64_t 
 }
 
 // Persistent pass A over the whole batch: every workgroup fills its table
-// once, then takes tasks from one device counter until the queue is empty
-// (every wavefront then exits). Each problem has its own rows per load.
-__global__ __launch_bounds__(256) void batch_pass_a_kernel(const BatchProb* __restrict__ probs, int n,
+// once, then takes two queue units at a time from one device counter until
+// the queue is empty (every wavefront then exits). A task of a problem with
+// rows of >= 512 column groups is two units and runs on the whole
+// workgroup, its blocks' sums held until its last block (as the plan's
+// deferred-store pass A); a task of any other problem is one unit and runs
+// on one 256-lane half. Every problem starts on an even unit, so a claim is
+// one whole task of the first kind or up to two of one problem of the
+// second. The halves share each SIMD (wavefronts w and w + 4) and
+// SimdBalance keeps them level. Each problem has its own rows per load.
+__global__ __launch_bounds__(512) void batch_pass_a_kernel(const BatchProb* __restrict__ probs, int n,
                                                            int64_t total, uint32_t* counter) {
   __shared__ __attribute__((aligned(16))) uint32_t lut32[LANE_LUT_DWORDS];
-  __shared__ int64_t s_task;
-  const int tid = threadIdx.x;
-  fill_lane_packed_lut<256>(lut32, tid);
+  __shared__ uint32_t simd_of[8], progress[8];
+  __shared__ int64_t s_unit;
+  const int tid = threadIdx.x, half = tid >> 8;
+  fill_lane_packed_lut<512>(lut32, tid);
+  simd_balance_post(simd_of, progress, tid);
+  __syncthreads();
+  SimdBalance bal = simd_balance_pair(simd_of, progress, 8);
   const LanePackedLut lut{reinterpret_cast<const uint8_t*>(lut32), (uint32_t)(tid & 63) * 4};
   for (;;) {
-    if (tid == 0) s_task = (int64_t)atomicAdd(counter, 1u);
+    if (tid == 0) s_unit = (int64_t)atomicAdd(counter, 2u);
     __syncthreads();
-    const int64_t task = s_task;
+    const int64_t u0 = s_unit;
     __syncthreads();
-    if (task >= total) break;
-    const int p = find_prob<&BatchProb::a_begin>(probs, n, task);
+    if (u0 >= total) break;
+    const int p = find_prob<&BatchProb::a_begin>(probs, n, u0);
     const BatchProb& P = probs[p];
-    if (P.rows == 8) pass_a_task_side_by_side<8>(P.a, P.lpr, task - P.a_begin, lut);
-    else pass_a_task_side_by_side<16>(P.a, P.lpr, task - P.a_begin, lut);
+    if (P.lpr == 512) {
+      const int64_t task = (u0 - P.a_begin) >> 1;
+      if (task < P.a.n_tasks) {
+        const int q = P.a.blocks_per_task;
+        if (P.rows == 8) {
+          if (q == 4) pass_a_task_deferred<4, 8>(P.a, task, lut, bal);
+          else if (q == 2) pass_a_task_deferred<2, 8>(P.a, task, lut, bal);
+          else pass_a_task_deferred<1, 8>(P.a, task, lut, bal);
+        } else {
+          if (q == 4) pass_a_task_deferred<4, 16>(P.a, task, lut, bal);
+          else if (q == 2) pass_a_task_deferred<2, 16>(P.a, task, lut, bal);
+          else pass_a_task_deferred<1, 16>(P.a, task, lut, bal);
+        }
+      }
+    } else {
+      const int64_t task = u0 + half - P.a_begin;   // past the problem's tasks: its padding unit
+      if (task < P.a.n_tasks) {
+        if (P.rows == 8) pass_a_task_side_by_side<8>(P.a, P.lpr, task, lut, tid & 255, bal);
+        else pass_a_task_side_by_side<16>(P.a, P.lpr, task, lut, tid & 255, bal);
+      }
+    }
   }
 }
 
@@ -327,7 +359,7 @@ static void set_pass_a(BatchProb& P, int rows, int q) {
   P.a.block0 = 0;
   P.a.block_end = P.a.n_blocks;
   P.a.blocks_per_task = P.lpr >= 256 ? q : 256 / P.lpr;
-  P.a.chunks = P.lpr >= 256 ? (P.a.col_groups + 255) / 256 : 1;
+  P.a.chunks = P.lpr >= 256 ? (P.a.col_groups + P.lpr - 1) / P.lpr : 1;
   P.a.n_tasks = (((int64_t)P.a.n_blocks + P.a.blocks_per_task - 1) / P.a.blocks_per_task) * P.a.chunks;
 }
 
@@ -346,8 +378,10 @@ static Layout layout(std::vector<BatchProb>& tab) {
   Layout l;
   for (BatchProb& P : tab) {
     const int64_t F = P.a.row_bytes / P.a.n_inputs;
-    P.a_begin = l.ta;
-    l.ta += P.a.n_tasks;
+    // Queue units: two per task of 512-group rows, one otherwise; every
+    // problem starts on an even unit.
+    P.a_begin = (l.ta + 1) & ~(int64_t)1;
+    l.ta = P.a_begin + P.a.n_tasks * (P.lpr == 512 ? 2 : 1);
     P.sc_begin = l.tsc;
     const int slices = (P.a.n_inputs + 63) / 64, spw = SCAN_MAX_WAVES / P.scan_waves;
     P.sc_count = (P.a.n_blocks > 0 && pass_b_needs_scan(P.window, P.chunk, P.a.n_blocks))
@@ -393,7 +427,7 @@ static hipError_t upload_table(const DeviceTable& d, const std::vector<BatchProb
 
 static void launch_pass_a_table(const BatchProb* d_tab, int n, int64_t total, int grid, uint32_t* counter,
                                 hipStream_t s) {
-  batch_pass_a_kernel<<<dim3(grid), dim3(256), 0, s>>>(d_tab, n, total, counter);
+  batch_pass_a_kernel<<<dim3(grid), dim3(512), 0, s>>>(d_tab, n, total, counter);
 }
 
 template <int R, typename RI>
@@ -596,7 +630,7 @@ int sk_batch_create(const sk_plan_desc* descs, int32_t n, const sk_batch_opts* o
   if (hipGetDeviceProperties(&prop, b->device) != hipSuccess) { batch_free(b); set_error("device query failed"); return SK_ERR_DEVICE; }
   b->arch = prop.gcnArchName;
   int occ = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, batch_pass_a_kernel, 256, 0) != hipSuccess || occ < 1) occ = 2;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, batch_pass_a_kernel, 512, 0) != hipSuccess || occ < 1) occ = 1;
   b->grid_a = occ * prop.multiProcessorCount;
   b->use_graph = !opts || opts->use_graph;
 
@@ -627,7 +661,7 @@ int sk_batch_create(const sk_plan_desc* descs, int32_t n, const sk_batch_opts* o
     {
       int lpb = 1;
       while (lpb < 256 && lpb < P.a.col_groups) lpb *= 2;
-      P.lpr = lpb;
+      P.lpr = P.a.col_groups >= 512 ? 512 : lpb;
     }
     P.window = L;
     P.hist_cap = L >= 2 ? L - 1 : 0;

@@ -197,7 +197,8 @@ __global__ __launch_bounds__(256) void pass_a_side_by_side_kernel(PassATask t, i
   fill_lane_packed_lut<256>(lut32, tid);
   __syncthreads();
   const LanePackedLut lut{reinterpret_cast<const uint8_t*>(lut32), (uint32_t)(tid & 63) * 4};
-  for (int64_t task = blockIdx.x; task < t.n_tasks; task += gridDim.x) pass_a_task_side_by_side<U>(t, lpb, task, lut);
+  for (int64_t task = blockIdx.x; task < t.n_tasks; task += gridDim.x)
+    pass_a_task_side_by_side<U>(t, lpb, task, lut, tid);
 }
 
 int pass_a_side_by_side_lanes(int64_t col_groups) {

@@ -226,7 +226,7 @@ __device__ __forceinline__ void sum_rows(const uint8_t* base, int64_t G, int M, 
 }
 
 // One 256-lane task with the packed lane table (Eq. singlesums), every lane
-// summing whole rows of one (block, column group). lpb = lanes per block row:
+// (tid, 0..255) summing whole rows of one (block, column group). lpb = lanes per block row:
 // 256 for wide rows (task = t.blocks_per_task consecutive blocks, walked one
 // after the other, of a chunk of 256 column groups); a power of two >= the
 // row's column groups otherwise (task = t.blocks_per_task = 256 / lpb
@@ -235,11 +235,11 @@ __device__ __forceinline__ void sum_rows(const uint8_t* base, int64_t G, int M, 
 // block_end set to match. With wide rows and t.cs set, the task also writes
 // its blocks' S1 total (the chunk sum of pass B chunks of blocks_per_task
 // blocks); narrow rows need t.cs null.
-template <int U>
+template <int U, typename Balance = NoBalance>
 __device__ __forceinline__ void pass_a_task_side_by_side(const PassATask& t, int lpb, int64_t task,
-                                                         const LanePackedLut& lut) {
+                                                         const LanePackedLut& lut, int tid,
+                                                         Balance&& bal = Balance()) {
   constexpr int VEC = 16;
-  const int tid = threadIdx.x;
   const int64_t bg = task / t.chunks;
   const int ch = (int)(task % t.chunks);
   int64_t b, b_end;
@@ -268,7 +268,7 @@ __device__ __forceinline__ void pass_a_task_side_by_side(const PassATask& t, int
     uint32_t s1[VEC], s2[VEC];
 #pragma unroll
     for (int k = 0; k < VEC; ++k) s1[k] = s2[k] = 0;
-    sum_rows_packed<VEC, 1, U>(t.x + b * M * G + (int64_t)g * VEC, G, M, 0, lut, s1, s2);
+    sum_rows_packed<VEC, 1, U>(t.x + b * M * G + (int64_t)g * VEC, G, M, 0, lut, s1, s2, bal);
     int32_t* d1 = t.s1 + (f * B + b) * N + i;
     int32_t* d2 = t.s2 + (f * B + b) * N + i;
 #pragma unroll
@@ -287,6 +287,57 @@ __device__ __forceinline__ void pass_a_task_side_by_side(const PassATask& t, int
     int32_t* d = t.cs + (f * nk + (b_first - t.block0) / Q) * N + i;
 #pragma unroll
     for (int k = 0; k < VEC; k += 4) *reinterpret_cast<u32x4*>(d + k) = u32x4{c[k], c[k + 1], c[k + 2], c[k + 3]};
+  }
+}
+
+// One 512-lane task of Q consecutive blocks over 512 column groups (chunk
+// task % chunks), every lane summing whole rows of one column group, with
+// all Q blocks' sums held in registers and stored after the last block, so
+// the stores do not interleave with the task's reads; with t.cs set, the S1
+// total of the Q blocks too (the chunk sums of pass B chunks of Q blocks).
+// Contains no barrier.
+template <int Q, int U, typename Balance>
+__device__ __forceinline__ void pass_a_task_deferred(const PassATask& t, int64_t task, const LanePackedLut& lut,
+                                                     Balance&& bal) {
+  constexpr int VEC = 16;
+  const int tid = threadIdx.x;
+  const int b0 = t.block0 + (int)(task / t.chunks) * Q;
+  const int g = (int)(task % t.chunks) * 512 + tid;
+  if (g >= t.col_groups) return;
+  const int M = t.block_len, N = t.n_inputs, B = t.n_blocks;
+  const int64_t G = t.row_bytes;
+  uint32_t a1[Q][VEC], a2[Q][VEC];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+#pragma unroll
+    for (int k = 0; k < VEC; ++k) a1[q][k] = a2[q][k] = 0;
+    if (b0 + q < t.block_end)
+      sum_rows_packed<VEC, 1, U>(t.x + (int64_t)(b0 + q) * M * G + (int64_t)g * VEC, G, M, 0, lut, a1[q], a2[q], bal);
+  }
+  __builtin_amdgcn_s_setprio(0);
+  const int64_t col = (int64_t)g * VEC;
+  const int64_t f = col / N, i = col % N;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    if (b0 + q >= t.block_end) continue;
+    int32_t* d1 = t.s1 + (f * B + b0 + q) * N + i;
+    int32_t* d2 = t.s2 + (f * B + b0 + q) * N + i;
+#pragma unroll
+    for (int k = 0; k < VEC; k += 4) {
+      *reinterpret_cast<u32x4*>(d1 + k) = u32x4{a1[q][k], a1[q][k + 1], a1[q][k + 2], a1[q][k + 3]};
+      *reinterpret_cast<u32x4*>(d2 + k) = u32x4{a2[q][k], a2[q][k + 1], a2[q][k + 2], a2[q][k + 3]};
+    }
+  }
+  if (t.cs) {
+    const int64_t nk = (t.n_blocks + Q - 1) / Q;
+    int32_t* d = t.cs + (f * nk + (b0 - t.block0) / Q) * N + i;
+#pragma unroll
+    for (int k = 0; k < VEC; k += 4) {
+      u32x4 c = {a1[0][k], a1[0][k + 1], a1[0][k + 2], a1[0][k + 3]};
+#pragma unroll
+      for (int q = 1; q < Q; ++q) c += u32x4{a1[q][k], a1[q][k + 1], a1[q][k + 2], a1[q][k + 3]};
+      *reinterpret_cast<u32x4*>(d + k) = c;
+    }
   }
 }
 

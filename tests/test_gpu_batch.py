@@ -132,14 +132,15 @@ def test_batch_tiles_and_cache(tmp_path):
     assert [b2.tiles(j) for j in range(len(probs))] == tiles
     for (lpr, grid), (_, kw) in zip(tiles, probs):
         groups = kw["n_inputs"] * kw["n_channels"] // 16
-        want = 256 if groups >= 256 else 1 << max(0, (groups - 1).bit_length())
+        want = 512 if groups >= 512 else 256 if groups >= 256 else 1 << max(0, (groups - 1).bit_length())
         assert lpr == want and grid > 0
     b2.close()
 
 
 def test_batch_wide_and_narrow_rows(tmp_path):
     # Default outputs (no SK_i or significance computed). Rows of 512 column
-    # groups (two 256-lane chunks per block), of 1 group
+    # groups (one 512-group task per block, run by a whole workgroup with
+    # deferred stores), of 1 group
     # (256 blocks side by side per workgroup) and of 48 groups (a block row
     # padded to 64 lanes), with a block count that leaves a partial last task.
     shapes = [(2048, 4, 64 * 9, 64, 3), (16, 1, 16 * 301, 16, 4), (256, 3, 32 * 45, 32, 2)]
@@ -207,7 +208,11 @@ def test_batch_chunk_sums_from_pass_a(q, tmp_path):
     # plan's bit for bit over two calls and match the oracle.
     import json
     arch = torch.cuda.get_device_properties(0).gcnArchName
-    shapes = [(1024, 4, 64, 37, 9), (2048, 2, 32, 50, 20), (4096, 1, 16, 23, 64)]
+    # Rows of 256 column groups (256-lane tasks on half a workgroup) and of
+    # 512 and 768 (512-group tasks on a whole workgroup; the second chunk of
+    # the 768-group rows half idle).
+    shapes = [(1024, 4, 64, 37, 9), (2048, 2, 32, 50, 20), (4096, 1, 16, 23, 64), (2048, 4, 32, 29, 7),
+              (2048, 6, 16, 18, 5)]
     cache = {}
     for N, F, M, B, L in shapes:
         cache[f"{arch}|batch|N={N}|M={M}|F={F}|pick"] = 8 * 100 + q * 10 + q
