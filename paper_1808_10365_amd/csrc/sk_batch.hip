@@ -179,6 +179,31 @@ __global__ __launch_bounds__(64 * SCAN_MAX_WAVES) void batch_scan_kernel(const B
   scan_body_rows(a, f, slice, w % Ws, Ws, lds + sub * Ws * 64);
 }
 
+// What a call does after its last kernel: advance every problem's history
+// length and ping-pong parity, and re-arm the pass A queue.
+__device__ __forceinline__ void advance_state(const BatchProb* __restrict__ probs, BatchState* st, int n,
+                                              uint32_t* counter, int tid, int threads) {
+  for (int p = tid; p < n; p += threads) {
+    if (probs[p].window >= 2) {
+      const int64_t total = (int64_t)st[p].hist_len + probs[p].a.n_blocks;
+      st[p].hist_len = (int32_t)(total < probs[p].hist_cap ? total : probs[p].hist_cap);
+      st[p].parity ^= 1;
+    }
+  }
+  if (tid == 0) *counter = 0u;
+}
+
+// The last combine launch of a call also advances the state: its last
+// workgroup to finish (a count in done[0], cleared again by that workgroup)
+// runs advance_state once every workgroup has read the state it needs. The
+// count is a relaxed atomic: each workgroup adds to it after its last read.
+struct BatchFinal {
+  BatchState* st;        // null: not the last launch (or a tuning run)
+  uint32_t* counter;     // pass A queue counter
+  uint32_t* done;        // workgroups of this launch that have finished
+  int n;
+};
+
 // Combine workgroups of one class of problems (chunk length R, 32- or 64-bit
 // R1/R2 sums):
 // (problem, channel, group of 8 / W chunks), 8 wavefronts, W per chunk as in
@@ -188,9 +213,10 @@ __global__ __launch_bounds__(64 * SCAN_MAX_WAVES) void batch_scan_kernel(const B
 // positions, begins[] their first workgroups.
 template <int R, typename RI, bool OFF32>
 __global__ __launch_bounds__(64 * COMBINE_MAX_WAVES) void batch_combine_kernel(
-    const BatchProb* __restrict__ probs, const BatchState* __restrict__ st, const int32_t* __restrict__ members,
-    const int64_t* __restrict__ begins, int count) {
+    const BatchProb* __restrict__ probs, const BatchState* st, const int32_t* __restrict__ members,
+    const int64_t* __restrict__ begins, int count, BatchFinal fin) {
   __shared__ CombineShared sh[COMBINE_MAX_WAVES];
+  __shared__ uint32_t last_out;
   const int64_t task = blockIdx.x;
   int lo = 0, hi = count - 1;
   while (lo < hi) {
@@ -200,28 +226,31 @@ __global__ __launch_bounds__(64 * COMBINE_MAX_WAVES) void batch_combine_kernel(
   const int p = members[lo];
   const BatchProb& P = probs[p];
   const int64_t lt = task - P.cb_begin;
-  if (lt >= P.cb_count) return;                       // whole workgroup
-  const PassBArgs a = make_args(P, st[p]);
-  const int W = P.waves, cpw = COMBINE_MAX_WAVES / W;
-  const int groups = (a.n_chunks + cpw - 1) / cpw;
-  const int f = (int)(lt / groups);
-  const int w = wave_id(), sub = w / W;
-  const int k = (int)(lt % groups) * cpw + sub;
-  const bool live = sub < cpw && k < a.n_chunks;
-  combine_body<4, R, RI, OFF32>(a, k, f, w % W, W, sh[sub < cpw ? sub : 0], live);
+  if (lt < P.cb_count) {                              // else the whole workgroup is idle
+    const PassBArgs a = make_args(P, st[p]);
+    const int W = P.waves, cpw = COMBINE_MAX_WAVES / W;
+    const int groups = (a.n_chunks + cpw - 1) / cpw;
+    const int f = (int)(lt / groups);
+    const int w = wave_id(), sub = w / W;
+    const int k = (int)(lt % groups) * cpw + sub;
+    const bool live = sub < cpw && k < a.n_chunks;
+    combine_body<4, R, RI, OFF32>(a, k, f, w % W, W, sh[sub < cpw ? sub : 0], live);
+  }
+  if (fin.st) {
+    __syncthreads();   // every wavefront of this workgroup has read the state
+    if (threadIdx.x == 0) last_out = atomicAdd(fin.done, 1u) == gridDim.x - 1;
+    __syncthreads();
+    if (last_out) {
+      advance_state(probs, fin.st, fin.n, fin.counter, threadIdx.x, blockDim.x);
+      if (threadIdx.x == 0) *fin.done = 0u;
+    }
+  }
 }
 
 // Last node: advance every problem's history and rearm the work queue.
 __global__ __launch_bounds__(256) void batch_state_kernel(const BatchProb* __restrict__ probs,
                                                           BatchState* st, int n, uint32_t* counter) {
-  for (int p = threadIdx.x; p < n; p += 256) {
-    if (probs[p].window >= 2) {
-      const int64_t total = (int64_t)st[p].hist_len + probs[p].a.n_blocks;
-      st[p].hist_len = (int32_t)(total < probs[p].hist_cap ? total : probs[p].hist_cap);
-      st[p].parity ^= 1;
-    }
-  }
-  if (threadIdx.x == 0) *counter = 0u;
+  advance_state(probs, st, n, counter, threadIdx.x, 256);
 }
 
 }  // namespace sk
@@ -431,25 +460,44 @@ static void launch_pass_a_table(const BatchProb* d_tab, int n, int64_t total, in
 }
 
 template <int R, typename RI>
-static void launch_combine_class(const DeviceTable& d, const BatchState* st, const Layout& l, hipStream_t s) {
+static void launch_combine_class(const DeviceTable& d, BatchState* st, const Layout& l, hipStream_t s,
+                                 const BatchFinal& fin, int last_class) {
   const int c = combine_class(R, sizeof(RI) == 8 ? 1 : 0);
   if (l.tcb[c] <= 0) return;
   const dim3 grid((unsigned)l.tcb[c]), wg(64 * COMBINE_MAX_WAVES);
   const int32_t* m = d.members + l.cls_off[c];
   const int64_t* bg = d.begins + l.cls_off[c];
-  if (l.off32) batch_combine_kernel<R, RI, true><<<grid, wg, 0, s>>>(d.probs, st, m, bg, l.cls_cnt[c]);
-  else batch_combine_kernel<R, RI, false><<<grid, wg, 0, s>>>(d.probs, st, m, bg, l.cls_cnt[c]);
+  const BatchFinal f = c == last_class ? fin : BatchFinal{nullptr, nullptr, nullptr, 0};
+  if (l.off32) batch_combine_kernel<R, RI, true><<<grid, wg, 0, s>>>(d.probs, st, m, bg, l.cls_cnt[c], f);
+  else batch_combine_kernel<R, RI, false><<<grid, wg, 0, s>>>(d.probs, st, m, bg, l.cls_cnt[c], f);
 }
 
-// Scan, then one combine launch per nonempty class, the longest first.
-static void launch_pass_b_table(const DeviceTable& d, const BatchState* st, int n, const Layout& l, hipStream_t s) {
+// Combine classes in launch order.
+static const int kCombineOrder[N_COMBINE_CLASSES][2] = {{4, 0}, {2, 0}, {1, 0}, {4, 1}, {2, 1}, {1, 1}};
+
+// The class whose combine launch comes last in a call, or -1 without one.
+static int last_combine_class(const Layout& l) {
+  int last = -1;
+  for (const auto& rc : kCombineOrder) {
+    const int c = combine_class(rc[0], rc[1]);
+    if (l.tcb[c] > 0) last = c;
+  }
+  return last;
+}
+
+// Scan, then one combine launch per nonempty class, the longest first. With
+// fin.st set, the last combine launch also advances the state (the caller
+// launches batch_state_kernel instead when there is no combine launch).
+static void launch_pass_b_table(const DeviceTable& d, BatchState* st, int n, const Layout& l, hipStream_t s,
+                                const BatchFinal& fin = BatchFinal{nullptr, nullptr, nullptr, 0}) {
   if (l.tsc > 0) batch_scan_kernel<<<dim3((unsigned)l.tsc), dim3(64 * SCAN_MAX_WAVES), 0, s>>>(d.probs, st, n);
-  launch_combine_class<4, int32_t>(d, st, l, s);
-  launch_combine_class<2, int32_t>(d, st, l, s);
-  launch_combine_class<1, int32_t>(d, st, l, s);
-  launch_combine_class<4, int64_t>(d, st, l, s);
-  launch_combine_class<2, int64_t>(d, st, l, s);
-  launch_combine_class<1, int64_t>(d, st, l, s);
+  const int last = fin.st ? last_combine_class(l) : -1;
+  launch_combine_class<4, int32_t>(d, st, l, s, fin, last);
+  launch_combine_class<2, int32_t>(d, st, l, s, fin, last);
+  launch_combine_class<1, int32_t>(d, st, l, s, fin, last);
+  launch_combine_class<4, int64_t>(d, st, l, s, fin, last);
+  launch_combine_class<2, int64_t>(d, st, l, s, fin, last);
+  launch_combine_class<1, int64_t>(d, st, l, s, fin, last);
 }
 
 static DeviceTable device_table(const sk_batch_s* b) { return DeviceTable{b->d_probs, b->d_members, b->d_begins}; }
@@ -457,10 +505,13 @@ static DeviceTable device_table(const sk_batch_s* b) { return DeviceTable{b->d_p
 static int launch_sequence(sk_batch_s* b, hipStream_t s) {
   launch_pass_a_table(b->d_probs, b->n, b->lay.ta, b->grid_a, b->d_counter, s);
   SK_HIP_TRY(hipGetLastError());
-  launch_pass_b_table(device_table(b), b->d_state, b->n, b->lay, s);
+  const BatchFinal fin{b->d_state, b->d_counter, b->d_counter + 1, b->n};
+  launch_pass_b_table(device_table(b), b->d_state, b->n, b->lay, s, fin);
   SK_HIP_TRY(hipGetLastError());
-  batch_state_kernel<<<dim3(1), dim3(256), 0, s>>>(b->d_probs, b->d_state, b->n, b->d_counter);
-  SK_HIP_TRY(hipGetLastError());
+  if (last_combine_class(b->lay) < 0) {
+    batch_state_kernel<<<dim3(1), dim3(256), 0, s>>>(b->d_probs, b->d_state, b->n, b->d_counter);
+    SK_HIP_TRY(hipGetLastError());
+  }
   return SK_OK;
 }
 
@@ -717,7 +768,8 @@ int sk_batch_create(const sk_plan_desc* descs, int32_t n, const sk_batch_opts* o
   if ((rc = batch_alloc(b, &p, sizeof(BatchState) * n))) { batch_free(b); return rc; }
   b->owned.pop_back();
   b->d_state = (BatchState*)p;
-  if ((rc = batch_alloc(b, &p, sizeof(uint32_t)))) { batch_free(b); return rc; }
+  // [0] pass A queue, [1] finished workgroups of the last combine launch.
+  if ((rc = batch_alloc(b, &p, 2 * sizeof(uint32_t)))) { batch_free(b); return rc; }
   b->owned.pop_back();
   b->d_counter = (uint32_t*)p;
   if ((rc = batch_alloc(b, &p, sizeof(int32_t) * n))) { batch_free(b); return rc; }
@@ -730,7 +782,7 @@ int sk_batch_create(const sk_plan_desc* descs, int32_t n, const sk_batch_opts* o
   (void)layout(b->host);
   if (hipMemcpyAsync(b->d_probs, b->host.data(), sizeof(BatchProb) * n, hipMemcpyHostToDevice, s) != hipSuccess ||
       hipMemcpyAsync(b->d_state, st.data(), sizeof(BatchState) * n, hipMemcpyHostToDevice, s) != hipSuccess ||
-      hipMemsetAsync(b->d_counter, 0, sizeof(uint32_t), s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
+      hipMemsetAsync(b->d_counter, 0, 2 * sizeof(uint32_t), s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
     batch_free(b);
     set_error("batch table upload failed");
     return SK_ERR_DEVICE;
@@ -785,7 +837,7 @@ int sk_batch_create(const sk_plan_desc* descs, int32_t n, const sk_batch_opts* o
       return SK_ERR_SHAPE;
     }
     if (upload_table(device_table(b), b->host, l, s) != hipSuccess ||
-        hipMemsetAsync(b->d_counter, 0, sizeof(uint32_t), s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
+        hipMemsetAsync(b->d_counter, 0, 2 * sizeof(uint32_t), s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
       batch_free(b);
       set_error("batch table upload failed");
       return SK_ERR_DEVICE;

@@ -5,9 +5,11 @@ Reads the SQLite database rocprofv3 writes (``-d DIR -o run``) and prints:
 * ``trace DIR``: per-kernel dispatch count and duration (average, median,
   min, max, total) from the kernel trace; with ``--calls`` also the
   batched form's graph calls (a ``batch_pass_a_kernel`` dispatch followed
-  by the batched scan / combine kernels up to ``batch_state_kernel``),
-  grouped by their kernel sequence (the autotuner's trial launches, which
-  never end in the state kernel, are not counted as calls);
+  by the batched scan / combine / state kernels up to the next pass A),
+  grouped by their kernel sequence. The autotuner's and the pass A timer's
+  launches each follow a device fill (the queue counter cleared with a
+  memset), graph calls do not: sequences right after a
+  ``__amd_rocclr_fillBuffer`` dispatch are not counted as calls;
 * ``counters FETCH_DIR WRITE_DIR``: FETCH_SIZE and WRITE_SIZE per dispatch
   (KiB), scaled to bytes by what the same counters read for one device copy
   of ``--copy-bytes`` bytes (the ``__amd_rocclr_copyBuffer`` dispatch of
@@ -59,20 +61,21 @@ def trace(d: str, calls: bool = False, include: str = "") -> str:
                    f"{min(v):10.2f} {max(v):10.2f} {sum(v) / 1e3:10.3f}")
     if calls:
         out.append("")
-        out.append("batched graph calls (pass A dispatch followed by pass B kernels up to the state kernel):")
+        out.append("batched graph calls (pass A dispatch, not right after a fill, followed by pass B kernels "
+                   "up to the next pass A):")
         seqs = []
         i = 0
         while i < len(rows):
-            if "batch_pass_a_kernel" in rows[i][0] and i + 1 < len(rows) and \
+            trial = i > 0 and "fillBuffer" in rows[i - 1][0]
+            if "batch_pass_a_kernel" in rows[i][0] and not trial and i + 1 < len(rows) and \
                     ("batch_scan_kernel" in rows[i + 1][0] or "batch_combine_kernel" in rows[i + 1][0]):
                 j = i + 1
-                while j < len(rows) and "batch_state_kernel" not in rows[j][0] and \
+                while j < len(rows) and rows[j][0].lstrip("void ").startswith("sk::batch_") and \
                         "batch_pass_a_kernel" not in rows[j][0]:
                     j += 1
-                if j < len(rows) and "batch_state_kernel" in rows[j][0]:
-                    seqs.append(rows[i:j + 1])
-                    i = j + 1
-                    continue
+                seqs.append(rows[i:j])
+                i = j
+                continue
             i += 1
         groups = collections.defaultdict(list)
         for sq in seqs:
@@ -80,10 +83,10 @@ def trace(d: str, calls: bool = False, include: str = "") -> str:
         for names_k, gs in sorted(groups.items(), key=lambda kv: (len(kv[0]), kv[0])):
             n_k = len(names_k)
             pa = [(g[0][2] - g[0][1]) / 1e3 for g in gs]
-            pb = [(g[-1][1] - g[1][1]) / 1e3 for g in gs]
+            pb = [(g[-1][2] - g[1][1]) / 1e3 for g in gs]
             wall = [(g[-1][2] - g[0][1]) / 1e3 for g in gs]
             out.append(f"  {len(gs)} calls of {n_k} kernels: pass A avg {statistics.fmean(pa):.2f} us "
-                       f"(min {min(pa):.2f}), pass B + state avg {statistics.fmean(pb):.2f} us, "
+                       f"(min {min(pa):.2f}), pass B first start to last end avg {statistics.fmean(pb):.2f} us, "
                        f"call first start to last end avg {statistics.fmean(wall):.2f} us")
             names = [_short(k[0], 40) for k in gs[0]]
             durs = [statistics.fmean([(g[m][2] - g[m][1]) / 1e3 for g in gs]) for m in range(n_k)]

@@ -21,24 +21,28 @@ def test_trace_stats_and_batched_calls(tmp_path):
     ns = 1000
     k = []
     t = 0
-    # A trial launch (pass A then pass B, no state kernel), then two graph calls.
-    for name, dur in [("sk::batch_pass_a_kernel(x)", 100), ("sk::batch_scan_kernel(x)", 10),
-                      ("sk::batch_combine_kernel<4, int, true>(x)", 20),
-                      ("sk::batch_pass_a_kernel(x)", 200), ("sk::batch_scan_kernel(x)", 10),
-                      ("sk::batch_combine_kernel<4, int, true>(x)", 30), ("sk::batch_state_kernel(x)", 4),
-                      ("sk::batch_pass_a_kernel(x)", 210), ("sk::batch_scan_kernel(x)", 12),
-                      ("sk::batch_combine_kernel<4, int, true>(x)", 30), ("sk::batch_state_kernel(x)", 4)]:
+    # A trial launch (a counter fill, then pass A, scan, combine<2>), then
+    # three graph calls (pass A, scan, combine<4>), then a plan kernel.
+    seq = [("__amd_rocclr_fillBufferAligned", 2), ("sk::batch_pass_a_kernel(x)", 100), ("sk::batch_scan_kernel(x)", 10),
+           ("sk::batch_combine_kernel<2, int, true>(x)", 20)]
+    for p in (200, 210, 220):
+        seq += [("sk::batch_pass_a_kernel(x)", p), ("sk::batch_scan_kernel(x)", 12),
+                ("sk::batch_combine_kernel<4, int, true>(x)", 30)]
+    seq.append(("sk::pass_a_deferred_kernel<4, 16, true>(x)", 300))
+    for name, dur in seq:
         k.append((name, t, t + dur * ns))
         t += dur * ns + 5 * ns
     _db(str(d / "run_results.db"), k)
     out = rs.trace(str(d), calls=True)
     lines = out.splitlines()
     row = next(l for l in lines if l.startswith("sk::batch_pass_a_kernel"))
-    assert row.split()[1] == "3"                       # three pass A dispatches
-    assert abs(float(row.split()[2]) - 170.0) < 1e-6  # their mean
-    call = next(l for l in lines if "calls of" in l)
-    assert call.strip().startswith("2 calls of 4 kernels")   # the trial launch is not a call
-    assert "pass A avg 205.00 us" in call
+    assert row.split()[1] == "4"                       # four pass A dispatches
+    assert abs(float(row.split()[2]) - 182.5) < 1e-6  # their mean
+    call = [l for l in lines if "calls of" in l]
+    assert len(call) == 1                              # the trial launch after the fill is not a call
+    assert call[0].strip().startswith("3 calls of 3 kernels")
+    assert "pass A avg 210.00 us" in call[0]
+    assert "pass B first start to last end avg 47.00 us" in call[0]   # scan start to combine end: 12 + 5 + 30
     filt = rs.trace(str(d), include="scan")
     assert "batch_scan_kernel" in filt and "batch_pass_a_kernel" not in filt
 
