@@ -114,8 +114,9 @@ typedef struct {
  * Each pass's time is estimated from every combination that runs that pass
  * the same way (pass A: its launched variant, lanes, blocks per task and
  * whether it writes chunk sums; pass B: its chunk length and whether it
- * reads them), and the kept combination has the least sum of the two
- * estimates. The
+ * reads them), and the combination with the least sum of the two estimates
+ * is kept if, timed again in 4 calls alternating with the library's choice,
+ * it is still faster (else the library's choice is kept). The
  * normaliser state is exported before and imported after, so a stream in
  * progress continues unchanged; results of later calls do not depend on the
  * choice (integer sums are exact, and the combine's order does not depend on

@@ -467,7 +467,8 @@ int sk_compute(sk_plan_t p, const uint8_t* d_packed, const uint8_t* d_mask, cons
 // Autotuner of one plan: every candidate (pass A variant and its lanes or
 // blocks per task, pass B chunk length) runs one
 // untimed and `reps` timed calls on d_x; the least pooled estimate of pass A
-// plus pass B kernel time (dispatch timestamps) is kept. The normaliser state is
+// plus pass B kernel time (dispatch timestamps) wins, and is kept if it also
+// beats the library's choice in alternating calls. The normaliser state is
 // saved before and restored after, so a stream in progress continues as if
 // the tuning calls had not run.
 int sk_plan_autotune(sk_plan_t p, const uint8_t* d_x, int32_t reps, void* stream, sk_plan_tuning* out) {
@@ -566,7 +567,7 @@ int sk_plan_autotune(sk_plan_t p, const uint8_t* d_x, int32_t reps, void* stream
   // whether it reads them). Each pass is estimated from every candidate that
   // shares its settings, so one noisy pass A trial does not decide pass B.
   float best = 1e30f, best_a = 0.f, best_b = 0.f, lib_a = 0.f, lib_b = 0.f;
-  size_t best_i = 0;
+  size_t best_i = 0, lib_i = cands.size();
   if (rc == SK_OK) {
     auto same_a = [&](size_t i, size_t j) {
       return resolved[i].variant == resolved[j].variant && resolved[i].lpr == resolved[j].lpr &&
@@ -582,8 +583,57 @@ int sk_plan_autotune(sk_plan_t p, const uint8_t* d_x, int32_t reps, void* stream
       }
       const float ea_ms = (float)(ta / ((double)na * reps)), eb_ms = (float)(tb / ((double)nb * reps));
       const Cand& c = cands[ci];
-      if (c.variant == -1 && c.lpr == 0 && c.blocks == 0 && c.chunk == keep_chunk) { lib_a = ea_ms; lib_b = eb_ms; }
+      if (c.variant == -1 && c.lpr == 0 && c.blocks == 0 && c.chunk == keep_chunk && c.cs) {
+        lib_a = ea_ms;
+        lib_b = eb_ms;
+        lib_i = ci;
+      }
       if (ea_ms + eb_ms < best) { best = ea_ms + eb_ms; best_i = ci; best_a = ea_ms; best_b = eb_ms; }
+    }
+  }
+  // A pick other than the library's choice is confirmed against it in
+  // alternating calls (library, pick, library, pick, ...), so a drift of the
+  // device's speed during the trials cannot favour either; the pick is kept
+  // only if it is still faster.
+  const bool differs = rc == SK_OK && lib_i != best_i && lib_i < cands.size() &&
+                       !(resolved[lib_i].variant == resolved[best_i].variant &&
+                         resolved[lib_i].lpr == resolved[best_i].lpr &&
+                         resolved[lib_i].blocks == resolved[best_i].blocks && with_cs[lib_i] == with_cs[best_i] &&
+                         cands[lib_i].chunk == cands[best_i].chunk);
+  if (differs) {
+    constexpr int ROUNDS = 4;
+    double conf_a[2] = {0.0, 0.0}, conf_b[2] = {0.0, 0.0};
+    for (int r = 0; r < ROUNDS && rc == SK_OK; ++r) {
+      for (int side = 0; side < 2 && rc == SK_OK; ++side) {
+        const Cand& c = cands[side ? best_i : lib_i];
+        p->pass_a_lpr = c.lpr;
+        p->pass_a_variant = c.variant;
+        p->pass_a_blocks = c.blocks;
+        p->chunk_sums = c.cs;
+        if ((rc = sk_plan_set_pass_b_tile(p, c.chunk, c.vec))) break;
+        if ((rc = plan_call(p, d_x, nullptr, &none, s, PassEvents{ev[0], ev[1]}, PassEvents{ev[2], ev[3]}))) break;
+        float x = 0.f, y = 0.f;
+        if (hipEventSynchronize(ev[3]) != hipSuccess || hipEventElapsedTime(&x, ev[0], ev[1]) != hipSuccess ||
+            hipEventElapsedTime(&y, ev[2], ev[3]) != hipSuccess) {
+          rc = SK_ERR_DEVICE;
+          set_error("autotune: event timing failed");
+          break;
+        }
+        conf_a[side] += x;
+        conf_b[side] += y;
+      }
+    }
+    if (rc == SK_OK) {
+      lib_a = (float)(conf_a[0] / ROUNDS);
+      lib_b = (float)(conf_b[0] / ROUNDS);
+      if (conf_a[1] + conf_b[1] < conf_a[0] + conf_b[0]) {
+        best_a = (float)(conf_a[1] / ROUNDS);
+        best_b = (float)(conf_b[1] / ROUNDS);
+      } else {
+        best_i = lib_i;
+        best_a = lib_a;
+        best_b = lib_b;
+      }
     }
   }
   for (auto& e : ev) (void)hipEventDestroy(e);
