@@ -400,7 +400,13 @@ static void set_pass_b(BatchProb& P, int R) {
   P.n_chunks = (int32_t)((P.a.n_blocks + R - 1) / R);
   const bool cs = P.cs_buf && P.lpr >= 256 && R >= 2 && P.a.blocks_per_task == R;
   P.a.cs = cs ? P.cs_buf : nullptr;
-  P.scan_waves = scan_rows_waves(cs ? P.n_chunks : P.a.n_blocks);
+  // Waves per slice: enough for the units in SCAN_ROWS-unit lanes, and for
+  // the history rows moved once the history is full (a call shorter than the
+  // window), a power of two.
+  int w = scan_rows_waves(cs ? P.n_chunks : P.a.n_blocks);
+  const int64_t sg = shift_groups(P.hist_cap, P.a.n_blocks);
+  while (w < SCAN_MAX_WAVES && w < sg) w *= 2;
+  P.scan_waves = w;
 }
 
 static Layout layout(std::vector<BatchProb>& tab) {

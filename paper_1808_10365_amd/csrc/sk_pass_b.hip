@@ -61,7 +61,10 @@ int launch_pass_b(const PassBArgs& a, hipStream_t s, PassEvents ev) {
   const int F = a.n_channels;
   hipEvent_t start = ev.start;
   if (pass_b_needs_scan(a.window, a.chunk, a.n_blocks)) {
-    const dim3 grid((a.n_inputs + 63) / 64, F), wg(64 * scan_waves(a.n_chunks));
+    // Enough wavefronts for the chunks, or for the history rows a call
+    // shorter than the window moves.
+    const int64_t sg = shift_groups(a.hist_next_len, a.n_blocks);
+    const dim3 grid((a.n_inputs + 63) / 64, F), wg(64 * scan_waves(sg > a.n_chunks ? (int)sg : a.n_chunks));
     switch (a.chunk) {
       case 1: launch_kernel(scan_kernel<1>, grid, wg, 0, s, start, nullptr, a); break;
       case 2: launch_kernel(scan_kernel<2>, grid, wg, 0, s, start, nullptr, a); break;

@@ -253,6 +253,42 @@ __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane
 
 constexpr int SCAN_MAX_WAVES = 16;
 
+// History rows a scan wavefront moves per group (all loads, then all stores).
+constexpr int SHIFT_ROWS = 16;
+
+// History blocks that stay in the window of the next call (a call shorter
+// than the window): their suffix sums grow by the whole call, `carry`.
+// Next-call slot s holds position s - Hc, which is old position s - Hc + B,
+// so it reads old slot s + B. Wavefront w of W takes groups of SHIFT_ROWS
+// rows; a group's loads all issue before its stores (the two history buffers
+// are distinct), so a short call against a long window does not walk its
+// rows one load at a time.
+__device__ __forceinline__ void shift_history(const PassBArgs& a, int f, int i, bool active, uint32_t carry,
+                                              int w, int W) {
+  const int Hc = a.hist_cap, B = a.n_blocks;
+  const int from = Hc - a.hist_next_len, to = Hc - B;
+  if (!active || !a.hs_next || from >= to) return;
+  const int64_t rowN = a.n_inputs;
+  const int32_t* src = a.hs + ((int64_t)f * Hc + B) * rowN + i;
+  int32_t* dst = a.hs_next + (int64_t)f * Hc * rowN + i;
+  const bool had = a.hist_len > 0;
+  for (int s0 = from + w * SHIFT_ROWS; s0 < to; s0 += W * SHIFT_ROWS) {
+    int32_t old[SHIFT_ROWS];
+#pragma unroll
+    for (int j = 0; j < SHIFT_ROWS; ++j) old[j] = (had && s0 + j < to) ? src[(int64_t)(s0 + j) * rowN] : 0;
+#pragma unroll
+    for (int j = 0; j < SHIFT_ROWS; ++j)
+      if (s0 + j < to) dst[(int64_t)(s0 + j) * rowN] = (int32_t)((uint32_t)old[j] + carry);
+  }
+}
+
+// Wavefronts the history shift of one 64-input slice can use: its rows in
+// SHIFT_ROWS groups (0 when the call is at least as long as the window).
+__host__ __device__ __forceinline__ int64_t shift_groups(int64_t hist_next_len, int64_t n_blocks) {
+  const int64_t rows = hist_next_len - n_blocks;
+  return rows > 0 ? (rows + SHIFT_ROWS - 1) / SHIFT_ROWS : 0;
+}
+
 // Chunks a scan lane holds per round: 64 rows of S1 in flight at most.
 template <int R>
 constexpr int scan_chunks_per_lane() { return 64 / R; }
@@ -314,17 +350,7 @@ __device__ __forceinline__ void scan_body(const PassBArgs& a, int f, int slice, 
     }
     __syncthreads();
   }
-  // History blocks that stay in the window of the next call (a call shorter
-  // than the window): their suffix sums grow by the whole call, `carry`.
-  // Next-call slot s holds position s - Hc, which is old position s - Hc + B.
-  const int Hc = a.hist_cap;
-  const int from = Hc - a.hist_next_len, to = Hc - B;
-  if (active && a.hs_next) {
-    for (int s = from + w; s < to; s += W) {
-      const int32_t old = a.hist_len > 0 ? a.hs[((int64_t)f * Hc + s + B) * rowN + i] : 0;
-      a.hs_next[((int64_t)f * Hc + s) * rowN + i] = (int32_t)((uint32_t)old + carry);
-    }
-  }
+  shift_history(a, f, i, active, carry, w, W);
 }
 
 // The same scan for a chunk length known only at run time (the batched
@@ -378,14 +404,7 @@ __device__ __forceinline__ void scan_body_rows(const PassBArgs& a, int f, int sl
     }
     __syncthreads();
   }
-  const int Hc = a.hist_cap;
-  const int from = Hc - a.hist_next_len, to = Hc - B;
-  if (active && a.hs_next) {
-    for (int s = from + w; s < to; s += W) {
-      const int32_t old = a.hist_len > 0 ? a.hs[((int64_t)f * Hc + s + B) * rowN + i] : 0;
-      a.hs_next[((int64_t)f * Hc + s) * rowN + i] = (int32_t)((uint32_t)old + carry);
-    }
-  }
+  shift_history(a, f, i, active, carry, w, W);
 }
 
 // Waves per slice of the batched scan: a power of two covering the call's
