@@ -30,7 +30,7 @@ struct BatchProb {
   int32_t rows;                // pass A rows per load, 8 or 16 (tuned per problem class)
   int32_t window, hist_cap, chunk, n_chunks, estimator;
   int32_t waves;               // combine waves per chunk (inputs / 256, at most 8)
-  int32_t scan_waves;          // scan waves per 64-input slice (power of two, at most 16)
+  int32_t scan_waves;          // scan waves per 64-input slice (power of two, at most 8)
   int32_t wide_sums;           // 1: the combine's R1/R2 sums need 64 bits
   double k_sigma, expect_offset, sigma_override;
   uint32_t* pc;                // pass B prefix sums
@@ -156,21 +156,26 @@ __global__ __launch_bounds__(512) void batch_pass_a_kernel(const BatchProb* __re
   }
 }
 
+// Wavefronts of a batched scan workgroup. Eight rather than sixteen: the
+// kernel's registers allow three such workgroups per CU against one of
+// sixteen wavefronts, so more rows are in flight.
+constexpr int BATCH_SCAN_WAVES = 8;
+
 // Scan workgroups of the whole batch: (problem, channel, group of 64-input
-// slices), 16 wavefronts, Ws per slice (the problem's scan_waves) and 16 / Ws
-// slices per workgroup. The chunk length is read at run time
-// (scan_body_rows); the prefix sums are exact integers, so they equal the
-// single-plan kernel's.
-__global__ __launch_bounds__(64 * SCAN_MAX_WAVES) void batch_scan_kernel(const BatchProb* __restrict__ probs,
+// slices), BATCH_SCAN_WAVES wavefronts, Ws per slice (the problem's
+// scan_waves) and BATCH_SCAN_WAVES / Ws slices per workgroup. The chunk
+// length is read at run time (scan_body_rows); the prefix sums are exact
+// integers, so they equal the single-plan kernel's.
+__global__ __launch_bounds__(64 * BATCH_SCAN_WAVES) void batch_scan_kernel(const BatchProb* __restrict__ probs,
                                                                         const BatchState* __restrict__ st, int n) {
-  __shared__ uint32_t lds[SCAN_MAX_WAVES * 64];
+  __shared__ uint32_t lds[BATCH_SCAN_WAVES * 64];
   const int64_t task = blockIdx.x;
   const int p = find_prob<&BatchProb::sc_begin>(probs, n, task);
   const BatchProb& P = probs[p];
   const int64_t lt = task - P.sc_begin;
   if (lt >= P.sc_count) return;                       // whole workgroup
   const PassBArgs a = make_args(P, st[p]);
-  const int Ws = P.scan_waves, spw = SCAN_MAX_WAVES / Ws;
+  const int Ws = P.scan_waves, spw = BATCH_SCAN_WAVES / Ws;
   const int slices = (a.n_inputs + 63) / 64;
   const int groups = (slices + spw - 1) / spw;
   const int f = (int)(lt / groups);
@@ -403,9 +408,9 @@ static void set_pass_b(BatchProb& P, int R) {
   // Waves per slice: enough for the units in SCAN_ROWS-unit lanes, and for
   // the history rows moved once the history is full (a call shorter than the
   // window), a power of two.
-  int w = scan_rows_waves(cs ? P.n_chunks : P.a.n_blocks);
+  int w = scan_rows_waves(cs ? P.n_chunks : P.a.n_blocks, BATCH_SCAN_WAVES);
   const int64_t sg = shift_groups(P.hist_cap, P.a.n_blocks);
-  while (w < SCAN_MAX_WAVES && w < sg) w *= 2;
+  while (w < BATCH_SCAN_WAVES && w < sg) w *= 2;
   P.scan_waves = w;
 }
 
@@ -418,7 +423,7 @@ static Layout layout(std::vector<BatchProb>& tab) {
     P.a_begin = (l.ta + 1) & ~(int64_t)1;
     l.ta = P.a_begin + P.a.n_tasks * (P.lpr == 512 ? 2 : 1);
     P.sc_begin = l.tsc;
-    const int slices = (P.a.n_inputs + 63) / 64, spw = SCAN_MAX_WAVES / P.scan_waves;
+    const int slices = (P.a.n_inputs + 63) / 64, spw = BATCH_SCAN_WAVES / P.scan_waves;
     P.sc_count = (P.a.n_blocks > 0 && pass_b_needs_scan(P.window, P.chunk, P.a.n_blocks))
                      ? F * ((slices + spw - 1) / spw) : 0;
     l.tsc += P.sc_count;
@@ -496,7 +501,7 @@ static int last_combine_class(const Layout& l) {
 // launches batch_state_kernel instead when there is no combine launch).
 static void launch_pass_b_table(const DeviceTable& d, BatchState* st, int n, const Layout& l, hipStream_t s,
                                 const BatchFinal& fin = BatchFinal{nullptr, nullptr, nullptr, 0}) {
-  if (l.tsc > 0) batch_scan_kernel<<<dim3((unsigned)l.tsc), dim3(64 * SCAN_MAX_WAVES), 0, s>>>(d.probs, st, n);
+  if (l.tsc > 0) batch_scan_kernel<<<dim3((unsigned)l.tsc), dim3(64 * BATCH_SCAN_WAVES), 0, s>>>(d.probs, st, n);
   const int last = fin.st ? last_combine_class(l) : -1;
   launch_combine_class<4, int32_t>(d, st, l, s, fin, last);
   launch_combine_class<2, int32_t>(d, st, l, s, fin, last);

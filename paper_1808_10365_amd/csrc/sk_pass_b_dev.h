@@ -408,11 +408,11 @@ __device__ __forceinline__ void scan_body_rows(const PassBArgs& a, int f, int sl
 }
 
 // Waves per slice of the batched scan: a power of two covering the call's
-// rows in SCAN_ROWS-row lanes, at most SCAN_MAX_WAVES (so slices tile a
-// workgroup).
-__host__ __device__ __forceinline__ int scan_rows_waves(int64_t n_blocks) {
+// rows in SCAN_ROWS-row lanes, at most max_waves (a power of two: the
+// workgroup's wavefronts, so slices tile it).
+__host__ __device__ __forceinline__ int scan_rows_waves(int64_t n_blocks, int max_waves) {
   int W = 1;
-  while (W < SCAN_MAX_WAVES && (int64_t)W * SCAN_ROWS < n_blocks) W *= 2;
+  while (W < max_waves && (int64_t)W * SCAN_ROWS < n_blocks) W *= 2;
   return W;
 }
 
