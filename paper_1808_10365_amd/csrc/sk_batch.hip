@@ -92,15 +92,29 @@ __device__ __forceinline__ PassBArgs make_args(const BatchProb& P, const BatchSt
   return a;
 }
 
+// Index of the last entry of a sorted sequence (begin(0) = 0) at or before
+// `task`, found by the whole wavefront: each lane compares one entry, and the
+// lanes at or before `task` are a prefix, so the highest set bit of their
+// ballot is the answer (one load per 64 entries, rather than a chain of
+// dependent loads). Called by every lane of the wavefront.
+template <typename Begin>
+__device__ __forceinline__ int last_at_or_before(int n, int64_t task, Begin begin) {
+  const int lane = threadIdx.x & 63;
+  int last = 0;
+  for (int base = 0; base < n; base += 64) {
+    const int j = base + lane;
+    const uint64_t m = __ballot(j < n && begin(j) <= task);
+    if (m == 0) break;
+    last = base + 63 - __builtin_clzll(m);
+    if (m != ~0ull) break;
+  }
+  return __builtin_amdgcn_readfirstlane(last);
+}
+
 // Index of the last problem whose range starts at or before `task`.
 template <int64_t BatchProb::*BEGIN>
 __device__ __forceinline__ int find_prob(const BatchProb* probs, int n, int64_t task) {
-  int lo = 0, hi = n - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (probs[mid].*BEGIN <= task) lo = mid; else hi = mid - 1;
-  }
-  return lo;
+  return last_at_or_before(n, task, [&](int j) { return probs[j].*BEGIN; });
 }
 
 // Persistent pass A over the whole batch: every workgroup fills its table
@@ -223,12 +237,7 @@ __global__ __launch_bounds__(64 * COMBINE_MAX_WAVES) void batch_combine_kernel(
   __shared__ CombineShared sh[COMBINE_MAX_WAVES];
   __shared__ uint32_t last_out;
   const int64_t task = blockIdx.x;
-  int lo = 0, hi = count - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (begins[mid] <= task) lo = mid; else hi = mid - 1;
-  }
-  const int p = members[lo];
+  const int p = members[last_at_or_before(count, task, [&](int j) { return begins[j]; })];
   const BatchProb& P = probs[p];
   const int64_t lt = task - P.cb_begin;
   if (lt < P.cb_count) {                              // else the whole workgroup is idle
