@@ -569,7 +569,7 @@ static float time_pass_a_batch(sk_batch_s* b, hipStream_t s) {
 
 // Autotuner. Problems are grouped by class (N, M, F). For each class not in
 // the cache, the class's problems alone (a sub-table) are timed with every
-// candidate, best of three launches after one untimed: first pass A alone
+// candidate, best of kTuneReps launches after one untimed: first pass A alone
 // over rows per load {8, 16} x blocks per task {1, 2, 4} (wide rows; 1 for
 // narrow rows), then whole calls (pass A and pass B) with the best rows and
 // blocks over pass B chunk length {1, 2, 4}, and, for wide rows with a
@@ -578,6 +578,10 @@ static float time_pass_a_batch(sk_batch_s* b, hipStream_t s) {
 // candidate's time (ns) and the pick go into the cache, keyed by the device
 // arch and the class; a class found in the cache takes its pick without
 // timing.
+// Timed launches per tuning candidate (the least is kept): candidates of one
+// class often differ by a few microseconds, about the spread of single runs.
+constexpr int kTuneReps = 5;
+
 static int tune_batch(sk_batch_s* b, const std::string& path, hipStream_t s) {
   std::map<std::string, int> cache = load_cache(path);
   std::map<std::string, std::vector<int>> classes;
@@ -624,7 +628,7 @@ static int tune_batch(sk_batch_s* b, const std::string& path, hipStream_t s) {
             rc = SK_ERR_DEVICE;
             break;
           }
-          const float t = best_time(s, b->d_counter, 3, [&] {
+          const float t = best_time(s, b->d_counter, kTuneReps, [&] {
             launch_pass_a_table(d.probs, (int)sub.size(), l.ta, b->grid_a, b->d_counter, s);
           });
           char ck[320];
@@ -651,7 +655,7 @@ static int tune_batch(sk_batch_s* b, const std::string& path, hipStream_t s) {
           rc = SK_ERR_DEVICE;
           break;
         }
-        const float t = best_time(s, b->d_counter, 3, [&] {
+        const float t = best_time(s, b->d_counter, kTuneReps, [&] {
           launch_pass_a_table(d.probs, (int)sub.size(), l.ta, b->grid_a, b->d_counter, s);
           launch_pass_b_table(d, b->d_state, (int)sub.size(), l, s);
         });
